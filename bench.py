@@ -1,0 +1,162 @@
+"""Benchmark: RCP factor + solve on one MI355X.
+
+Workload (default): the dense symmetric indefinite n = 16384 matrix
+A = Q diag(s lam) Q^T (64 Householder reflectors, lam log-uniform in
+[1e-6, 1], random signs; cond ~ 1e6), block b = 128, oversampling p = 16,
+one right-hand side.  A step is one full factorization (rcp_factor) plus one
+solve (rcp_solve) with A and b already resident in HBM.  Throughput is
+(n^3/3) / time, in TFLOP/s.
+
+Prints one JSON line (rank 0, one GPU) with the roofline of the dominant
+matrix-core kernel (rcp_update) measured with HIP events inside the timed
+steps, and the CPU oracle timed on a bounded sample on the host.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_MFMA = 78.6     # TFLOP/s, MI355X dense FP64 matrix
+PEAK_HBM = 8000.0         # GB/s
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(cfg_name, n_sample):
+    """The oracle as it stands, factor + solve, on a smaller instance of the
+    same family (host cores)."""
+    from oracle import rcp as orcp
+    from workloads import CONFIGS
+    cfg = CONFIGS[cfg_name].scaled(n_sample)
+    A = cfg.matrix()
+    rhs = cfg.rhs()
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        threads = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    f = orcp.factor(A, cfg.b, cfg.p, seed=cfg.seed)
+    orcp.solve(f, rhs)
+    dt = time.perf_counter() - t0
+    return {"value": (n_sample ** 3 / 3.0) / dt / 1e12, "unit": "TFLOP/s",
+            "cores": int(threads), "kind": "oracle",
+            "sample": f"{cfg.kind} n={n_sample} b={cfg.b} p={cfg.p} nrhs={cfg.nrhs}, "
+                      f"one factor+solve in {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="householder16384")
+    ap.add_argument("--cpu-sample", type=int, default=4096,
+                    help="order of the oracle sample (0 skips it)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the factorization of one system runs on a single device)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1710_00125_amd as rcp
+    from workloads import CONFIGS
+
+    cfg = CONFIGS[args.config]
+    n = cfg.n
+    _log(f"bench: generating {cfg.name} (n={n}) on the host")
+    A_host = cfg.matrix()
+    rhs_host = cfg.rhs()
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(A_host).to(dev)
+    b = torch.from_numpy(rhs_host).to(dev)
+    del A_host
+    rcp.load()
+    rcp.rcp_set_profiling(True)
+
+    def step():
+        f = rcp.rcp_factor(A, cfg.b, cfg.p, cfg.seed)
+        st = rcp.rcp_get_stats()
+        x = rcp.rcp_solve(f, b)
+        st["ms_solve"] = rcp.rcp_get_stats()["ms_solve"]
+        return f, x, st
+
+    for w in range(args.warmup):
+        _log(f"bench: warmup {w + 1}/{args.warmup}")
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stats = []
+    e0.record()
+    for s in range(args.steps):
+        f, x, st = step()
+        stats.append(st)
+        _log(f"bench: step {s + 1}/{args.steps}: factor {st['ms_total']:.1f} ms, "
+             f"update {st['ms_update']:.1f} ms, panel {st['ms_panel']:.1f} ms, "
+             f"select {st['ms_select']:.1f} ms")
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    flops = n ** 3 / 3.0
+    value = flops / (ms * 1e-3) / 1e12
+
+    # correctness of the last step: backward error of the solve (eq. (5.1))
+    r = A @ x - b
+    anorm = A.abs().sum(dim=1).max()
+    berr = (r.abs().max(dim=0).values / (anorm * x.abs().max(dim=0).values)).max().item()
+    del r
+
+    upd_ms = sum(s["ms_update"] for s in stats) / len(stats)
+    upd_flops = stats[-1]["flops_update"]
+    upd_bytes = stats[-1]["bytes_update"]
+    launches = stats[-1]["launches_update"]
+    achieved = upd_flops / (upd_ms * 1e-3) / 1e12 if upd_ms > 0 else 0.0
+    breakdown = {k: round(sum(s[k] for s in stats) / len(stats), 3)
+                 for k in ("ms_total", "ms_omega", "ms_sketch", "ms_select", "ms_panel",
+                           "ms_sketch_update", "ms_commit", "ms_update", "ms_finalize",
+                           "ms_solve")}
+    out = {
+        "metric": "RCP factor+solve TFLOP/s at n=16384: FP64 vs FP32/BF16+IR at 1e-13 bwd error",
+        "value": round(value, 4),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": cfg.name, "n": n, "b": cfg.b, "p": cfg.p, "nrhs": cfg.nrhs,
+                   "cond": cfg.cond, "seed": cfg.seed, "precision": "fp64"},
+        "roofline": {"kernel": "rcp_update", "bound": "mfma", "achieved": round(achieved, 3),
+                     "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP64_MFMA, 4), "traffic": None,
+                     "launches": launches, "ms_total": round(upd_ms, 3),
+                     "algorithmic_flops": upd_flops, "algorithmic_bytes": upd_bytes,
+                     "achieved_GBps": round(upd_bytes / (upd_ms * 1e-3) / 1e9, 1)
+                     if upd_ms > 0 else 0.0},
+        "backward_error": berr,
+        "n2x2": stats[-1]["n2x2"],
+        "sbkp_cases": stats[-1]["ncase"],
+        "kernel_ms": breakdown,
+    }
+    if args.cpu_sample > 0:
+        _log(f"bench: timing the CPU oracle on n={args.cpu_sample}")
+        out["cpu_baseline"] = cpu_baseline(args.config, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

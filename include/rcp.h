@@ -1,0 +1,115 @@
+/*
+ * rcp.h -- C ABI of librcp, randomized complete pivoting (RCP) for the block
+ * LDL^T factorization of dense symmetric indefinite matrices on AMD MI355X
+ * (gfx950).
+ *
+ * Method: Feng, Xiao, Gu, "Randomized Complete Pivoting for Solving Symmetric
+ * Indefinite Linear Systems" (arXiv 1710.00125), Algorithm 1 with q = b:
+ * a Gaussian sketch B = Omega A picks b column pivots per block by partial
+ * QR with column pivoting, simplified Bunch-Kaufman pivoting (Figure 2)
+ * eliminates them with 1x1 and 2x2 pivots, the sketch is updated in O(l n)
+ * per block (eq. (3.3)), and the trailing Schur complement is updated once
+ * per block.
+ *
+ * Conventions shared by every entry point
+ *   - Every array pointer is a DEVICE pointer owned by the caller (for
+ *     instance the data pointer of a torch tensor on the GPU).  The library
+ *     never frees or keeps caller memory.
+ *   - Matrices are column-major with a leading dimension argument.
+ *   - Calls are enqueued on the stream set by rcp_set_stream (default: the
+ *     null stream) and return after one synchronisation of that stream, so
+ *     that the status can be reported.
+ *   - The library allocates its own device workspace (about 3 n^2 doubles
+ *     for an n x n factorization), keeps it for later calls on the same
+ *     device, and frees it in rcp_release().
+ *   - Status codes: 0 success; -i: argument i is invalid (nothing written);
+ *     +k (factor/solve): the factorization completed but the 1x1 pivot
+ *     D(k,k) (1-based) is exactly zero; RCP_E* below for other failures.
+ *   - Not thread-safe: calls from several host threads must be serialised
+ *     by the caller.
+ */
+#ifndef RCP_H
+#define RCP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RCP_ENONFINITE   (-1000) /* NaN or Inf met in the sketch or a pivot  */
+#define RCP_EDEVICE      (-1001) /* a HIP runtime call failed                */
+#define RCP_ENOMEM       (-1002) /* device workspace could not be allocated  */
+#define RCP_EUNSUPPORTED (-1003) /* size outside what this build supports    */
+
+/* Per-call statistics (filled by every rcp_factor / rcp_solve call). */
+typedef struct rcp_stats {
+  int64_t n;              /* order of the last factorization                  */
+  int64_t nblocks;        /* blocks processed                                 */
+  int64_t n2x2;           /* number of 2x2 pivots                             */
+  int64_t ncase[4];       /* SBKP cases (0)..(3) of Figure 2                  */
+  double  ms_total;       /* wall time of the call on the stream (events)     */
+  /* per-kernel-class GPU time in ms, filled only when profiling is on */
+  double  ms_omega, ms_sketch, ms_select, ms_panel, ms_sketch_update,
+          ms_commit, ms_update, ms_finalize, ms_solve;
+  int64_t launches_update; /* number of rcp_update launches                   */
+  double  flops_update;    /* algorithmic flops of all rcp_update launches     */
+  double  bytes_update;    /* algorithmic HBM bytes of all rcp_update launches */
+} rcp_stats;
+
+/* Set the HIP stream (a hipStream_t passed as void*) used by later calls.
+ * NULL selects the null stream.  Returns 0. */
+int rcp_set_stream(void* hip_stream);
+
+/* Bracket every kernel launch with HIP events and report per-kernel times
+ * in rcp_stats (on = 1) or not (on = 0, the default).  Returns 0. */
+int rcp_set_profiling(int32_t on);
+
+/* Copy the statistics of the last call into *st.  Returns 0, -1 if st is NULL. */
+int rcp_get_stats(rcp_stats* st);
+
+/* Free the cached device workspace.  Returns 0. */
+int rcp_release(void);
+
+/* The sketch matrix Omega (Section 3: i.i.d. N(0,1) entries) exactly as
+ * rcp_factor draws it for `seed`: Philox4x64-10, key (seed, 1), counter
+ * (q/4, 0, 0, 0) for flat index q = i*n + j, then Box-Muller on the four
+ * 64-bit words (u1 = ((w0>>11)+1)*2^-53, u2 = (w1>>11)*2^-53, z0 = rho cos,
+ * z1 = rho sin, rho = sqrt(-2 ln u1); likewise w2, w3 -> z2, z3).
+ * out: device, l x n row-major (out[i*n + j]).  Returns 0 or -2/-3/-4. */
+int rcp_omega(uint64_t seed, int32_t l, int64_t n, double* out);
+
+/* Block LDL^T with randomized complete pivoting: P A P^T = L D L^T
+ * (Algorithm 1, q = b).
+ *   n     order, n >= 0
+ *   A     n x n, lda >= max(1,n); only the lower triangle (i >= j) is read,
+ *         A is never written
+ *   b     block size >= 1 (QRCP pivots chosen per block)
+ *   p     oversampling >= 0; Omega has l = b + p rows (b + p <= 512)
+ *   seed  seed of Omega, see rcp_omega
+ *   perm  int64[n]: (P A P^T)(i,j) = A(perm[i], perm[j]); 0-based
+ *   L     n x n, ld = n: unit lower triangular with an explicit unit
+ *         diagonal, strict upper part zeroed, L(i+1,i) = 0 inside a 2x2 block
+ *   D     double[2n]: D[i] = d_ii; D[n+i] = d_{i+1,i} where ipiv[i] == 2,
+ *         otherwise 0
+ *   ipiv  int8[n]: 1 = 1x1 block, 2 = first index of a 2x2 block, 0 = second
+ * Returns 0, -i for a bad argument i, +k for an exactly zero 1x1 pivot at
+ * 1-based position k (first one; the factorization is still complete),
+ * RCP_ENONFINITE, RCP_EDEVICE, RCP_ENOMEM or RCP_EUNSUPPORTED. */
+int rcp_factor(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p,
+               uint64_t seed, int64_t* perm, double* L, double* D, int8_t* ipiv);
+
+/* Solve A X = B with the factors of rcp_factor (Table 1, solution phase):
+ * X = P^T L^{-T} D^{-1} L^{-1} P B, 2x2 blocks of D by Cramer's rule in FP64.
+ *   L, D, ipiv, perm  as written by rcp_factor for the same n
+ *   B     n x nrhs, ldb >= max(1,n), overwritten by X
+ * Returns 0, -i for a bad argument, +k if D has an exactly zero 1x1 pivot at
+ * 1-based position k (B is then left untouched), or RCP_EDEVICE. */
+int rcp_solve(int64_t n, const double* L, const double* D, const int8_t* ipiv,
+              const int64_t* perm, int64_t nrhs, double* B, int64_t ldb);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RCP_H */

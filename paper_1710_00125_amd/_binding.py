@@ -1,0 +1,178 @@
+"""ctypes marshalling for librcp.so (see include/rcp.h for the contract)."""
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+RCP_ENONFINITE = -1000
+RCP_EDEVICE = -1001
+RCP_ENOMEM = -1002
+RCP_EUNSUPPORTED = -1003
+
+
+class RCPError(RuntimeError):
+    def __init__(self, fn, code):
+        super().__init__(f"{fn} returned {code}")
+        self.code = code
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nblocks", ctypes.c_int64), ("n2x2", ctypes.c_int64),
+                ("ncase", ctypes.c_int64 * 4), ("ms_total", ctypes.c_double),
+                ("ms_omega", ctypes.c_double), ("ms_sketch", ctypes.c_double),
+                ("ms_select", ctypes.c_double), ("ms_panel", ctypes.c_double),
+                ("ms_sketch_update", ctypes.c_double), ("ms_commit", ctypes.c_double),
+                ("ms_update", ctypes.c_double), ("ms_finalize", ctypes.c_double),
+                ("ms_solve", ctypes.c_double), ("launches_update", ctypes.c_int64),
+                ("flops_update", ctypes.c_double), ("bytes_update", ctypes.c_double)]
+
+
+_SIGS = {
+    "rcp_set_stream": (ctypes.c_int, [ctypes.c_void_p]),
+    "rcp_set_profiling": (ctypes.c_int, [ctypes.c_int32]),
+    "rcp_get_stats": (ctypes.c_int, [ctypes.POINTER(_Stats)]),
+    "rcp_release": (ctypes.c_int, []),
+    "rcp_omega": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64,
+                                 ctypes.c_void_p]),
+    "rcp_factor": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p]),
+    "rcp_solve": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                 ctypes.c_void_p, ctypes.c_int64]),
+}
+
+
+def lib_path():
+    return os.path.join(_HERE, "librcp.so")
+
+
+def load():
+    """Load librcp.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        path = lib_path()
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with "
+                               "`python -m paper_1710_00125_amd.build`")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = lib
+    return _LIB
+
+
+def exported_symbols():
+    """Names of the C entry points the binding expects (all must resolve)."""
+    lib = load()
+    return {name: hasattr(lib, name) for name in _SIGS}
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("librcp needs a GPU: torch.cuda.is_available() is False")
+    return torch
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else ctypes.c_void_p(0)
+
+
+def _check(fn, code, ok_positive=False):
+    if code < 0 or (code > 0 and not ok_positive):
+        raise RCPError(fn, code)
+    return code
+
+
+def rcp_set_stream(stream=None):
+    """Hand a HIP stream (torch.cuda.Stream or raw handle) to the library."""
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    return load().rcp_set_stream(ctypes.c_void_p(handle))
+
+
+def rcp_set_profiling(on):
+    return load().rcp_set_profiling(1 if on else 0)
+
+
+def rcp_release():
+    return load().rcp_release()
+
+
+def rcp_get_stats():
+    st = _Stats()
+    load().rcp_get_stats(ctypes.byref(st))
+    out = {name: getattr(st, name) for name, _ in _Stats._fields_}
+    out["ncase"] = list(st.ncase)
+    return out
+
+
+def rcp_omega(seed, l, n, device="cuda"):
+    """Omega (l x n, row-major) as the factorization draws it for ``seed``."""
+    torch = _torch()
+    out = torch.empty((l, n), dtype=torch.float64, device=device)
+    rcp_set_stream()
+    _check("rcp_omega", load().rcp_omega(ctypes.c_uint64(seed & (2**64 - 1)), l, n, _ptr(out)))
+    return out
+
+
+@dataclass
+class Factors:
+    n: int
+    perm: object     # int64[n]
+    L: object        # n x n (logical view; storage is column-major)
+    D: object        # float64[2n]
+    ipiv: object     # int8[n]
+    info: int
+
+
+def rcp_factor(A, b, p, seed):
+    """P A P^T = L D L^T of the symmetric matrix whose lower triangle is A's.
+
+    A: (n, n) float64 tensor on the GPU (logical indexing A[i, j]).
+    Returns Factors; info > 0 flags an exactly zero 1x1 pivot.
+    """
+    torch = _torch()
+    n = A.shape[0]
+    assert A.dim() == 2 and A.shape[1] == n and A.dtype == torch.float64 and A.is_cuda
+    Acm = A.t().contiguous()                   # memory[i + j n] = A[i, j] (read only)
+    dev = A.device
+    perm = torch.empty(n, dtype=torch.int64, device=dev)
+    Lbuf = torch.empty((n, n), dtype=torch.float64, device=dev)
+    D = torch.empty(2 * n, dtype=torch.float64, device=dev)
+    ipiv = torch.empty(n, dtype=torch.int8, device=dev)
+    rcp_set_stream()
+    info = load().rcp_factor(n, _ptr(Acm), max(1, n), int(b), int(p),
+                             ctypes.c_uint64(int(seed) & (2**64 - 1)), _ptr(perm), _ptr(Lbuf),
+                             _ptr(D), _ptr(ipiv))
+    _check("rcp_factor", info, ok_positive=True)
+    return Factors(n, perm, Lbuf.t(), D, ipiv, info)
+
+
+def rcp_solve(f, B):
+    """X with A X = B from the factors of rcp_factor; B is (n,) or (n, nrhs)."""
+    torch = _torch()
+    vec = B.dim() == 1
+    Bm = B[:, None] if vec else B
+    n, nrhs = Bm.shape
+    # (nrhs, n) = column-major n x nrhs; always a fresh buffer so that the
+    # caller's B is never overwritten (B.t().contiguous() can alias B)
+    Bcm = torch.empty((nrhs, n), dtype=torch.float64, device=Bm.device)
+    Bcm.copy_(Bm.t())
+    Lcm = f.L.t()                              # the column-major storage itself
+    assert Lcm.is_contiguous()
+    rcp_set_stream()
+    code = load().rcp_solve(n, _ptr(Lcm), _ptr(f.D), _ptr(f.ipiv), _ptr(f.perm), nrhs,
+                            _ptr(Bcm), max(1, n))
+    _check("rcp_solve", code)
+    X = Bcm.t()
+    return X[:, 0] if vec else X

@@ -1,0 +1,222 @@
+// End-of-block operations of Algorithm 1 (q = b branch):
+//   * the sketch update  B(:, k:n) -= B~_1 L11^{-T} L21^T  (block form of
+//     eq. (3.3): the sketch of the new Schur complement is obtained from the
+//     old sketch in O(l n b) work instead of recomputing Omega A^{(k)});
+//   * the commit of the block: the block's interchanges applied to the
+//     permutation, the block's columns of L stored, and L21 and W21 = L21 D1
+//     packed in matrix-core fragment order for the trailing update.
+//
+// Inside a block every array is indexed by source (position at block start);
+// srcat[i] is the source that ends at block position i, so the first m
+// entries are the block's pivots in elimination order.
+#include "common.h"
+#include "kernels.h"
+#include "mfma.h"
+
+namespace rcp {
+namespace {
+
+// ---------------------------------------------------------------------------
+// T = B~_1 L11^{-T}: rows r of T solve T(r, :) L11^T = B~_1(r, :), i.e. a
+// forward substitution over t with the unit lower triangular L11.  A
+// workgroup takes 16 rows; 16 lanes share each row's dot products.
+// ---------------------------------------------------------------------------
+constexpr int kTrsmRows = 16;
+
+__global__ void __launch_bounds__(256) sketch_trsm_kernel(const double* __restrict__ B, int lpad,
+                                                         int l, const int* __restrict__ srcat,
+                                                         int m, const double* __restrict__ Lp,
+                                                         int ldp, double* __restrict__ T) {
+  extern __shared__ double smem[];
+  double* L11 = smem;                               // packed lower: row t at t(t-1)/2
+  double* Ts = L11 + (size_t)m * (m - 1) / 2 + 1;   // [16][m]
+  const int tid = threadIdx.x;
+  for (int t = 1; t < m; ++t) {
+    const double* src = Lp + (size_t)srcat[t] * ldp;
+    double* dst = L11 + (size_t)t * (t - 1) / 2;
+    for (int u = tid; u < t; u += 256) dst[u] = src[u];
+  }
+  const int rl = tid >> 4;           // row of this 16-lane group
+  const int j = tid & 15;
+  const int r = blockIdx.x * kTrsmRows + rl;
+  __syncthreads();
+  for (int t = 0; t < m; ++t) {
+    const double* Lt = L11 + (size_t)t * (t - 1) / 2;
+    double part = 0.0;
+    for (int u = j; u < t; u += 16) part = fma(Lt[u], Ts[rl * m + u], part);
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) part += __shfl_xor(part, off, 16);
+    if (j == 0) {
+      const double b1 = (r < l) ? B[(size_t)srcat[t] * lpad + r] : 0.0;
+      Ts[rl * m + t] = b1 - part;
+    }
+    __syncthreads();
+  }
+  if (r < lpad)
+    for (int t = j; t < m; t += 16) T[(size_t)t * lpad + r] = (r < l) ? Ts[rl * m + t] : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Bnext(:, i - m) = B(:, srcat[i]) - T L(srcat[i], 0:m)^T for i in [m, N).
+// Matrix-core product: A operand T (lpad x m), B operand L^T of 64 gathered
+// sources.  Wave w of a workgroup owns 16 output columns and all rows.
+// ---------------------------------------------------------------------------
+constexpr int kSuCols = 64;
+constexpr int kSuRowFrags = 12;   // rows per pass: 192
+
+__global__ void __launch_bounds__(256) sketch_update_kernel(
+    const double* __restrict__ B, int lpad, int l, const int* __restrict__ srcat, int m, int N,
+    const double* __restrict__ Lp, int ldp, const double* __restrict__ T,
+    double* __restrict__ Bnext) {
+  extern __shared__ double smem[];
+  const int mq = (m + 3) & ~3;
+  const int lds_ld = mq + 1;
+  double* Ls = smem;   // [64][mq+1]  L rows of my columns, zero padded in t
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int i0 = m + blockIdx.x * kSuCols;
+  for (int e = tid; e < kSuCols * mq; e += 256) {
+    const int cc = e / mq, t = e - cc * mq;
+    const int i = i0 + cc;
+    double v = 0.0;
+    if (i < N && t < m) v = Lp[(size_t)srcat[i] * ldp + t];
+    Ls[cc * lds_ld + t] = v;
+  }
+  __syncthreads();
+  const int nrf = lpad / 16;
+  for (int rf0 = 0; rf0 < nrf; rf0 += kSuRowFrags) {
+    rcp_d4 acc[kSuRowFrags];
+#pragma unroll
+    for (int f = 0; f < kSuRowFrags; ++f) acc[f] = rcp_d4{0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < mq / 4; ++q) {
+      const int t = 4 * q + frag_k(lane);
+      // A operand: L(column 16 w + l%16 of this workgroup, t)
+      const double av = Ls[(16 * w + frag_row(lane)) * lds_ld + t];
+#pragma unroll
+      for (int f = 0; f < kSuRowFrags; ++f) {
+        if (rf0 + f < nrf) {
+          // B operand: T(r, t) for r = 16 (rf0 + f) + l%16
+          const double bv = (t < m) ? T[(size_t)t * lpad + 16 * (rf0 + f) + frag_col(lane)] : 0.0;
+          acc[f] = mfma16x16x4(av, bv, acc[f]);
+        }
+      }
+    }
+    // acc[f]: lane l, element v = (column 16 w + l/16 + 4 v, row 16 (rf0 + f) + l%16)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ocol = 16 * w + acc_row(lane, v);
+      const int i = i0 + ocol;
+      if (i >= N) continue;
+      const int s = srcat[i];
+#pragma unroll
+      for (int f = 0; f < kSuRowFrags; ++f) {
+        if (rf0 + f < nrf) {
+          const int r = 16 * (rf0 + f) + acc_col(lane);
+          Bnext[(size_t)(i - m) * lpad + r] = (r < l) ? B[(size_t)s * lpad + r] - acc[f][v] : 0.0;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Commit of one block.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double w_of_row(const double* __restrict__ x, const double* __restrict__ Dg,
+                                           const int8_t* __restrict__ ipiv, int64_t n, int K0,
+                                           int t) {
+  const int64_t gt = K0 + t;
+  const int kd = ipiv[gt];
+  if (kd == 1) return x[t] * Dg[gt];
+  if (kd == 2) return fma(x[t], Dg[gt], x[t + 1] * Dg[n + gt]);
+  return fma(x[t - 1], Dg[n + gt - 1], x[t] * Dg[gt]);
+}
+
+__global__ void commit_pack_kernel(const int* __restrict__ srcat, int m, int N, int K0, int64_t n,
+                                   const double* __restrict__ Lp, int ldp,
+                                   const double* __restrict__ Dg, const int8_t* __restrict__ ipiv,
+                                   double* __restrict__ L21p, double* __restrict__ W21p, int Qk,
+                                   int rows_pad, int* __restrict__ rowsrc) {
+  // element e of the packed arrays: ((g * Qk + qk) * 64 + lane)
+  const int64_t total = (int64_t)rows_pad * Qk * 4;
+  const int N2 = N - m;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = (int)(e & 63);
+    const int64_t gq = e >> 6;
+    const int qk = (int)(gq % Qk);
+    const int g = (int)(gq / Qk);
+    const int row = 16 * g + (lane & 15);
+    const int t = 4 * qk + (lane >> 4);
+    double lv = 0.0, wv = 0.0;
+    if (row < N2 && t < m) {
+      const double* x = Lp + (size_t)srcat[m + row] * ldp;
+      lv = x[t];
+      wv = w_of_row(x, Dg, ipiv, n, K0, t);
+    }
+    L21p[e] = lv;
+    W21p[e] = wv;
+  }
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N2;
+       i += (int64_t)gridDim.x * blockDim.x)
+    rowsrc[i] = srcat[m + i];
+}
+
+__global__ void commit_rows_kernel(const int* __restrict__ srcat, int m, int N, int K0, int64_t n,
+                                   const double* __restrict__ Lp, int ldp,
+                                   const int64_t* __restrict__ Pcur, int64_t* __restrict__ Pnext,
+                                   double* __restrict__ Lwork) {
+  // one workgroup per block position i: the block's L entries of the source
+  // that ends at i go to row P(original index) of Lwork
+  for (int i = blockIdx.x; i < N; i += gridDim.x) {
+    const int s = srcat[i];
+    const int64_t orig = Pcur[K0 + s];
+    const double* x = Lp + (size_t)s * ldp;
+    double* dst = Lwork + orig * n + K0;
+    for (int t = threadIdx.x; t < m; t += blockDim.x) dst[t] = x[t];
+    if (threadIdx.x == 0) Pnext[K0 + i] = orig;
+  }
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < K0;
+       j += (int64_t)gridDim.x * blockDim.x)
+    Pnext[j] = Pcur[j];
+}
+
+}  // namespace
+
+void launch_sketch_trsm(const double* B, int lpad, int l, const int* srcat, int m,
+                        const double* Lpanel, int ldp, double* T, hipStream_t s) {
+  const size_t lds = ((size_t)m * (m - 1) / 2 + 1 + (size_t)kTrsmRows * m) * 8;
+  hipFuncSetAttribute((const void*)sketch_trsm_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)lds);
+  hipLaunchKernelGGL(sketch_trsm_kernel, dim3((lpad + kTrsmRows - 1) / kTrsmRows), dim3(256), lds,
+                     s, B, lpad, l, srcat, m, Lpanel, ldp, T);
+}
+
+void launch_sketch_update(const double* B, int lpad, int l, const int* srcat, int m, int N,
+                          const double* Lpanel, int ldp, const double* T, double* Bnext,
+                          hipStream_t s) {
+  const int N2 = N - m;
+  if (N2 <= 0) return;
+  const int mq = (m + 3) & ~3;
+  const size_t lds = (size_t)kSuCols * (mq + 1) * 8;
+  hipFuncSetAttribute((const void*)sketch_update_kernel,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(sketch_update_kernel, dim3((N2 + kSuCols - 1) / kSuCols), dim3(256), lds, s,
+                     B, lpad, l, srcat, m, N, Lpanel, ldp, T, Bnext);
+}
+
+void launch_commit(const int* srcat, int m, int N, int K0, int64_t n, const double* Lpanel,
+                   int ldp, const double* Dg, const int8_t* ipiv, const int64_t* Pcur,
+                   int64_t* Pnext, double* Lwork, double* L21p, double* W21p, int Qk,
+                   int rows_pad, int* rowsrc, hipStream_t s) {
+  if (N - m > 0) {
+    const int64_t total = (int64_t)rows_pad * Qk * 4;
+    const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(commit_pack_kernel, dim3(blocks), dim3(256), 0, s, srcat, m, N, K0, n,
+                       Lpanel, ldp, Dg, ipiv, L21p, W21p, Qk, rows_pad, rowsrc);
+  }
+  const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(N, 8192));
+  hipLaunchKernelGGL(commit_rows_kernel, dim3(blocks), dim3(128), 0, s, srcat, m, N, K0, n,
+                     Lpanel, ldp, Pcur, Pnext, Lwork);
+}
+
+}  // namespace rcp

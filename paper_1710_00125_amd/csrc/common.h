@@ -1,0 +1,160 @@
+// Device-side helpers shared by the RCP kernels (gfx950 / CDNA4).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define RCP_WAVE 64
+
+// alpha of the SBKP tests (Figure 2): the double nearest sqrt(2)/2
+#define RCP_ALPHA 0x1.6a09e667f3bcdp-1
+
+// ---------------------------------------------------------------------------
+// Cross-workgroup communication inside a persistent kernel.
+//
+// Workgroups on different XCDs sit behind different L2 caches.  Every value
+// one workgroup writes for another is therefore stored with an agent-scope
+// atomic store (written through to the device coherence point) and read with
+// an agent-scope atomic load; nothing relies on cache write-back or
+// invalidation, which on this chip cost microseconds per barrier.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void st_agent(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T ld_agent(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Stride (in 32-bit words) between the arrival flags of two workgroups: one
+// flag per 128-byte line.
+#define RCP_FLAG_STRIDE 32
+
+// Grid-wide barrier for persistent kernels whose workgroups are all resident
+// (launched cooperatively).  flags[g * RCP_FLAG_STRIDE] holds the number of
+// barriers workgroup g has reached; all flags are zeroed before the launch.
+// Each workgroup waits until its own communication stores have completed
+// (s_waitcnt), publishes its arrival, and polls every other workgroup's
+// flag with one thread per flag.  The waits are bounded: a barrier that
+// never completes (which a correct launch cannot produce) raises *abort_flag
+// instead of spinning forever, and then every later wait returns at once.
+__device__ __forceinline__ void grid_barrier(unsigned int* flags, unsigned int& epoch,
+                                             unsigned int nblocks, int* abort_flag) {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  epoch += 1;
+  if (threadIdx.x == 0) st_agent(&flags[blockIdx.x * RCP_FLAG_STRIDE], epoch);
+  for (unsigned int w = threadIdx.x; w < nblocks; w += blockDim.x) {
+    unsigned int spins = 0;
+    while (ld_agent(&flags[w * RCP_FLAG_STRIDE]) < epoch) {
+      if ((++spins & 1023u) == 0) {
+        if (ld_agent(abort_flag)) break;
+        if (spins > (1u << 22)) {
+          st_agent(abort_flag, 1);
+          break;
+        }
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  __syncthreads();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// ---------------------------------------------------------------------------
+// Argmax keys.  A candidate is (value, position); larger value wins, equal
+// values go to the smaller position (the paper's smallest-index rule).
+// value < 0 marks "no candidate".
+// ---------------------------------------------------------------------------
+struct ArgKey {
+  double val;
+  int pos;
+  int idx;   // payload: source index (or workgroup id)
+};
+
+__device__ __forceinline__ bool key_better(const ArgKey& a, const ArgKey& b) {
+  if (a.val != b.val) return a.val > b.val;
+  return a.pos < b.pos;
+}
+
+__device__ __forceinline__ ArgKey shfl_key(const ArgKey& k, int src_lane) {
+  ArgKey o;
+  o.val = __shfl(k.val, src_lane, RCP_WAVE);
+  o.pos = __shfl(k.pos, src_lane, RCP_WAVE);
+  o.idx = __shfl(k.idx, src_lane, RCP_WAVE);
+  return o;
+}
+
+// Workgroup-wide argmax; the result is returned to every thread.
+// `sh` must hold (blockDim.x / 64) ArgKeys.
+__device__ __forceinline__ ArgKey block_argmax(ArgKey k, ArgKey* sh) {
+  const int lane = threadIdx.x & (RCP_WAVE - 1);
+  const int wid = threadIdx.x / RCP_WAVE;
+#pragma unroll
+  for (int off = RCP_WAVE / 2; off > 0; off >>= 1) {
+    ArgKey o = shfl_key(k, lane ^ off);
+    if (key_better(o, k)) k = o;
+  }
+  if (lane == 0) sh[wid] = k;
+  __syncthreads();
+  ArgKey best = sh[0];
+  const int nw = blockDim.x / RCP_WAVE;
+  for (int w = 1; w < nw; ++w)
+    if (key_better(sh[w], best)) best = sh[w];
+  __syncthreads();
+  return best;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  const int lane = threadIdx.x & (RCP_WAVE - 1);
+  const int wid = threadIdx.x / RCP_WAVE;
+#pragma unroll
+  for (int off = RCP_WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, RCP_WAVE);
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  const int nw = blockDim.x / RCP_WAVE;
+  for (int w = 0; w < nw; ++w) s += sh[w];
+  __syncthreads();
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// The one definition of a Schur-column entry used by every kernel that forms
+// one:  a = A(s, c) - sum_{t < i} L(s, t) W(c, t).  The sum is split into
+// four contiguous chunks, each an fma chain in increasing t, combined as
+// (c0 + c1) + (c2 + c3).  Four lanes can evaluate the chunks in parallel
+// (dot_chunk + combine4) or one lane all of them (dot4): the bits agree.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int chunk_len(int i) { return (i + 3) >> 2; }
+
+template <typename T>
+__device__ __forceinline__ T dot_chunk(const T* __restrict__ x, const T* __restrict__ y,
+                                       int i, int q) {
+  const int cs = chunk_len(i);
+  const int t0 = q * cs;
+  const int t1 = min(i, t0 + cs);
+  T s = T(0);
+  for (int t = t0; t < t1; ++t) s = fma(x[t], y[t], s);
+  return s;
+}
+
+template <typename T>
+__device__ __forceinline__ T combine4(T c0, T c1, T c2, T c3) {
+  return (c0 + c1) + (c2 + c3);
+}
+
+template <typename T>
+__device__ __forceinline__ T dot4(const T* __restrict__ x, const T* __restrict__ y, int i) {
+  return combine4(dot_chunk(x, y, i, 0), dot_chunk(x, y, i, 1), dot_chunk(x, y, i, 2),
+                  dot_chunk(x, y, i, 3));
+}
+
+// Element (i, j) of the symmetric matrix whose lower triangle is stored
+// column-major in A with leading dimension ld.
+template <typename T>
+__device__ __forceinline__ T sym_at(const T* __restrict__ A, int64_t ld, int64_t i, int64_t j) {
+  return (i >= j) ? A[i + j * ld] : A[j + i * ld];
+}

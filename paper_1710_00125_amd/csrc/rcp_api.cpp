@@ -1,0 +1,427 @@
+// librcp host side: argument checks, device workspace, and the block loop of
+// Algorithm 1 (q = b) driving the HIP kernels on one stream.
+//
+// Per block: rcp_select (QRCP on the sketch) -> rcp_panel (SBKP
+// eliminations) -> [host reads the number m of eliminated columns] ->
+// sketch update -> commit (permutation, L rows, packed L21/W21) ->
+// rcp_update (trailing Schur complement with the block's interchanges
+// applied on the fly).  The working matrix, the sketch and the permutation
+// are double-buffered across blocks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "../../include/rcp.h"
+#include "kernels.h"
+
+using namespace rcp;
+
+namespace {
+
+hipStream_t g_stream = nullptr;
+bool g_prof = false;
+rcp_stats g_stats;
+
+struct Arena {
+  int device = -1;
+  size_t cap = 0;
+  char* base = nullptr;
+  size_t off = 0;
+  bool reserve(size_t bytes, int dev) {
+    if (base && cap >= bytes && device == dev) {
+      off = 0;
+      return true;
+    }
+    if (base) hipFree(base);
+    base = nullptr;
+    cap = 0;
+    if (hipMalloc((void**)&base, bytes) != hipSuccess) {
+      base = nullptr;
+      return false;
+    }
+    cap = bytes;
+    device = dev;
+    off = 0;
+    return true;
+  }
+  template <typename T>
+  T* take(size_t count) {
+    T* p = (T*)(base + off);
+    off += (count * sizeof(T) + 255) & ~(size_t)255;
+    return p;
+  }
+};
+
+Arena g_fact, g_solve;
+Ctrl* g_ctrl_host = nullptr;
+
+size_t al(size_t bytes) { return (bytes + 255) & ~(size_t)255; }
+
+// kernel classes for profiling
+enum KClass { KOmega, KSketch, KSelect, KPanel, KSketchUpd, KCommit, KUpdate, KFinal, KSolve, KNum };
+
+struct Prof {
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<int, std::pair<int, int>>> marks;  // class, (ev0, ev1)
+  size_t used = 0;
+  hipEvent_t get() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      hipEventCreate(&e);
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  void reset() {
+    used = 0;
+    marks.clear();
+  }
+};
+Prof g_profiler;
+
+struct Scope {
+  int cls;
+  int e0 = -1;
+  Scope(int c) : cls(c) {
+    if (g_prof) {
+      e0 = (int)g_profiler.used;
+      hipEventRecord(g_profiler.get(), g_stream);
+    }
+  }
+  ~Scope() {
+    if (g_prof) {
+      const int e1 = (int)g_profiler.used;
+      hipEventRecord(g_profiler.get(), g_stream);
+      g_profiler.marks.push_back({cls, {e0, e1}});
+    }
+  }
+};
+
+void collect_profile() {
+  double* dst[KNum] = {&g_stats.ms_omega, &g_stats.ms_sketch, &g_stats.ms_select,
+                       &g_stats.ms_panel, &g_stats.ms_sketch_update, &g_stats.ms_commit,
+                       &g_stats.ms_update, &g_stats.ms_finalize, &g_stats.ms_solve};
+  for (auto& m : g_profiler.marks) {
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, g_profiler.pool[m.second.first], g_profiler.pool[m.second.second]);
+    *dst[m.first] += ms;
+  }
+  g_profiler.reset();
+}
+
+int num_cus() {
+  int dev = 0, ncu = 0;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  return ncu > 0 ? ncu : 1;
+}
+
+#define RCP_CHECK(x)                      \
+  do {                                    \
+    if ((x) != hipSuccess) return RCP_EDEVICE; \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+int rcp_set_stream(void* hip_stream) {
+  g_stream = (hipStream_t)hip_stream;
+  return 0;
+}
+
+int rcp_set_profiling(int32_t on) {
+  g_prof = on != 0;
+  return 0;
+}
+
+int rcp_get_stats(rcp_stats* st) {
+  if (!st) return -1;
+  *st = g_stats;
+  return 0;
+}
+
+int rcp_release(void) {
+  if (g_fact.base) hipFree(g_fact.base);
+  if (g_solve.base) hipFree(g_solve.base);
+  g_fact = Arena();
+  g_solve = Arena();
+  return 0;
+}
+
+int rcp_omega(uint64_t seed, int32_t l, int64_t n, double* out) {
+  if (l < 0) return -2;
+  if (n < 0) return -3;
+  if (!out && (int64_t)l * n > 0) return -4;
+  launch_omega(seed, l, n, out, 0, l, g_stream);
+  if (hipGetLastError() != hipSuccess) return RCP_EDEVICE;
+  if (hipStreamSynchronize(g_stream) != hipSuccess) return RCP_EDEVICE;
+  return 0;
+}
+
+int rcp_factor(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, uint64_t seed,
+               int64_t* perm, double* L, double* D, int8_t* ipiv) {
+  if (n < 0) return -1;
+  if (!A && n > 0) return -2;
+  if (lda < std::max<int64_t>(1, n)) return -3;
+  if (b < 1 || b > kMaxB) return -4;
+  if (p < 0 || b + p > kMaxL) return -5;
+  if (n > 0 && !perm) return -7;
+  if (n > 0 && !L) return -8;
+  if (n > 0 && !D) return -9;
+  if (n > 0 && !ipiv) return -10;
+  memset(&g_stats, 0, sizeof(g_stats));
+  g_stats.n = n;
+  if (n == 0) return 0;
+  if (n > INT_MAX / 2) return RCP_EUNSUPPORTED;
+
+  const int l = b + p;
+  const int lpad = (l + 15) / 16 * 16;
+  const int ldp = (b + 2) | 1;
+  const int ncu = num_cus();
+  const int ksplit = 4;
+  const int Qmax = (b + 1 + 3) / 4;
+  const int64_t rows_pad_max = (n + 127) / 128 * 128;
+
+  // feasibility of the LDS-resident panels for the first (largest) block
+  {
+    const int Gs = select_grid((int)n, lpad, ncu);
+    const int Rs = (int)((n + Gs - 1) / Gs);
+    if ((size_t)l * (Rs | 1) * 8 + (size_t)lpad * 8 + 4096 > 150 * 1024) return RCP_EUNSUPPORTED;
+    size_t lds = 0;
+    panel_grid((int)n, ldp, ncu, &lds);
+    if (lds > 150 * 1024) return RCP_EUNSUPPORTED;
+  }
+  const int Gmax = ncu;
+  const int vec_stride = std::max(lpad, ldp);
+
+  const size_t nn = (size_t)n * n;
+  size_t bytes = 3 * al(nn * 8) + al((size_t)n * lpad * 8) * (2 + 1 + ksplit) +
+                 al((size_t)n * ldp * 8) + 2 * al((size_t)rows_pad_max * Qmax * 4 * 8) +
+                 al((size_t)lpad * (b + 2) * 8) + 2 * al((size_t)n * 8) + 3 * al((size_t)n * 4) +
+                 al((size_t)(b + 2) * 4) + al(sizeof(Ctrl)) + 3 * al((size_t)2 * Gmax * 8) +
+                 2 * al((size_t)2 * Gmax * 4) + al((size_t)2 * Gmax * vec_stride * 8) + al((size_t)Gmax * 128) +
+                 4096;
+  int dev = 0;
+  hipGetDevice(&dev);
+  if (!g_fact.reserve(bytes, dev)) return RCP_ENOMEM;
+  double* Acur = g_fact.take<double>(nn);
+  double* Anext = g_fact.take<double>(nn);
+  double* Lwork = g_fact.take<double>(nn);
+  double* OmT = g_fact.take<double>((size_t)n * lpad);
+  double* Bcur = g_fact.take<double>((size_t)n * lpad);
+  double* Bnext = g_fact.take<double>((size_t)n * lpad);
+  double* partial = g_fact.take<double>((size_t)n * lpad * ksplit);
+  double* Lpanel = g_fact.take<double>((size_t)n * ldp);
+  double* L21p = g_fact.take<double>((size_t)rows_pad_max * Qmax * 4);
+  double* W21p = g_fact.take<double>((size_t)rows_pad_max * Qmax * 4);
+  double* Tm = g_fact.take<double>((size_t)lpad * (b + 2));
+  int64_t* P0 = g_fact.take<int64_t>(n);
+  int64_t* P1 = g_fact.take<int64_t>(n);
+  int* posof = g_fact.take<int>(n);
+  int* srcat = g_fact.take<int>(n);
+  int* rowsrc = g_fact.take<int>(n);
+  int* win = g_fact.take<int>(b + 2);
+  Ctrl* ctrl = g_fact.take<Ctrl>(1);
+  Exchange ex;
+  ex.val = g_fact.take<double>(2 * Gmax);
+  ex.aux0 = g_fact.take<double>(2 * Gmax);
+  ex.aux1 = g_fact.take<double>(2 * Gmax);
+  ex.pos = g_fact.take<int>(2 * Gmax);
+  ex.src = g_fact.take<int>(2 * Gmax);
+  ex.vec = g_fact.take<double>((size_t)2 * Gmax * vec_stride);
+  ex.vec_stride = vec_stride;
+  ex.bar = g_fact.take<unsigned int>((size_t)Gmax * 32);
+  ex.abort_flag = &ctrl->abort_flag;
+
+  if (!g_ctrl_host) {
+    if (hipHostMalloc((void**)&g_ctrl_host, sizeof(Ctrl)) != hipSuccess) return RCP_EDEVICE;
+  }
+  hipStream_t s = g_stream;
+  hipEvent_t t0, t1;
+  hipEventCreate(&t0);
+  hipEventCreate(&t1);
+  hipEventRecord(t0, s);
+
+  memset(g_ctrl_host, 0, sizeof(Ctrl));
+  g_ctrl_host->info = INT_MAX;
+  RCP_CHECK(hipMemcpyAsync(ctrl, g_ctrl_host, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+  {
+    Scope sc(KOmega);
+    launch_omega(seed, l, n, OmT, 1, lpad, s);
+  }
+  {
+    Scope sc(KSketch);
+    launch_copy_lower(n, A, lda, Acur, s);
+    launch_sketch(n, Acur, n, OmT, lpad, Bcur, partial, ksplit, s);
+    launch_check_finite(n, Bcur, lpad, l, ctrl, s);
+    launch_iota64(n, P0, s);
+  }
+  RCP_CHECK(hipGetLastError());
+
+  int64_t* Pc = P0;
+  int64_t* Pn = P1;
+  double* Ac = Acur;
+  double* An = Anext;
+  double* Bc = Bcur;
+  double* Bn = Bnext;
+  int64_t K0 = 0;
+  int nblocks = 0;
+  int status = 0;
+  while (K0 < n) {
+    const int N = (int)(n - K0);
+    const int bb = std::min<int>(b, N);
+    {
+      Scope sc(KSelect);
+      const int Gs = select_grid(N, lpad, ncu);
+      hipMemsetAsync(ex.bar, 0, (size_t)Gmax * 128, s);
+      launch_select(Bc, lpad, l, N, bb, posof, win, ex, Gs, s);
+    }
+    {
+      Scope sc(KPanel);
+      size_t lds = 0;
+      const int Gp = panel_grid(N, ldp, ncu, &lds);
+      PanelArgs pa;
+      pa.A = Ac + K0 + K0 * n;
+      pa.ld = n;
+      pa.N = N;
+      pa.bb = bb;
+      pa.K0 = (int)K0;
+      pa.posof = posof;
+      pa.win = win;
+      pa.Lpanel = Lpanel;
+      pa.ldp = ldp;
+      pa.Dg = D;
+      pa.ipiv = ipiv;
+      pa.n = n;
+      pa.srcat = srcat;
+      pa.ctrl = ctrl;
+      hipMemsetAsync(ex.bar, 0, (size_t)Gmax * 128, s);
+      launch_panel(pa, ex, Gp, lds, s);
+    }
+    RCP_CHECK(hipGetLastError());
+    RCP_CHECK(hipMemcpyAsync(g_ctrl_host, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    RCP_CHECK(hipStreamSynchronize(s));
+    if (g_ctrl_host->abort_flag) {
+      status = RCP_EDEVICE;
+      break;
+    }
+    if (g_ctrl_host->nonfinite) {
+      status = RCP_ENONFINITE;
+      break;
+    }
+    const int m = g_ctrl_host->m;
+    if (m < 1 || m > bb + 1 || K0 + m > n) {
+      status = RCP_EDEVICE;
+      break;
+    }
+    const int64_t K1 = K0 + m;
+    const int N2 = N - m;
+    if (N2 > 0) {
+      Scope sc(KSketchUpd);
+      launch_sketch_trsm(Bc, lpad, l, srcat, m, Lpanel, ldp, Tm, s);
+      launch_sketch_update(Bc, lpad, l, srcat, m, N, Lpanel, ldp, Tm, Bn, s);
+    }
+    const int Qk = (m + 3) / 4;
+    const int rows_pad = (N2 + 127) / 128 * 128;
+    {
+      Scope sc(KCommit);
+      launch_commit(srcat, m, N, (int)K0, n, Lpanel, ldp, D, ipiv, Pc, Pn, Lwork, L21p, W21p, Qk,
+                    rows_pad, rowsrc, s);
+    }
+    if (N2 > 0) {
+      Scope sc(KUpdate);
+      launch_update(Ac + K0 + K0 * n, An + K1 + K1 * n, n, rowsrc, N2, L21p, W21p, Qk, s);
+      g_stats.launches_update += 1;
+      g_stats.flops_update += (double)N2 * (N2 + 1) * m;           // lower triangle, 2m per entry
+      g_stats.bytes_update += (double)N2 * (N2 + 1) / 2 * 16.0;    // read + write of each entry
+    }
+    RCP_CHECK(hipGetLastError());
+    std::swap(Pc, Pn);
+    std::swap(Ac, An);
+    std::swap(Bc, Bn);
+    K0 = K1;
+    ++nblocks;
+  }
+  if (status == 0) {
+    Scope sc(KFinal);
+    launch_finalize_L(n, Lwork, Pc, ipiv, L, s);
+    RCP_CHECK(hipMemcpyAsync(perm, Pc, n * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    RCP_CHECK(hipMemcpyAsync(g_ctrl_host, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+  }
+  hipEventRecord(t1, s);
+  RCP_CHECK(hipGetLastError());
+  RCP_CHECK(hipStreamSynchronize(s));
+  float ms = 0.f;
+  hipEventElapsedTime(&ms, t0, t1);
+  hipEventDestroy(t0);
+  hipEventDestroy(t1);
+  g_stats.ms_total = ms;
+  g_stats.nblocks = nblocks;
+  for (int i = 0; i < 4; ++i) g_stats.ncase[i] = g_ctrl_host->ncase[i];
+  g_stats.n2x2 = g_ctrl_host->ncase[3];
+  if (g_prof) collect_profile();
+  if (status != 0) return status;
+  if (g_ctrl_host->info != INT_MAX) return g_ctrl_host->info;
+  return 0;
+}
+
+int rcp_solve(int64_t n, const double* L, const double* D, const int8_t* ipiv,
+              const int64_t* perm, int64_t nrhs, double* B, int64_t ldb) {
+  if (n < 0) return -1;
+  if (n > 0 && !L) return -2;
+  if (n > 0 && !D) return -3;
+  if (n > 0 && !ipiv) return -4;
+  if (n > 0 && !perm) return -5;
+  if (nrhs < 0) return -6;
+  if (n > 0 && nrhs > 0 && !B) return -7;
+  if (ldb < std::max<int64_t>(1, n)) return -8;
+  if (n == 0 || nrhs == 0) return 0;
+  int dev = 0;
+  hipGetDevice(&dev);
+  const size_t words = solve_sync_words(n);
+  const size_t bytes = al((size_t)n * 8 * 8) + al(words * 4) + al(64);
+  if (!g_solve.reserve(bytes, dev)) return RCP_ENOMEM;
+  double* Y = g_solve.take<double>((size_t)n * 8);
+  unsigned int* sync = g_solve.take<unsigned int>(words);
+  int* zp = g_solve.take<int>(16);
+  hipStream_t s = g_stream;
+  if (!g_ctrl_host) {
+    if (hipHostMalloc((void**)&g_ctrl_host, sizeof(Ctrl)) != hipSuccess) return RCP_EDEVICE;
+  }
+  const int big = INT_MAX;
+  RCP_CHECK(hipMemcpyAsync(zp, &big, sizeof(int), hipMemcpyHostToDevice, s));
+  launch_find_zero_pivot(n, D, ipiv, zp, s);
+  int zhost = 0;
+  RCP_CHECK(hipMemcpyAsync(&zhost, zp, sizeof(int), hipMemcpyDeviceToHost, s));
+  RCP_CHECK(hipStreamSynchronize(s));
+  if (zhost != INT_MAX) return zhost;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (g_prof) {
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    hipEventRecord(e0, s);
+  }
+  launch_solve(n, L, D, ipiv, perm, nrhs, B, ldb, Y, sync, s);
+  if (g_prof) hipEventRecord(e1, s);
+  RCP_CHECK(hipGetLastError());
+  unsigned int abort_word = 0;
+  RCP_CHECK(hipMemcpyAsync(&abort_word, sync + (words - 1), sizeof(unsigned int),
+                           hipMemcpyDeviceToHost, s));
+  RCP_CHECK(hipStreamSynchronize(s));
+  if (abort_word) return RCP_EDEVICE;
+  if (g_prof) {
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    g_stats.ms_solve = ms;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+  }
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,174 @@
+// The sketch B = Omega A (Section 3; computed once by Algorithm 1) as an
+// FP64 matrix-core product, plus the small set-up kernels of a factorization.
+//
+// B is kept column-major with lpad (l rounded up to 16) rows so that column
+// j of B -- the sketch of column j of A -- is one contiguous run of lpad
+// doubles.  We compute B^T = sym(A) Omega^T: rows j of B^T are output rows,
+// the contraction runs over the n columns i of A.  A is stored lower, so a
+// 64 x 32 tile A(j0.., i0..) is read from column i (i <= j) or, transposed,
+// from column j (i > j), always along contiguous columns.  The contraction
+// is split over gridDim.y workgroups (split-K) to give the chip >> 256
+// workgroups; a second kernel adds the partial products in a fixed order.
+#include "common.h"
+#include "kernels.h"
+#include "mfma.h"
+
+namespace rcp {
+namespace {
+
+constexpr int kTJ = 64;    // output rows (j) per workgroup
+constexpr int kTK = 32;    // contraction chunk (i)
+constexpr int kTC = 160;   // output columns (r) per workgroup (10 fragments)
+
+__global__ void __launch_bounds__(256) sketch_partial_kernel(int64_t n, const double* __restrict__ A,
+                                                             int64_t ld,
+                                                             const double* __restrict__ OmT,
+                                                             int lpad, double* __restrict__ P,
+                                                             int64_t kchunk) {
+  __shared__ double As[kTJ][kTK + 1];
+  __shared__ double Bs[kTK][kTC + 2];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  const int64_t j0 = (int64_t)blockIdx.x * kTJ;
+  const int64_t kbeg = (int64_t)blockIdx.y * kchunk;
+  const int64_t kend = std::min<int64_t>(n, kbeg + kchunk);
+  const int c0 = blockIdx.z * kTC;
+  const int ncols = std::min(kTC, lpad - c0);
+  const int nf = ncols / 16;
+
+  rcp_d4 acc[kTC / 16];
+#pragma unroll
+  for (int f = 0; f < kTC / 16; ++f) acc[f] = rcp_d4{0.0, 0.0, 0.0, 0.0};
+
+  for (int64_t i0 = kbeg; i0 < kend; i0 += kTK) {
+    // ---- stage A tile (rows j0.., cols i0..) of the symmetric matrix
+    const bool all_lower = (i0 + kTK - 1) <= j0;
+    const bool all_upper = i0 > (j0 + kTJ - 1);
+    for (int e = tid; e < kTJ * kTK; e += 256) {
+      int jj, ii;
+      if (all_upper) {
+        ii = e % kTK;
+        jj = e / kTK;
+      } else {
+        jj = e % kTJ;
+        ii = e / kTJ;
+      }
+      const int64_t j = j0 + jj, i = i0 + ii;
+      double v = 0.0;
+      if (j < n && i < kend) v = (j >= i) ? A[j + i * ld] : A[i + j * ld];
+      As[jj][ii] = v;
+    }
+    (void)all_lower;
+    // ---- stage Omega^T rows i0.., columns c0..
+    for (int e = tid; e < kTK * ncols; e += 256) {
+      const int ii = e / ncols, cc = e - ii * ncols;
+      const int64_t i = i0 + ii;
+      Bs[ii][cc] = (i < kend) ? OmT[i * lpad + c0 + cc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kTK / 4; ++kk) {
+      const double a = As[16 * w + frag_row(lane)][4 * kk + frag_k(lane)];
+#pragma unroll
+      for (int f = 0; f < kTC / 16; ++f) {
+        if (f < nf) {
+          const double b = Bs[4 * kk + frag_k(lane)][16 * f + frag_col(lane)];
+          acc[f] = mfma16x16x4(a, b, acc[f]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double* Pz = P + (int64_t)blockIdx.y * n * lpad;
+#pragma unroll
+  for (int f = 0; f < kTC / 16; ++f) {
+    if (f < nf) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t j = j0 + 16 * w + acc_row(lane, v);
+        if (j < n) Pz[j * lpad + c0 + 16 * f + acc_col(lane)] = acc[f][v];
+      }
+    }
+  }
+}
+
+__global__ void sketch_reduce_kernel(int64_t total, int ksplit, int64_t stride,
+                                     const double* __restrict__ P, double* __restrict__ B) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double s = P[e];
+    for (int z = 1; z < ksplit; ++z) s += P[z * stride + e];
+    B[e] = s;
+  }
+}
+
+__global__ void copy_lower_kernel(int64_t n, const double* __restrict__ A, int64_t lda,
+                                  double* __restrict__ Acur) {
+  // one workgroup per column, rows j..n-1
+  for (int64_t j = blockIdx.x; j < n; j += gridDim.x) {
+    for (int64_t i = j + threadIdx.x; i < n; i += blockDim.x) Acur[i + j * n] = A[i + j * lda];
+  }
+}
+
+__global__ void check_finite_kernel(int64_t n, const double* __restrict__ B, int lpad, int l,
+                                    Ctrl* ctrl) {
+  int bad = 0;
+  const int64_t total = n * lpad;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e % lpad);
+    if (r < l && !isfinite(B[e])) bad = 1;
+  }
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(&ctrl->nonfinite, 1);
+}
+
+__global__ void iota64_kernel(int64_t n, int64_t* P) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    P[i] = i;
+}
+
+unsigned grid1d(int64_t total, int threads = 256, int64_t cap = 65536) {
+  int64_t b = (total + threads - 1) / threads;
+  if (b < 1) b = 1;
+  return (unsigned)std::min<int64_t>(b, cap);
+}
+
+}  // namespace
+
+void launch_copy_lower(int64_t n, const double* A, int64_t lda, double* Acur, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(copy_lower_kernel, dim3((unsigned)std::min<int64_t>(n, 65536)), dim3(256),
+                     0, s, n, A, lda, Acur);
+}
+
+void launch_sketch(int64_t n, const double* Acur, int64_t ld, const double* OmT, int lpad,
+                   double* B, double* partial, int ksplit, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t kchunk = (n + ksplit - 1) / ksplit;
+  kchunk = (kchunk + kTK - 1) / kTK * kTK;
+  const int ks = (int)((n + kchunk - 1) / kchunk);
+  dim3 grid((unsigned)((n + kTJ - 1) / kTJ), (unsigned)ks, (unsigned)((lpad + kTC - 1) / kTC));
+  hipLaunchKernelGGL(sketch_partial_kernel, grid, dim3(256), 0, s, n, Acur, ld, OmT, lpad,
+                     ks == 1 ? B : partial, kchunk);
+  if (ks > 1) {
+    const int64_t total = n * lpad;
+    hipLaunchKernelGGL(sketch_reduce_kernel, dim3(grid1d(total)), dim3(256), 0, s, total, ks,
+                       total, partial, B);
+  }
+}
+
+void launch_check_finite(int64_t n, const double* B, int lpad, int l, Ctrl* ctrl,
+                         hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(check_finite_kernel, dim3(grid1d(n * lpad, 256, 4096)), dim3(256), 0, s, n,
+                     B, lpad, l, ctrl);
+}
+
+void launch_iota64(int64_t n, int64_t* P, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(iota64_kernel, dim3(grid1d(n)), dim3(256), 0, s, n, P);
+}
+
+}  // namespace rcp

@@ -1,0 +1,264 @@
+// rcp_solve: X = P^T L^{-T} D^{-1} L^{-1} P B (Table 1, solution phase), and
+// the assembly of the final L of a factorization.
+//
+// The triangular solves are single launches over 64-row blocks.  Workgroups
+// take blocks in the order they obtain a ticket from an atomic counter, so a
+// workgroup only ever waits for blocks whose workgroups are already running;
+// each subtracts the contributions of finished blocks as their "done" flags
+// appear, solves its diagonal block in one wave, publishes its part of the
+// solution and raises its flag.  L is read once per solve direction, in
+// 64 x 64 tiles staged through LDS with coalesced column runs.
+#include <climits>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace rcp {
+namespace {
+
+constexpr int kBlk = 64;
+constexpr int kMaxRhs = 8;
+
+// ---------------------------------------------------------------------------
+// L(i, c) for the final order: row i of L is row P[i] (original index) of
+// Lwork, whose column c holds the multiplier of the pivot at position c.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) finalize_L_kernel(int64_t n, const double* __restrict__ Lwork,
+                                                        const int64_t* __restrict__ P,
+                                                        const int8_t* __restrict__ ipiv,
+                                                        double* __restrict__ L) {
+  __shared__ double tile[kBlk][kBlk + 1];
+  const int64_t nb = (n + kBlk - 1) / kBlk;
+  const int64_t I = blockIdx.x % nb, C = blockIdx.x / nb;   // row tile, column tile
+  const int64_t i0 = I * kBlk, c0 = C * kBlk;
+  const int tid = threadIdx.x;
+  if (I >= C) {
+    // read: thread -> (row ii, column run cc), contiguous along c in Lwork
+    for (int e = tid; e < kBlk * kBlk; e += 256) {
+      const int ii = e / kBlk, cc = e % kBlk;
+      const int64_t i = i0 + ii, c = c0 + cc;
+      double v = 0.0;
+      if (i < n && c < n && c < i) v = Lwork[P[i] * n + c];
+      tile[ii][cc] = v;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < kBlk * kBlk; e += 256) {
+    const int ii = e % kBlk, cc = e / kBlk;
+    const int64_t i = i0 + ii, c = c0 + cc;
+    if (i >= n || c >= n) continue;
+    double v;
+    if (c > i) v = 0.0;
+    else if (c == i) v = 1.0;
+    else if (i == c + 1 && ipiv[c] == 2) v = 0.0;
+    else v = tile[ii][cc];
+    L[i + c * n] = v;
+  }
+}
+
+__global__ void find_zero_pivot_kernel(int64_t n, const double* __restrict__ D,
+                                       const int8_t* __restrict__ ipiv, int* out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    if (ipiv[i] == 1 && D[i] == 0.0) atomicMin(out, (int)(i + 1));
+}
+
+__global__ void gather_rows_kernel(int64_t n, int nrhs, const int64_t* __restrict__ perm,
+                                   const double* __restrict__ B, int64_t ldb,
+                                   double* __restrict__ Y) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * nrhs;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = e / n, i = e - c * n;
+    Y[c * n + i] = B[perm[i] + c * ldb];
+  }
+}
+
+__global__ void scatter_rows_kernel(int64_t n, int nrhs, const int64_t* __restrict__ perm,
+                                    const double* __restrict__ Y, double* __restrict__ B,
+                                    int64_t ldb) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * nrhs;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = e / n, i = e - c * n;
+    B[perm[i] + c * ldb] = Y[c * n + i];
+  }
+}
+
+// D^{-1}: 1x1 blocks divide, 2x2 blocks by Cramer's rule
+__global__ void dsolve_kernel(int64_t n, int nrhs, const double* __restrict__ D,
+                              const int8_t* __restrict__ ipiv, double* __restrict__ Y) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * nrhs;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = e / n, i = e - c * n;
+    double* y = Y + c * n;
+    const int kd = ipiv[i];
+    if (kd == 1) {
+      y[i] = y[i] / D[i];
+    } else if (kd == 2 && i + 1 < n) {
+      const double e00 = D[i], e11 = D[i + 1], e10 = D[n + i];
+      const double det = fma(e00, e11, -(e10 * e10));
+      const double y0 = y[i], y1 = y[i + 1];
+      y[i] = fma(e11, y0, -(e10 * y1)) / det;
+      y[i + 1] = fma(e00, y1, -(e10 * y0)) / det;
+    }
+  }
+}
+
+__device__ __forceinline__ void wait_flag(const unsigned int* f, unsigned int* abort_word) {
+  if (threadIdx.x == 0) {
+    unsigned int spins = 0;
+    while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+      if (__hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+      if (++spins > (1u << 24)) {
+        __hip_atomic_store(abort_word, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+__device__ __forceinline__ void raise_flag(unsigned int* f) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(f, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Forward (lower = 1): L y = y.  Backward (lower = 0): L^T y = y.
+// sync[0] = ticket counter, sync[1 + k] = done flag of block k, sync[1 + nb]
+// = abort word (raised by a wait that timed out).
+__global__ void __launch_bounds__(256) trsv_chain_kernel(int64_t n, int nrhs,
+                                                        const double* __restrict__ L,
+                                                        double* __restrict__ Y,
+                                                        unsigned int* sync, int lower) {
+  __shared__ double Ls[kBlk][kBlk + 1];   // Ls[col][row] of the staged 64 x 64 tile
+  __shared__ double xs[kMaxRhs][kBlk];
+  __shared__ double part[4][kMaxRhs][kBlk];
+  __shared__ int sh_blk;
+  const int tid = threadIdx.x;
+  const int64_t nb = (n + kBlk - 1) / kBlk;
+  if (tid == 0) {
+    const unsigned int t = atomicAdd(&sync[0], 1u);
+    sh_blk = lower ? (int)t : (int)(nb - 1 - t);
+  }
+  __syncthreads();
+  const int64_t K = sh_blk;
+  const int64_t k0 = K * kBlk;
+  const int kn = (int)std::min<int64_t>(kBlk, n - k0);
+  const int ro = tid & 63;      // row (forward) or column (backward) within the block
+  const int grp = tid >> 6;     // 4 groups split the other index
+  double acc[kMaxRhs];
+#pragma unroll
+  for (int c = 0; c < kMaxRhs; ++c) acc[c] = 0.0;
+
+  const int64_t jfirst = lower ? 0 : K + 1, jlast = lower ? K - 1 : nb - 1;
+  for (int64_t jj = jfirst; jj <= jlast; ++jj) {
+    const int64_t J = lower ? jj : (nb - 1 - (jj - jfirst));
+    wait_flag(&sync[1 + J], &sync[1 + nb]);
+    const int64_t j0 = J * kBlk;
+    const int jn = (int)std::min<int64_t>(kBlk, n - j0);
+    // stage the off-diagonal tile: forward L(rows K, cols J), backward L(rows J, cols K)
+    const int64_t rbase = lower ? k0 : j0, cbase = lower ? j0 : k0;
+    const int rn = lower ? kn : jn, cn = lower ? jn : kn;
+    for (int e = tid; e < kBlk * kBlk; e += 256) {
+      const int rr = e & 63, cc = e >> 6;
+      Ls[cc][rr] = (rr < rn && cc < cn) ? L[(rbase + rr) + (cbase + cc) * n] : 0.0;
+    }
+    for (int e = tid; e < nrhs * kBlk; e += 256) {
+      const int c = e / kBlk, t = e % kBlk;
+      xs[c][t] = (t < jn) ? Y[c * n + j0 + t] : 0.0;
+    }
+    __syncthreads();
+    if (lower) {
+      // acc(row ro) += sum over columns t in my group of L(ro, t) x(t)
+      for (int t = grp; t < kBlk; t += 4) {
+        const double lv = Ls[t][ro];
+        for (int c = 0; c < nrhs; ++c) acc[c] = fma(lv, xs[c][t], acc[c]);
+      }
+    } else {
+      // acc(column ro) += sum over rows t in my group of L(t, ro) x(t)
+      for (int t = grp; t < kBlk; t += 4) {
+        const double lv = Ls[ro][t];
+        for (int c = 0; c < nrhs; ++c) acc[c] = fma(lv, xs[c][t], acc[c]);
+      }
+    }
+    __syncthreads();
+  }
+  for (int c = 0; c < nrhs; ++c) part[grp][c][ro] = acc[c];
+  // stage the diagonal tile
+  for (int e = tid; e < kBlk * kBlk; e += 256) {
+    const int rr = e & 63, cc = e >> 6;
+    Ls[cc][rr] = (rr < kn && cc < kn) ? L[(k0 + rr) + (k0 + cc) * n] : 0.0;
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const int rho = tid;
+    for (int c = 0; c < nrhs; ++c) {
+      double val = 0.0;
+      if (rho < kn)
+        val = Y[c * n + k0 + rho] - ((part[0][c][rho] + part[1][c][rho]) +
+                                     (part[2][c][rho] + part[3][c][rho]));
+      if (lower) {
+        for (int t = 0; t < kn; ++t) {
+          const double xt = __shfl(val, t, 64);
+          if (rho > t) val = fma(-Ls[t][rho], xt, val);
+        }
+      } else {
+        for (int t = kn - 1; t >= 0; --t) {
+          const double xt = __shfl(val, t, 64);
+          if (rho < t) val = fma(-Ls[rho][t], xt, val);
+        }
+      }
+      if (rho < kn) Y[c * n + k0 + rho] = val;
+    }
+  }
+  raise_flag(&sync[1 + K]);
+}
+
+unsigned grid1d(int64_t total) {
+  int64_t b = (total + 255) / 256;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 65536));
+}
+
+}  // namespace
+
+void launch_finalize_L(int64_t n, const double* Lwork, const int64_t* P, const int8_t* ipiv,
+                       double* L, hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t nb = (n + kBlk - 1) / kBlk;
+  hipLaunchKernelGGL(finalize_L_kernel, dim3((unsigned)(nb * nb)), dim3(256), 0, s, n, Lwork, P,
+                     ipiv, L);
+}
+
+void launch_find_zero_pivot(int64_t n, const double* D, const int8_t* ipiv, int* out,
+                            hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(find_zero_pivot_kernel, dim3(grid1d(n)), dim3(256), 0, s, n, D, ipiv, out);
+}
+
+size_t solve_sync_words(int64_t n) { return (size_t)(2 + (n + kBlk - 1) / kBlk); }
+
+void launch_solve(int64_t n, const double* L, const double* D, const int8_t* ipiv,
+                  const int64_t* perm, int64_t nrhs, double* B, int64_t ldb, double* Y,
+                  unsigned int* sync, hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return;
+  const int64_t nb = (n + kBlk - 1) / kBlk;
+  for (int64_t c0 = 0; c0 < nrhs; c0 += kMaxRhs) {
+    const int nr = (int)std::min<int64_t>(kMaxRhs, nrhs - c0);
+    double* Bc = B + c0 * ldb;
+    hipLaunchKernelGGL(gather_rows_kernel, dim3(grid1d(n * nr)), dim3(256), 0, s, n, nr, perm, Bc,
+                       ldb, Y);
+    hipMemsetAsync(sync, 0, solve_sync_words(n) * sizeof(unsigned int), s);
+    hipLaunchKernelGGL(trsv_chain_kernel, dim3((unsigned)nb), dim3(256), 0, s, n, nr, L, Y, sync,
+                       1);
+    hipLaunchKernelGGL(dsolve_kernel, dim3(grid1d(n * nr)), dim3(256), 0, s, n, nr, D, ipiv, Y);
+    hipMemsetAsync(sync, 0, solve_sync_words(n) * sizeof(unsigned int), s);
+    hipLaunchKernelGGL(trsv_chain_kernel, dim3((unsigned)nb), dim3(256), 0, s, n, nr, L, Y, sync,
+                       0);
+    hipLaunchKernelGGL(scatter_rows_kernel, dim3(grid1d(n * nr)), dim3(256), 0, s, n, nr, perm, Y,
+                       Bc, ldb);
+  }
+}
+
+}  // namespace rcp

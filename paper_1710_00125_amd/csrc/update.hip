@@ -1,0 +1,132 @@
+// rcp_update: the delayed Schur complement update of Algorithm 1,
+//     A22 <- A22 - L21 D1 L21^T = A22 - L21 W21^T,
+// on the lower triangle only (n^3/3 flops over the whole factorization,
+// Section 3.2), in FP64 on the matrix cores.
+//
+// The block's interchanges are applied on the fly: the kernel reads the
+// block-start matrix Acur at the source of each position (rowsrc) and writes
+// the updated trailing matrix, already in the new order, to Anext.  Reading
+// and writing different buffers also keeps the update free of in-place
+// hazards.  For positions the block did not move rowsrc is the identity and
+// the reads are plain coalesced column runs.
+//
+// Tiling: a workgroup owns a 128 x 128 tile (I, J), I >= J, of the lower
+// triangle; its four waves each own 64 x 64 (4 x 4 fragments of 16 x 16).
+// L21 and W21 arrive packed in fragment order, so each operand fragment is
+// one coalesced 512-byte load per wave, straight from L2 into registers,
+// double-buffered across the k loop.  Workgroups are numbered so that each
+// XCD (which receives every 8th workgroup) walks a contiguous stretch of the
+// tile order and reuses the same rows of L21 in its own L2.
+#include "common.h"
+#include "kernels.h"
+#include "mfma.h"
+
+namespace rcp {
+namespace {
+
+constexpr int kTile = 128;
+constexpr int kXcd = 8;
+
+__device__ __forceinline__ void tile_of(int64_t id, int& I, int& J) {
+  // id -> (I, J) with I >= J, row-major over the lower triangle of tiles
+  int64_t i = (int64_t)((sqrt(8.0 * (double)id + 1.0) - 1.0) * 0.5);
+  while ((i + 1) * (i + 2) / 2 <= id) ++i;
+  while (i * (i + 1) / 2 > id) --i;
+  I = (int)i;
+  J = (int)(id - i * (i + 1) / 2);
+}
+
+__global__ void __launch_bounds__(256, 2) update_kernel(const double* __restrict__ Acur,
+                                                        double* __restrict__ Anext, int64_t ld,
+                                                        const int* __restrict__ rowsrc, int N2,
+                                                        const double* __restrict__ L21p,
+                                                        const double* __restrict__ W21p, int Qk,
+                                                        int64_t ntiles) {
+  // XCD-aware numbering: hardware block b runs on XCD b % 8
+  const int64_t b = blockIdx.x;
+  const int64_t per = (ntiles + kXcd - 1) / kXcd;
+  const int64_t id = (b % kXcd) * per + b / kXcd;
+  if (id >= ntiles) return;
+  int I, J;
+  tile_of(id, I, J);
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int wy = w >> 1, wx = w & 1;
+  if (I == J && wx > wy) return;   // strictly upper quarter of a diagonal tile
+  const int r0 = I * kTile + wy * 64;   // first row of my 64 x 64
+  const int c0 = J * kTile + wx * 64;   // first column
+  if (r0 >= N2 || c0 >= N2) return;
+
+  const int g0 = r0 / 16, h0 = c0 / 16;
+  const double* pa = L21p + ((int64_t)g0 * Qk) * 64 + lane;
+  const double* pb = W21p + ((int64_t)h0 * Qk) * 64 + lane;
+  const int64_t gstride = (int64_t)Qk * 64;
+
+  rcp_d4 acc[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = rcp_d4{0.0, 0.0, 0.0, 0.0};
+
+  double a_cur[4], b_cur[4], a_nxt[4], b_nxt[4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    a_cur[x] = pa[x * gstride];
+    b_cur[x] = pb[x * gstride];
+  }
+  for (int q = 0; q < Qk; ++q) {
+    if (q + 1 < Qk) {
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        a_nxt[x] = pa[x * gstride + (q + 1) * 64];
+        b_nxt[x] = pb[x * gstride + (q + 1) * 64];
+      }
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[x][y] = mfma16x16x4(b_cur[y], a_cur[x], acc[x][y]);
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      a_cur[x] = a_nxt[x];
+      b_cur[x] = b_nxt[x];
+    }
+  }
+
+  // acc[x][y] holds the 16 x 16 block (j, i) = (W L^T)(c0 + 16y.., r0 + 16x..):
+  // lane l, element v is column j = c0 + 16y + l/16 + 4v, row i = r0 + 16x + l%16,
+  // so 16 consecutive lanes cover 16 consecutive rows of one column.
+  // C = Acur(rowsrc(i), rowsrc(j)) - acc, written to Anext(i, j)
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    const int i = r0 + 16 * x + acc_col(lane);
+    if (i >= N2) continue;
+    const int64_t si = rowsrc[i];
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = c0 + 16 * y + acc_row(lane, v);
+        if (j < N2) {
+          const int64_t sj = rowsrc[j];
+          const double a = (si >= sj) ? Acur[si + sj * ld] : Acur[sj + si * ld];
+          Anext[i + (int64_t)j * ld] = a - acc[x][y][v];
+        }
+      }
+    }
+  }
+}
+
+}  // namespace
+
+void launch_update(const double* Acur, double* Anext, int64_t ld, const int* rowsrc, int N2,
+                   const double* L21p, const double* W21p, int Qk, hipStream_t s) {
+  if (N2 <= 0) return;
+  const int64_t T = (N2 + kTile - 1) / kTile;
+  const int64_t ntiles = T * (T + 1) / 2;
+  const int64_t per = (ntiles + kXcd - 1) / kXcd;
+  hipLaunchKernelGGL(update_kernel, dim3((unsigned)(per * kXcd)), dim3(256), 0, s, Acur, Anext,
+                     ld, rowsrc, N2, L21p, W21p, Qk, ntiles);
+}
+
+}  // namespace rcp

@@ -1,0 +1,62 @@
+"""CPU checks of the C ABI library: it loads, and it exports every entry
+point that include/rcp.h declares (no compute calls without a GPU)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rcp.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\bint\s+(rcp_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("rcp_factor", "rcp_solve", "rcp_omega", "rcp_set_stream",
+                     "rcp_get_stats", "rcp_set_profiling", "rcp_release"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1710_00125_amd as pkg
+    path = pkg.lib_path()
+    if not os.path.exists(path):
+        pytest.skip("librcp.so not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert all(pkg.exported_symbols().values())
+
+
+def test_argument_errors_without_gpu():
+    # argument validation happens before any device call
+    import paper_1710_00125_amd as pkg
+    if not os.path.exists(pkg.lib_path()):
+        pytest.skip("librcp.so not built")
+    lib = pkg.load()
+    null = ctypes.c_void_p(0)
+    one = ctypes.c_void_p(8)   # never dereferenced: validation fails first
+    assert lib.rcp_factor(-1, null, 1, 4, 2, 0, null, null, null, null) == -1
+    assert lib.rcp_factor(4, null, 4, 4, 2, 0, one, one, one, one) == -2
+    assert lib.rcp_factor(4, one, 3, 4, 2, 0, one, one, one, one) == -3
+    assert lib.rcp_factor(4, one, 4, 0, 2, 0, one, one, one, one) == -4
+    assert lib.rcp_factor(4, one, 4, 4, -1, 0, one, one, one, one) == -5
+    assert lib.rcp_factor(4, one, 4, 4, 2, 0, null, one, one, one) == -7
+    assert lib.rcp_factor(4, one, 4, 4, 2, 0, one, null, one, one) == -8
+    assert lib.rcp_factor(4, one, 4, 4, 2, 0, one, one, null, one) == -9
+    assert lib.rcp_factor(4, one, 4, 4, 2, 0, one, one, one, null) == -10
+    assert lib.rcp_factor(0, null, 1, 4, 2, 0, null, null, null, null) == 0
+    assert lib.rcp_solve(-1, null, null, null, null, 1, null, 1) == -1
+    assert lib.rcp_solve(4, one, one, one, one, 1, one, 3) == -8
+    assert lib.rcp_solve(4, one, one, one, one, -1, one, 4) == -6
+    assert lib.rcp_solve(0, null, null, null, null, 1, null, 1) == 0
+    assert lib.rcp_omega(0, -1, 4, null) == -2
+    assert lib.rcp_omega(0, 2, -4, null) == -3
+    assert lib.rcp_omega(0, 2, 4, null) == -4

@@ -1,0 +1,125 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Every case prints its name before running so that a failing GPU step can be
+traced.  Tolerances:
+  * permutation and block pattern: bit-exact (integer results) whenever the
+    oracle's decision log has no near-tie (relative margin > 1e-9); the
+    cases below are checked to have none;
+  * L, D: |GPU - oracle| <= 1e3 * n * u * max(1, |oracle|) elementwise -- both
+    are FP64 and differ only by summation order, amplified at most by the
+    growth of the factorization (small for these inputs);
+  * reconstruction ||P A P^T - L D L^T||_inf / ||A||_inf <= 50 n u;
+  * solve backward error ||A x - b||_inf / (||A||_inf ||x||_inf) <= 1e-13.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import omega as oomega, rcp as orcp, textbook as tb
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+U = np.finfo(np.float64).eps / 2
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rcp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1710_00125_amd as pkg
+    pkg.load()
+    return pkg
+
+
+def _dev():
+    import torch
+    return torch.device("cuda:0")
+
+
+@pytest.mark.parametrize("seed,l,n", [(1, 40, 512), (3, 7, 13), (2**64 - 5, 144, 300), (0, 1, 1)])
+def test_omega_bit_identical(rcp, seed, l, n):
+    _say(f"omega seed={seed} l={l} n={n}")
+    got = rcp.rcp_omega(seed, l, n).cpu().numpy()
+    ref = oomega.omega(seed, l, n)
+    assert got.shape == ref.shape
+    assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))
+
+
+def _factor_case(rcp, A, b, p, seed, check_margin=True):
+    import torch
+    n = A.shape[0]
+    ref = orcp.factor(A, b, p, seed=seed)
+    if check_margin:
+        margin, _ = orcp.min_margin(ref, scale=np.max(np.abs(A)))
+        assert margin > 1e-9, f"near-tie in the oracle run (margin {margin})"
+    f = rcp.rcp_factor(torch.from_numpy(A).to(_dev()), b, p, seed)
+    torch.cuda.synchronize()
+    perm, ipiv = f.perm.cpu().numpy(), f.ipiv.cpu().numpy()
+    assert np.array_equal(perm, ref.perm)
+    assert np.array_equal(ipiv, ref.ipiv)
+    L, D = f.L.cpu().numpy(), f.D.cpu().numpy()
+    tol = 1e3 * n * U
+    assert np.all(np.abs(L - ref.L) <= tol * np.maximum(1.0, np.abs(ref.L)))
+    assert np.all(np.abs(D - ref.D) <= tol * np.maximum(1.0, np.abs(ref.D)))
+    assert tb.reconstruction_error(A, perm, L, _dmat(D, ipiv)) <= 50 * n * U
+    return f, ref
+
+
+def _dmat(D, ipiv):
+    n = len(ipiv)
+    Dm = np.diag(D[:n])
+    for i in range(n - 1):
+        if ipiv[i] == 2:
+            Dm[i + 1, i] = Dm[i, i + 1] = D[n + i]
+    return Dm
+
+
+@pytest.mark.parametrize("n,b,p,seed", [
+    (1, 4, 2, 1), (2, 4, 2, 2), (3, 2, 2, 3), (17, 4, 4, 6), (64, 8, 8, 8),
+    (96, 16, 8, 7), (200, 32, 8, 10), (333, 32, 8, 11), (512, 32, 8, 1),
+])
+def test_factor_gaussian_matches_oracle(rcp, n, b, p, seed):
+    _say(f"factor gaussian n={n} b={b} p={p} seed={seed}")
+    A = gen.gaussian_sym(n, seed)
+    _factor_case(rcp, A, b, p, seed)
+
+
+@pytest.mark.parametrize("n,b,p,seed", [(1000, 64, 10, 5), (1300, 128, 16, 6)])
+def test_factor_householder_matches_oracle(rcp, n, b, p, seed):
+    _say(f"factor householder n={n} b={b} p={p} seed={seed}")
+    A = gen.householder_spectrum(n, seed, cond=1e6, nrefl=64)
+    _factor_case(rcp, A, b, p, seed)
+
+
+@pytest.mark.parametrize("n,b,p,seed", [(128, 16, 4, 2), (400, 64, 10, 2), (1500, 64, 10, 3)])
+def test_factor_kkt_matches_oracle(rcp, n, b, p, seed):
+    _say(f"factor kkt n={n} b={b} p={p} seed={seed}")
+    A = gen.kkt(n, (3 * n) // 4, seed, nrefl=min(64, (3 * n) // 4))
+    _factor_case(rcp, A, b, p, seed)
+
+
+@pytest.mark.parametrize("nrhs", [1, 4])
+def test_solve_backward_error(rcp, nrhs):
+    import torch
+    n, b, p, seed = 300, 32, 8, 4
+    _say(f"solve n={n} nrhs={nrhs}")
+    A = gen.gaussian_sym(n, seed)
+    rhs = gen.rhs(n, nrhs, seed)
+    f = rcp.rcp_factor(torch.from_numpy(A).to(_dev()), b, p, seed)
+    rhs_dev = torch.from_numpy(rhs).to(_dev())
+    X = rcp.rcp_solve(f, rhs_dev).cpu().numpy()
+    # the right-hand side is not modified by the binding
+    assert np.array_equal(rhs_dev.cpu().numpy(), rhs)
+    ref = orcp.factor(A, b, p, seed=seed)
+    xr = orcp.solve(ref, rhs)
+    assert np.all(tb.backward_error(A, X, rhs) <= 1e-13)
+    assert np.max(np.abs(X - xr)) <= 1e-9 * max(1.0, np.max(np.abs(xr)))
