@@ -31,6 +31,25 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def measured_traffic():
+    """HBM bytes per rcp_update launch from the committed rocprofv3 counter
+    summary, if the kernel source is unchanged since it was measured."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "rcp_update_traffic_householder16384.md")
+    src = os.path.join(ROOT, "paper_1710_00125_amd", "csrc", "update.hip")
+    try:
+        text = open(path).read()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    if f"sha256 prefix at measurement time: {digest}" not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith("traffic_bytes_per_launch:"):
+            return float(line.split(":")[1])
+    return None
+
+
 def cpu_baseline(cfg_name, n_sample):
     """The oracle as it stands, factor + solve, on a smaller instance of the
     same family (host cores)."""
@@ -62,7 +81,21 @@ def main():
     ap.add_argument("--config", default="householder16384")
     ap.add_argument("--cpu-sample", type=int, default=4096,
                     help="order of the oracle sample (0 skips it)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (a known "
+                         "byte count for calibrating hardware traffic counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        nbytes = args.copy_calibration * 2**20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": nbytes, "bytes_written": nbytes,
+                          "launches": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the factorization of one system runs on a single device)", file=sys.stderr)
@@ -142,7 +175,8 @@ def main():
                    "cond": cfg.cond, "seed": cfg.seed, "precision": "fp64"},
         "roofline": {"kernel": "rcp_update", "bound": "mfma", "achieved": round(achieved, 3),
                      "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP64_MFMA, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_FP64_MFMA, 4),
+                     "traffic": measured_traffic() if args.config == "householder16384" else None,
                      "launches": launches, "ms_total": round(upd_ms, 3),
                      "algorithmic_flops": upd_flops, "algorithmic_bytes": upd_bytes,
                      "achieved_GBps": round(upd_bytes / (upd_ms * 1e-3) / 1e9, 1)

@@ -2,6 +2,7 @@
 //   * the sketch update  B(:, k:n) -= B~_1 L11^{-T} L21^T  (block form of
 //     eq. (3.3): the sketch of the new Schur complement is obtained from the
 //     old sketch in O(l n b) work instead of recomputing Omega A^{(k)});
+//     T = B~_1 L11^{-T} is built column by column by the panel kernel;
 //   * the commit of the block: the block's interchanges applied to the
 //     permutation, the block's columns of L stored, and L21 and W21 = L21 D1
 //     packed in matrix-core fragment order for the trailing update.
@@ -15,46 +16,6 @@
 
 namespace rcp {
 namespace {
-
-// ---------------------------------------------------------------------------
-// T = B~_1 L11^{-T}: rows r of T solve T(r, :) L11^T = B~_1(r, :), i.e. a
-// forward substitution over t with the unit lower triangular L11.  A
-// workgroup takes 16 rows; 16 lanes share each row's dot products.
-// ---------------------------------------------------------------------------
-constexpr int kTrsmRows = 16;
-
-__global__ void __launch_bounds__(256) sketch_trsm_kernel(const double* __restrict__ B, int lpad,
-                                                         int l, const int* __restrict__ srcat,
-                                                         int m, const double* __restrict__ Lp,
-                                                         int ldp, double* __restrict__ T) {
-  extern __shared__ double smem[];
-  double* L11 = smem;                               // packed lower: row t at t(t-1)/2
-  double* Ts = L11 + (size_t)m * (m - 1) / 2 + 1;   // [16][m]
-  const int tid = threadIdx.x;
-  for (int t = 1; t < m; ++t) {
-    const double* src = Lp + (size_t)srcat[t] * ldp;
-    double* dst = L11 + (size_t)t * (t - 1) / 2;
-    for (int u = tid; u < t; u += 256) dst[u] = src[u];
-  }
-  const int rl = tid >> 4;           // row of this 16-lane group
-  const int j = tid & 15;
-  const int r = blockIdx.x * kTrsmRows + rl;
-  __syncthreads();
-  for (int t = 0; t < m; ++t) {
-    const double* Lt = L11 + (size_t)t * (t - 1) / 2;
-    double part = 0.0;
-    for (int u = j; u < t; u += 16) part = fma(Lt[u], Ts[rl * m + u], part);
-#pragma unroll
-    for (int off = 8; off > 0; off >>= 1) part += __shfl_xor(part, off, 16);
-    if (j == 0) {
-      const double b1 = (r < l) ? B[(size_t)srcat[t] * lpad + r] : 0.0;
-      Ts[rl * m + t] = b1 - part;
-    }
-    __syncthreads();
-  }
-  if (r < lpad)
-    for (int t = j; t < m; t += 16) T[(size_t)t * lpad + r] = (r < l) ? Ts[rl * m + t] : 0.0;
-}
 
 // ---------------------------------------------------------------------------
 // Bnext(:, i - m) = B(:, srcat[i]) - T L(srcat[i], 0:m)^T for i in [m, N).
@@ -181,15 +142,6 @@ __global__ void commit_rows_kernel(const int* __restrict__ srcat, int m, int N, 
 }
 
 }  // namespace
-
-void launch_sketch_trsm(const double* B, int lpad, int l, const int* srcat, int m,
-                        const double* Lpanel, int ldp, double* T, hipStream_t s) {
-  const size_t lds = ((size_t)m * (m - 1) / 2 + 1 + (size_t)kTrsmRows * m) * 8;
-  hipFuncSetAttribute((const void*)sketch_trsm_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)lds);
-  hipLaunchKernelGGL(sketch_trsm_kernel, dim3((lpad + kTrsmRows - 1) / kTrsmRows), dim3(256), lds,
-                     s, B, lpad, l, srcat, m, Lpanel, ldp, T);
-}
 
 void launch_sketch_update(const double* B, int lpad, int l, const int* srcat, int m, int N,
                           const double* Lpanel, int ldp, const double* T, double* Bnext,

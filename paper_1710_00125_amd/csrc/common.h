@@ -35,17 +35,23 @@ __device__ __forceinline__ T ld_agent(const T* p) {
 // (launched cooperatively).  flags[g * RCP_FLAG_STRIDE] holds the number of
 // barriers workgroup g has reached; all flags are zeroed before the launch.
 // Each workgroup waits until its own communication stores have completed
-// (s_waitcnt), publishes its arrival, and polls every other workgroup's
-// flag with one thread per flag.  The waits are bounded: a barrier that
+// (s_waitcnt), publishes its arrival (grid_arrive), and polls every other
+// workgroup's flag with one thread per flag (grid_wait); work that needs no
+// other workgroup's data may run between the two.  The waits are bounded: a barrier that
 // never completes (which a correct launch cannot produce) raises *abort_flag
 // instead of spinning forever, and then every later wait returns at once.
-__device__ __forceinline__ void grid_barrier(unsigned int* flags, unsigned int& epoch,
-                                             unsigned int nblocks, int* abort_flag) {
+__device__ __forceinline__ void grid_arrive(unsigned int* flags, unsigned int& epoch) {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   epoch += 1;
   if (threadIdx.x == 0) st_agent(&flags[blockIdx.x * RCP_FLAG_STRIDE], epoch);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+__device__ __forceinline__ void grid_wait(unsigned int* flags, unsigned int epoch,
+                                          unsigned int nblocks, int* abort_flag) {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
   for (unsigned int w = threadIdx.x; w < nblocks; w += blockDim.x) {
     unsigned int spins = 0;
     while (ld_agent(&flags[w * RCP_FLAG_STRIDE]) < epoch) {
@@ -61,6 +67,12 @@ __device__ __forceinline__ void grid_barrier(unsigned int* flags, unsigned int& 
   }
   __syncthreads();
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+__device__ __forceinline__ void grid_barrier(unsigned int* flags, unsigned int& epoch,
+                                             unsigned int nblocks, int* abort_flag) {
+  grid_arrive(flags, epoch);
+  grid_wait(flags, epoch, nblocks, abort_flag);
 }
 
 // ---------------------------------------------------------------------------
@@ -123,33 +135,59 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 // ---------------------------------------------------------------------------
 // The one definition of a Schur-column entry used by every kernel that forms
-// one:  a = A(s, c) - sum_{t < i} L(s, t) W(c, t).  The sum is split into
-// four contiguous chunks, each an fma chain in increasing t, combined as
-// (c0 + c1) + (c2 + c3).  Four lanes can evaluate the chunks in parallel
-// (dot_chunk + combine4) or one lane all of them (dot4): the bits agree.
+// one:  a = A(s, c) - sum_{t < i} L(s, t) W(c, t).  The sum over t is split
+// into 16 contiguous chunks of ceil(i/16) terms, each an fma chain in
+// increasing t, and the 16 chunk sums are added by a balanced binary tree
+// ((c0 + c1) + (c2 + c3)) + ... .  Sixteen lanes (one chunk each, xor
+// shuffles 1, 2, 4, 8) or four lanes (four chunks each, then xor 1, 2) give
+// the same bits, because every level of the tree adds the same two values
+// (IEEE addition is commutative).  So a value that one workgroup forms for
+// its own row and another workgroup forms redundantly agree exactly.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int chunk_len(int i) { return (i + 3) >> 2; }
-
 template <typename T>
-__device__ __forceinline__ T dot_chunk(const T* __restrict__ x, const T* __restrict__ y,
-                                       int i, int q) {
-  const int cs = chunk_len(i);
-  const int t0 = q * cs;
+__device__ __forceinline__ T dot_chunk16(const T* __restrict__ x, const T* __restrict__ y,
+                                         int i, int j) {
+  const int cs = (i + 15) >> 4;
+  const int t0 = j * cs;
   const int t1 = min(i, t0 + cs);
   T s = T(0);
-  for (int t = t0; t < t1; ++t) s = fma(x[t], y[t], s);
+  // loads of 8 terms are issued before their fma chain (same order of adds)
+  for (int b = t0; b < t1; b += 8) {
+    T xs[8], ys[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      xs[u] = (b + u < t1) ? x[b + u] : T(0);
+      ys[u] = (b + u < t1) ? y[b + u] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (b + u < t1) s = fma(xs[u], ys[u], s);
+  }
   return s;
 }
 
+// four lanes of a quad (q = lane & 3): returns the full sum in all four
 template <typename T>
-__device__ __forceinline__ T combine4(T c0, T c1, T c2, T c3) {
-  return (c0 + c1) + (c2 + c3);
+__device__ __forceinline__ T dot16_quad(const T* __restrict__ x, const T* __restrict__ y, int i,
+                                        int q) {
+  const T a = dot_chunk16(x, y, i, 4 * q), b = dot_chunk16(x, y, i, 4 * q + 1);
+  const T c = dot_chunk16(x, y, i, 4 * q + 2), d = dot_chunk16(x, y, i, 4 * q + 3);
+  T v = (a + b) + (c + d);
+  v += __shfl_xor(v, 1, 4);
+  v += __shfl_xor(v, 2, 4);
+  return v;
 }
 
+// sixteen lanes (j = lane & 15): returns the full sum in all sixteen
 template <typename T>
-__device__ __forceinline__ T dot4(const T* __restrict__ x, const T* __restrict__ y, int i) {
-  return combine4(dot_chunk(x, y, i, 0), dot_chunk(x, y, i, 1), dot_chunk(x, y, i, 2),
-                  dot_chunk(x, y, i, 3));
+__device__ __forceinline__ T dot16_lanes(const T* __restrict__ x, const T* __restrict__ y, int i,
+                                         int j) {
+  T v = dot_chunk16(x, y, i, j);
+  v += __shfl_xor(v, 1, 16);
+  v += __shfl_xor(v, 2, 16);
+  v += __shfl_xor(v, 4, 16);
+  v += __shfl_xor(v, 8, 16);
+  return v;
 }
 
 // Element (i, j) of the symmetric matrix whose lower triangle is stored

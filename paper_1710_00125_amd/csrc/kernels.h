@@ -74,14 +74,15 @@ struct PanelArgs {
   int64_t n;
   int* srcat;         // out [N]: source at each block position
   Ctrl* ctrl;
+  const double* B;    // sketch of the block (lpad x N column-major)
+  int l, lpad;
+  double* T;          // out: T = B(:, piv) L11^{-T}, lpad x m column-major
 };
-int panel_grid(int N, int ldp, int num_cu, size_t* lds_bytes);
-void launch_panel(const PanelArgs& a, Exchange ex, int G, size_t lds_bytes, hipStream_t s);
+int panel_grid(int N, int ldp, int lpad, int num_cu, size_t* lds_bytes, int* ngr);
+void launch_panel(const PanelArgs& a, Exchange ex, int G, int ngr, size_t lds_bytes,
+                  hipStream_t s);
 
 // ---- blockops.hip
-// T (lpad x m, column-major) = B(:, piv) L11^{-T}; piv = srcat[0..m)
-void launch_sketch_trsm(const double* B, int lpad, int l, const int* srcat, int m,
-                        const double* Lpanel, int ldp, double* T, hipStream_t s);
 // Bnext(:, i - m) = B(:, srcat[i]) - T Lpanel(srcat[i], 0:m)^T, i in [m, N)
 void launch_sketch_update(const double* B, int lpad, int l, const int* srcat, int m, int N,
                           const double* Lpanel, int ldp, const double* T, double* Bnext,

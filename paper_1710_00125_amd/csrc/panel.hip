@@ -14,16 +14,27 @@
 //   (3) otherwise: interchange k+1 and r, 2x2 pivot [[a_kk, a_rk],[a_rk, a_rr]]
 //       with multipliers by Cramer's rule (proof of Theorem 3.2).
 //
+// The kernel also builds T = B~_1 L11^{-T}, the small triangular solve of the
+// block sketch update (eq. (3.3) in block form), one column per eliminated
+// pivot: T(:, t) = B(:, piv_t) - sum_{u<t} T(:, u) L11(t, u).
+//
 // One persistent launch of G workgroups, one grid barrier per step.
-// Workgroup g owns the sources [g R, g R + R) of the block (their L rows
-// stay in LDS) and tracks their positions; nothing is physically
-// interchanged.  In phase A every workgroup forms the current column on its
-// rows and publishes its best off-diagonal candidate together with that
-// candidate's diagonal a_rr and its W row.  After the barrier every
-// workgroup derives the same decision; column r is then formed from the
-// published W row without a second barrier, and the L row of the next pivot
-// is formed redundantly in every workgroup (with the same arithmetic as its
-// owner) so that the next step can start at once.
+// Workgroup g owns the sources [g R, g R + R) of the block: their L rows and
+// their diagonal entries of A stay in LDS, and it tracks their positions
+// (nothing is physically interchanged).  Per step:
+//   phase A  every workgroup forms the current column on its rows and
+//            publishes one record -- its best off-diagonal candidate (value,
+//            position, source, a_rk, a_rr) and that candidate's L row -- then
+//            arrives at the barrier;
+//   (gap)    between arriving and waiting, every workgroup prefetches the
+//            columns of the next window candidates, and the workgroups that
+//            own rows of T add the previous step's pivot columns to them;
+//   phase B  after the barrier every workgroup reads all records in one
+//            round trip, derives the same decision, forms column r from the
+//            winner's L row when SBKP needs it, stores its multipliers, and
+//            forms the L row of the next pivot redundantly.  The next pivot
+//            is always one of {c, win[k+1], win[k+2]}: their rows of L and
+//            their columns of A are prefetched during the step.
 #include <climits>
 
 #include "common.h"
@@ -39,6 +50,8 @@ struct PanelParams {
   PanelArgs a;
   Exchange ex;
   int G, R;
+  int ntr;        // rows of T owned per workgroup (rows G-1-g, G-1-g+G, ...)
+  int ldt;        // LDS row stride of T (>= bb + 2)
 };
 
 // multipliers of a 1x1 pivot d (zero column when d == 0: SBKP case (0))
@@ -61,65 +74,158 @@ __device__ __forceinline__ double w_entry(const double* x, const double* Dd, con
   return fma(x[t - 1], Ds[t - 1], x[t] * Dd[t]);
 }
 
+// one workgroup's candidate, as read back after the barrier
+struct Rec {
+  double val;   // |a(r)|, -1 if the workgroup had no candidate
+  int pos;      // position of r
+  int src;      // source of r
+  double ark;   // signed a(r)
+  double arr;   // current diagonal a_rr
+  int g;        // publishing workgroup
+};
+
+__device__ __forceinline__ bool rec_better(const Rec& a, const Rec& b) {
+  if (a.val != b.val) return a.val > b.val;
+  return a.pos < b.pos;
+}
+
+__device__ __forceinline__ Rec shfl_rec(const Rec& r, int lane) {
+  Rec o;
+  o.val = __shfl(r.val, lane, 64);
+  o.pos = __shfl(r.pos, lane, 64);
+  o.src = __shfl(r.src, lane, 64);
+  o.ark = __shfl(r.ark, lane, 64);
+  o.arr = __shfl(r.arr, lane, 64);
+  o.g = __shfl(r.g, lane, 64);
+  return o;
+}
+
+__device__ __forceinline__ Rec block_best_rec(Rec r, Rec* sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    Rec o = shfl_rec(r, lane ^ off);
+    if (rec_better(o, r)) r = o;
+  }
+  if (lane == 0) sh[wid] = r;
+  __syncthreads();
+  Rec best = sh[0];
+  for (int w = 1; w < kThreads / 64; ++w)
+    if (rec_better(sh[w], best)) best = sh[w];
+  __syncthreads();
+  return best;
+}
+
 __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
   const PanelArgs& a = P.a;
   extern __shared__ double smem[];
-  const int R = P.R;
-  const int ldp = a.ldp;
-  double* Lrow = smem;                      // [R][ldp]
-  double* vcol = Lrow + (size_t)R * ldp;    // [R]
-  double* Lp = vcol + R;                    // [ldp] L row of the pivot
-  double* Wp = Lp + ldp;                    // [ldp] W row of the pivot
-  double* Wr = Wp + ldp;                    // [ldp] W row of the candidate r
-  double* Wc = Wr + ldp;                    // [ldp] W row of my candidate
-  double* Dd = Wc + ldp;                    // [ldp] diagonal of the block's D
+  const int R = P.R, ldp = a.ldp, ldt = P.ldt, ntr = P.ntr;
+  double* Lrow = smem;                      // [R][ldp] L rows of my sources
+  double* vcol = Lrow + (size_t)R * ldp;    // [R] current column on my rows
+  double* acolv = vcol + R;                 // [3][R] A(s, .) for c, win[k+1], win[k+2]
+  double* Adiag = acolv + 3 * R;            // [R] A(s, s)
+  double* avec = Adiag + R;                 // [R] A(s, r)
+  double* Lp = avec + R;                    // [ldp] L row of the pivot
+  double* Wp = Lp + ldp;                    // [ldp] its W row
+  double* Wn = Wp + ldp;                    // [ldp] W row of the next pivot
+  double* Lr = Wn + ldp;                    // [ldp] L row of the winner r
+  double* Wr = Lr + ldp;                    // [ldp] its W row
+  double* Ln1 = Wr + ldp;                   // [ldp] L row of win[k+1]
+  double* Ln2 = Ln1 + ldp;                  // [ldp] L row of win[k+2]
+  double* Pd1 = Ln2 + ldp;                  // [ldp] pending T: L row of pivot 1
+  double* Pd2 = Pd1 + ldp;                  // [ldp] pending T: L row of pivot 2
+  double* Dd = Pd2 + ldp;                   // [ldp] diagonal of the block's D
   double* Ds = Dd + ldp;                    // [ldp] sub-diagonal of the block's D
-  int* kind = (int*)(Ds + ldp);             // [ldp]
+  double* Tl = Ds + ldp;                    // [ntr][ldt] my rows of T
+  int* kind = (int*)(Tl + (size_t)ntr * ldt);   // [ldp]
   int* posl = kind + ldp;                   // [R]
   int* win = posl + R;                      // [bb + 2]
+  __shared__ Rec shr[kThreads / 64];
   __shared__ ArgKey shk[kThreads / 64];
-  __shared__ double sh_akk;
-  __shared__ double sh_arr_mine;
+  __shared__ double sh_akk, sh_Acc, sh_A1c, sh_A2c, sh_A11, sh_A22, sh_Anr;
+  __shared__ double sh_vn, sh_vrn;
+  __shared__ int sh_pend_n, sh_pend_t, sh_pend_s1, sh_pend_s2;
 
   const int tid = threadIdx.x;
   const int g = blockIdx.x;
   const int s0 = g * R;
   const int nown = max(0, min(R, a.N - s0));
   const int bb = a.bb;
-  const int q = tid & 3;          // chunk of the dot product
+  const int q = tid & 3;          // quad lane: four chunks of the 16-chunk dot
   const int rho = tid >> 2;       // row within a pass
+  const int grp16 = tid >> 4;     // 16-lane group (T rows)
+  const int l16 = tid & 15;
   const double* A = a.A;
   const int64_t ld = a.ld;
+  const int lpad = a.lpad;
+  const int tr0 = P.G - 1 - g;    // my rows of T: tr0, tr0 + G, ... (< lpad)
   unsigned int epoch = 0;
   long long ncase[4] = {0, 0, 0, 0};
+  double bp1 = 0.0, bp2 = 0.0;    // prefetched B(r, pivot) for my first pass of T rows
 
-  for (int r = tid; r < nown; r += kThreads) posl[r] = a.posof[s0 + r];
+  // ---- prologue
+  for (int r = tid; r < nown; r += kThreads) {
+    posl[r] = a.posof[s0 + r];
+    Adiag[r] = A[(int64_t)(s0 + r) * (ld + 1)];
+  }
   for (int t = tid; t <= bb && t < a.N; t += kThreads) win[t] = a.win[t];
+  for (int e = tid; e < ntr * ldt; e += kThreads) Tl[e] = 0.0;
+  if (tid == 0) sh_pend_n = 0;
   __syncthreads();
+  int cur = 0;   // which of the three acolv slots holds the pivot column
+  {
+    const int c = win[0];
+    for (int r = tid; r < nown; r += kThreads)
+      acolv[r] = sym_at(A, ld, (int64_t)(s0 + r), (int64_t)c);
+    if (tid == 0) {
+      sh_Acc = A[(int64_t)c * (ld + 1)];
+      sh_akk = sh_Acc;
+    }
+  }
+  __syncthreads();
+
+  // add the pending pivot columns to my rows of T, 16 lanes per row:
+  //   T(r, t) = B(r, src) - sum_{u<t} T(r, u) L(src, u)
+  auto flush_T = [&]() {
+    const int pn = sh_pend_n;
+    if (pn == 0) return;
+    const int t0 = sh_pend_t;
+    for (int j0 = 0; j0 < ntr; j0 += kThreads / 16) {
+      const int j = j0 + grp16;
+      const int r = tr0 + j * P.G;
+      if (j < ntr && r < lpad) {
+        double* Tr = Tl + (size_t)j * ldt;
+        for (int jj = 0; jj < pn; ++jj) {
+          const double* Lq = jj == 0 ? Pd1 : Pd2;
+          double bv = jj == 0 ? bp1 : bp2;
+          if (j0 > 0 && r < a.l)
+            bv = a.B[(int64_t)(jj == 0 ? sh_pend_s1 : sh_pend_s2) * lpad + r];
+          const double dsum = dot16_lanes(Tr, Lq, t0, l16);
+          if (l16 == 0) Tr[t0 + jj] = (r < a.l ? bv : 0.0) - dsum;
+        }
+      }
+    }
+    __syncthreads();
+    if (tid == 0) sh_pend_n = 0;
+  };
 
   int k = 0;
   while (k < bb) {
     const int par = k & 1;
     const int c = win[k];
+    const int c1 = (k + 1 < bb) ? win[k + 1] : -1;
+    const int c2 = (k + 2 < bb) ? win[k + 2] : -1;
+    double* acol = acolv + cur * R;
+    double* acol1 = acolv + ((cur + 1) % 3) * R;
+    double* acol2 = acolv + ((cur + 2) % 3) * R;
     // ---- phase A: current column of c on my rows, my best candidate
-    if (tid == 0) sh_akk = sym_at(A, ld, (int64_t)c, (int64_t)c) - dot4(Lp, Wp, k);
     ArgKey best{-1.0, INT_MAX, -1};
     for (int rb = 0; rb < nown; rb += kRowsPerPass) {
       const int r = rb + rho;
       const bool live = r < nown && posl[r] > k;
-      double part = 0.0, arc = 0.0;
-      if (live) {
-        part = dot_chunk(Lrow + (size_t)r * ldp, Wp, k, q);
-        if (q == 0) arc = sym_at(A, ld, (int64_t)(s0 + r), (int64_t)c);
-      }
-      // quad lanes 4j..4j+3 of this wave hold the four chunks of one row
-      const int lb = (tid & 63) & ~3;
-      const double p0 = __shfl(part, lb + 0, 64);
-      const double p1 = __shfl(part, lb + 1, 64);
-      const double p2 = __shfl(part, lb + 2, 64);
-      const double p3 = __shfl(part, lb + 3, 64);
+      const double dsum = dot16_quad(Lrow + (size_t)(live ? r : 0) * ldp, Wp, live ? k : 0, q);
       if (live && q == 0) {
-        const double v = arc - combine4(p0, p1, p2, p3);
+        const double v = acol[r] - dsum;
         vcol[r] = v;
         ArgKey kk{fabs(v), posl[r], s0 + r};
         if (key_better(kk, best)) best = kk;
@@ -127,119 +233,180 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
     }
     best = block_argmax(best, shk);
     const bool have = best.idx >= 0;
-    if (have) {
-      const int rl = best.idx - s0;
+    const int rl = have ? best.idx - s0 : 0;
+    {
+      // publish the candidate's L row, and its current diagonal a_rr (formed
+      // only here) from its W row
       const double* xr = Lrow + (size_t)rl * ldp;
-      for (int t = tid; t < k; t += kThreads) Wc[t] = w_entry(xr, Dd, Ds, kind, t);
-    }
-    __syncthreads();
-    if (have) {
-      const int rl = best.idx - s0;
-      double* dst = P.ex.vec + ((size_t)par * P.G + g) * P.ex.vec_stride;
-      for (int t = tid; t < k; t += kThreads) st_agent(&dst[t], Wc[t]);
-      if (tid == 0)
-        sh_arr_mine = sym_at(A, ld, (int64_t)best.idx, (int64_t)best.idx) -
-                      dot4(Lrow + (size_t)rl * ldp, Wc, k);
-    }
-    __syncthreads();
-    if (tid == 0) {
-      st_agent(&P.ex.val[par * P.G + g], best.val);
-      st_agent(&P.ex.pos[par * P.G + g], best.pos);
-      st_agent(&P.ex.src[par * P.G + g], best.idx);
       if (have) {
-        st_agent(&P.ex.aux0[par * P.G + g], vcol[best.idx - s0]);
-        st_agent(&P.ex.aux1[par * P.G + g], (double)sh_arr_mine);
+        double* dst = P.ex.vec + ((size_t)par * P.G + g) * P.ex.vec_stride;
+        for (int t = tid; t < k; t += kThreads) {
+          st_agent(&dst[t], xr[t]);
+          Wr[t] = w_entry(xr, Dd, Ds, kind, t);
+        }
+      }
+      __syncthreads();
+      if (tid < 16) {
+        const double dsum = dot16_lanes(xr, Wr, have ? k : 0, tid);
+        if (tid == 0) {
+          st_agent(&P.ex.val[par * P.G + g], best.val);
+          st_agent(&P.ex.pos[par * P.G + g], best.pos);
+          st_agent(&P.ex.src[par * P.G + g], best.idx);
+          st_agent(&P.ex.aux0[par * P.G + g], have ? vcol[rl] : 0.0);
+          st_agent(&P.ex.aux1[par * P.G + g], have ? Adiag[rl] - dsum : 0.0);
+        }
       }
     }
-    grid_barrier(P.ex.bar, epoch, P.G, P.ex.abort_flag);
+    grid_arrive(P.ex.bar, epoch);
+    // ---- gap: prefetch the columns of the two window candidates for the
+    // next step, and extend T by the previous step's pivots
+    for (int r = tid; r < nown; r += kThreads) {
+      if (c1 >= 0) acol1[r] = sym_at(A, ld, (int64_t)(s0 + r), (int64_t)c1);
+      if (c2 >= 0) acol2[r] = sym_at(A, ld, (int64_t)(s0 + r), (int64_t)c2);
+    }
+    if (tid == 64 && c1 >= 0) {
+      sh_A1c = sym_at(A, ld, (int64_t)c1, (int64_t)c);
+      sh_A11 = A[(int64_t)c1 * (ld + 1)];
+    }
+    if (tid == 128 && c2 >= 0) {
+      sh_A2c = sym_at(A, ld, (int64_t)c2, (int64_t)c);
+      sh_A22 = A[(int64_t)c2 * (ld + 1)];
+    }
+    flush_T();
+    grid_wait(P.ex.bar, epoch, P.G, P.ex.abort_flag);
 
-    // ---- phase B: the decision (identical in all workgroups)
-    ArgKey cand{-1.0, INT_MAX, -1};
+    // ---- phase B: every record in one round trip, the same decision everywhere
+    Rec rc{-1.0, INT_MAX, -1, 0.0, 0.0, -1};
     for (int w = tid; w < P.G; w += kThreads) {
-      ArgKey kk{ld_agent(&P.ex.val[par * P.G + w]), ld_agent(&P.ex.pos[par * P.G + w]), w};
-      if (key_better(kk, cand)) cand = kk;
+      Rec o;
+      o.val = ld_agent(&P.ex.val[par * P.G + w]);
+      o.pos = ld_agent(&P.ex.pos[par * P.G + w]);
+      o.src = ld_agent(&P.ex.src[par * P.G + w]);
+      o.ark = ld_agent(&P.ex.aux0[par * P.G + w]);
+      o.arr = ld_agent(&P.ex.aux1[par * P.G + w]);
+      o.g = w;
+      if (rec_better(o, rc)) rc = o;
     }
-    cand = block_argmax(cand, shk);
+    // L rows of the two window candidates for the next pivot (entries < k
+    // were stored by their owners before this step's barrier)
+    for (int t = tid; t < k; t += kThreads) {
+      if (c1 >= 0) Ln1[t] = ld_agent(&a.Lpanel[(size_t)c1 * ldp + t]);
+      if (c2 >= 0) Ln2[t] = ld_agent(&a.Lpanel[(size_t)c2 * ldp + t]);
+    }
+    rc = block_best_rec(rc, shr);
     const double akk = sh_akk;
-    double lam = 0.0, ark = 0.0, arr = 0.0;
-    int rpos = -1, rsrc = -1;
-    if (cand.val >= 0.0) {
-      lam = cand.val;
-      rpos = cand.pos;
-      rsrc = ld_agent(&P.ex.src[par * P.G + cand.idx]);
-      ark = ld_agent(&P.ex.aux0[par * P.G + cand.idx]);
-      arr = ld_agent(&P.ex.aux1[par * P.G + cand.idx]);
-    }
+    const double lam = rc.val >= 0.0 ? rc.val : 0.0;
+    const int rpos = rc.pos, rsrc = rc.src;
+    const double ark = rc.ark, arr = rc.arr;
     int kase;
     if (lam == 0.0) kase = 0;
     else if (fabs(akk) >= RCP_ALPHA * lam) kase = 1;
     else if (fabs(arr) >= RCP_ALPHA * lam) kase = 2;
     else kase = 3;
     const int sstep = (kase == 3) ? 2 : 1;
-    if (kase >= 2) {
-      const double* xv = P.ex.vec + ((size_t)par * P.G + cand.idx) * P.ex.vec_stride;
-      for (int t = tid; t < k; t += kThreads) Wr[t] = ld_agent(&xv[t]);
+    // next pivot source after this step's interchange
+    int cn;
+    if (kase == 2) cn = (rpos == k + 1) ? c : c1;
+    else if (kase == 3) cn = (rpos == k + 2) ? c1 : c2;
+    else cn = c1;
+    if (k + sstep >= bb) cn = -1;
+    const int piv1 = (kase == 2) ? rsrc : c;   // pivot source(s) of this step
+    const int piv2 = rsrc;
+    // interchange of case (2) k <-> r or case (3) k+1 <-> r (read the window
+    // before any thread can modify it below)
+    const int p1 = (kase == 2) ? k : k + 1;
+    const int sp1 = (kase >= 2) ? win[p1] : -1;
+    // prefetch B(r, pivot) for my first pass of T rows (used in the next gap)
+    {
+      const int r = tr0 + grp16 * P.G;
+      if (l16 == 0 && grp16 < ntr && r < a.l) {
+        bp1 = a.B[(int64_t)piv1 * lpad + r];
+        if (kase == 3) bp2 = a.B[(int64_t)piv2 * lpad + r];
+      }
     }
-    // interchange: case (2) k <-> r, case (3) k+1 <-> r
     if (kase >= 2) {
-      const int p1 = (kase == 2) ? k : k + 1;
-      const int sp1 = win[p1];
-      if (rpos != p1) {
-        for (int r = tid; r < nown; r += kThreads) {
-          if (s0 + r == rsrc) posl[r] = p1;
-          else if (s0 + r == sp1) posl[r] = rpos;
+      // second round trip: the winner's L row, A(s, r) on my rows, A(cn, r)
+      const double* xv = P.ex.vec + ((size_t)par * P.G + rc.g) * P.ex.vec_stride;
+      for (int t = tid; t < k; t += kThreads) Lr[t] = ld_agent(&xv[t]);
+      for (int r = tid; r < nown; r += kThreads)
+        avec[r] = sym_at(A, ld, (int64_t)(s0 + r), (int64_t)rsrc);
+      if (tid == 0 && cn >= 0) sh_Anr = sym_at(A, ld, (int64_t)cn, (int64_t)rsrc);
+      __syncthreads();
+      for (int t = tid; t < k; t += kThreads) Wr[t] = w_entry(Lr, Dd, Ds, kind, t);
+      __syncthreads();
+    }
+    const double det = (kase == 3) ? fma(akk, arr, -(ark * ark)) : 0.0;
+    const double dpiv = (kase == 2) ? arr : akk;
+    // ---- multipliers for my remaining rows (a quad per row); the window is
+    // only rewritten (by thread 0, below) in case (2)/(3), after the
+    // barriers of the second round trip that follow every thread's read of it
+    for (int rb = 0; rb < nown; rb += kRowsPerPass) {
+      const int r = rb + rho;
+      int pr = (r < nown) ? posl[r] : -1;
+      if (kase >= 2 && rpos != p1 && r < nown) {
+        if (s0 + r == rsrc) pr = p1;
+        else if (s0 + r == sp1) pr = rpos;
+      }
+      const bool live = r < nown && pr >= k + sstep;
+      double vr = 0.0;
+      if (kase >= 2) {
+        const double dsum = dot16_quad(Lrow + (size_t)(live ? r : 0) * ldp, Wr, live ? k : 0, q);
+        if (live) vr = avec[r] - dsum;
+      }
+      if (r < nown && q == 0) {
+        posl[r] = pr;
+        if (live) {
+          double* Lrr = Lrow + (size_t)r * ldp;
+          double* Lg = a.Lpanel + (size_t)(s0 + r) * ldp;
+          if (kase == 3) {
+            double l1, l2;
+            mult_2x2(vcol[r], vr, akk, ark, arr, det, l1, l2);
+            Lrr[k] = l1;
+            Lrr[k + 1] = l2;
+            st_agent(&Lg[k], l1);
+            st_agent(&Lg[k + 1], l2);
+          } else {
+            const double l1 = mult_1x1(kase == 2 ? vr : vcol[r], dpiv);
+            Lrr[k] = l1;
+            st_agent(&Lg[k], l1);
+          }
+        } else if (kase == 3 && s0 + r == rsrc) {
+          // inside a 2x2 block L(k+1, k) = 0
+          Lrow[(size_t)r * ldp + k] = 0.0;
+          st_agent(&a.Lpanel[(size_t)rsrc * ldp + k], 0.0);
         }
       }
-      __syncthreads();
-      if (tid == 0 && rpos != p1) {
+    }
+    // pivot rows of L for the pending columns of T; next pivot's old row and
+    // its W entries (columns < k) -- the D entries they use are unchanged
+    const double* Lsrc = (cn == c) ? Lp : (cn == c1 ? Ln1 : Ln2);
+    for (int t = tid; t < k; t += kThreads) {
+      Pd1[t] = (kase == 2) ? Lr[t] : Lp[t];
+      if (kase == 3) Pd2[t] = Lr[t];
+      if (cn >= 0) {
+        Wn[t] = w_entry(Lsrc, Dd, Ds, kind, t);
+        if (Lsrc != Lp) Lp[t] = Lsrc[t];
+      }
+    }
+    if (cn >= 0 && (tid >> 6) == 1 && (tid & 63) < 16) {
+      // the next pivot's entry in column c at this step
+      const double dsum = dot16_lanes(Lsrc, Wp, k, l16);
+      if (l16 == 0) sh_vn = ((cn == c) ? sh_Acc : (cn == c1 ? sh_A1c : sh_A2c)) - dsum;
+    }
+    if (cn >= 0 && kase >= 2 && (tid >> 6) == 2 && (tid & 63) < 16) {
+      // ... and in column r
+      const double dsum = dot16_lanes(Lsrc, Wr, k, l16);
+      if (l16 == 0) sh_vrn = sh_Anr - dsum;
+    }
+    if (tid == 0) {
+      if (kase >= 2 && rpos != p1) {
         win[p1] = rsrc;
         if (rpos <= bb) win[rpos] = sp1;
       }
-    }
-    __syncthreads();
-    const double det = (kase == 3) ? fma(akk, arr, -(ark * ark)) : 0.0;
-    const double dpiv = (kase == 2) ? arr : akk;
-    // ---- multipliers for my remaining rows
-    for (int rb = 0; rb < nown; rb += kRowsPerPass) {
-      const int r = rb + rho;
-      const bool live = r < nown && posl[r] >= k + sstep;
-      double vr = 0.0;
-      if (kase >= 2) {
-        double part = 0.0, arc = 0.0;
-        if (live) {
-          part = dot_chunk(Lrow + (size_t)r * ldp, Wr, k, q);
-          if (q == 0) arc = sym_at(A, ld, (int64_t)(s0 + r), (int64_t)rsrc);
-        }
-        const int lb = (tid & 63) & ~3;
-        const double p0 = __shfl(part, lb + 0, 64);
-        const double p1 = __shfl(part, lb + 1, 64);
-        const double p2 = __shfl(part, lb + 2, 64);
-        const double p3 = __shfl(part, lb + 3, 64);
-        vr = arc - combine4(p0, p1, p2, p3);
-      }
-      if (live && q == 0) {
-        double* Lr = Lrow + (size_t)r * ldp;
-        double* Lg = a.Lpanel + (size_t)(s0 + r) * ldp;
-        if (kase == 3) {
-          double l1, l2;
-          mult_2x2(vcol[r], vr, akk, ark, arr, det, l1, l2);
-          Lr[k] = l1;
-          Lr[k + 1] = l2;
-          st_agent(&Lg[k], l1);
-          st_agent(&Lg[k + 1], l2);
-        } else {
-          const double l1 = mult_1x1(kase == 2 ? vr : vcol[r], dpiv);
-          Lr[k] = l1;
-          st_agent(&Lg[k], l1);
-        }
-      }
-    }
-    if (kase == 3 && rsrc >= s0 && rsrc < s0 + nown && tid == 0) {
-      // inside a 2x2 block L(k+1, k) = 0
-      Lrow[(size_t)(rsrc - s0) * ldp + k] = 0.0;
-      st_agent(&a.Lpanel[(size_t)rsrc * ldp + k], 0.0);
-    }
-    if (tid == 0) {
+      sh_pend_n = sstep;
+      sh_pend_t = k;
+      sh_pend_s1 = piv1;
+      sh_pend_s2 = piv2;
       if (kase == 3) {
         Dd[k] = akk;
         Dd[k + 1] = arr;
@@ -274,62 +441,83 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
     const int kold = k;
     k += sstep;
     if (k >= bb) break;
-    // ---- L and W rows of the next pivot, formed redundantly
-    const int cn = win[k];
-    // L(cn, 0:kold) was written by its owner before this step's barrier
-    for (int t = tid; t < kold; t += kThreads) Lp[t] = ld_agent(&a.Lpanel[(size_t)cn * ldp + t]);
-    __syncthreads();
-    if (tid == 0) {
-      const double vn = sym_at(A, ld, (int64_t)cn, (int64_t)c) - dot4(Lp, Wp, kold);
-      double vrn = 0.0;
-      if (kase >= 2) vrn = sym_at(A, ld, (int64_t)cn, (int64_t)rsrc) - dot4(Lp, Wr, kold);
-      if (kase == 3) {
-        double l1, l2;
-        mult_2x2(vn, vrn, akk, ark, arr, det, l1, l2);
+    // ---- the next pivot's new L entries, W entries and a_kk (wave 0; the
+    // same in every workgroup)
+    if (tid < 16) {
+      const double sold = dot16_lanes(Lp, Wn, kold, tid);
+      if (tid == 0) {
+        const double vn = sh_vn, vrn = (kase >= 2) ? sh_vrn : 0.0;
+        double l1 = 0.0, l2 = 0.0;
+        if (kase == 3) mult_2x2(vn, vrn, akk, ark, arr, det, l1, l2);
+        else l1 = mult_1x1(kase == 2 ? vrn : vn, dpiv);
         Lp[kold] = l1;
-        Lp[kold + 1] = l2;
-      } else {
-        Lp[kold] = mult_1x1(kase == 2 ? vrn : vn, dpiv);
+        if (kase == 3) Lp[kold + 1] = l2;
+        double tail = 0.0;
+        for (int t = kold; t < k; ++t) {
+          Wn[t] = w_entry(Lp, Dd, Ds, kind, t);
+          tail = fma(Lp[t], Wn[t], tail);
+        }
+        const double Acc = (cn == c) ? sh_Acc : (cn == c1 ? sh_A11 : sh_A22);
+        sh_Acc = Acc;
+        sh_akk = Acc - (sold + tail);
       }
     }
-    __syncthreads();
-    for (int t = tid; t < k; t += kThreads) Wp[t] = w_entry(Lp, Dd, Ds, kind, t);
+    {
+      double* tmp = Wp;
+      Wp = Wn;
+      Wn = tmp;
+    }
+    cur = (cn == c) ? cur : (cn == c1 ? (cur + 1) % 3 : (cur + 2) % 3);
     __syncthreads();
   }
+  flush_T();
 
   // ---- results
   for (int r = tid; r < nown; r += kThreads) {
     a.posof[s0 + r] = posl[r];
     a.srcat[posl[r]] = s0 + r;
   }
+  // my rows of T, column-major lpad x m
+  for (int e = tid; e < ntr * k; e += kThreads) {
+    const int j = e / k, t = e % k;
+    const int r = tr0 + j * P.G;
+    if (r < lpad) a.T[(size_t)t * lpad + r] = Tl[(size_t)j * ldt + t];
+  }
   if (g == 0 && tid == 0) {
     a.ctrl->m = k;
-    for (int i = 0; i < 4; ++i) atomicAdd((unsigned long long*)&a.ctrl->ncase[i],
-                                          (unsigned long long)ncase[i]);
+    for (int i = 0; i < 4; ++i)
+      atomicAdd((unsigned long long*)&a.ctrl->ncase[i], (unsigned long long)ncase[i]);
   }
 }
 
-size_t panel_lds(int R, int ldp, int bb) {
-  return (size_t)R * ldp * 8 + (size_t)R * 8 + (size_t)6 * ldp * 8 + (size_t)ldp * 4 +
-         (size_t)R * 4 + (size_t)(bb + 2) * 4 + 64;
+size_t panel_lds(int R, int ldp, int bb, int ntr, int ldt) {
+  return (size_t)R * ldp * 8 + (size_t)7 * R * 8 + (size_t)12 * ldp * 8 +
+         (size_t)ntr * ldt * 8 + (size_t)ldp * 4 + (size_t)R * 4 + (size_t)(bb + 2) * 4 + 64;
 }
 
 }  // namespace
 
-int panel_grid(int N, int ldp, int num_cu, size_t* lds_bytes) {
+int panel_grid(int N, int ldp, int lpad, int num_cu, size_t* lds_bytes, int* ntr_out) {
   int G = std::max(1, std::min(num_cu, (N + 15) / 16));
-  int bb = ldp;  // upper bound for the window size
-  while (G < num_cu && panel_lds((N + G - 1) / G, ldp, bb) > 150 * 1024) ++G;
-  *lds_bytes = panel_lds((N + G - 1) / G, ldp, bb);
+  auto lds_of = [&](int gg) {
+    const int ntr = (lpad + gg - 1) / gg;
+    return panel_lds((N + gg - 1) / gg, ldp, ldp, ntr, ldp);
+  };
+  while (G < num_cu && lds_of(G) > 150 * 1024) ++G;
+  *lds_bytes = lds_of(G);
+  *ntr_out = (lpad + G - 1) / G;
   return G;
 }
 
-void launch_panel(const PanelArgs& a, Exchange ex, int G, size_t lds_bytes, hipStream_t s) {
+void launch_panel(const PanelArgs& a, Exchange ex, int G, int ntr, size_t lds_bytes,
+                  hipStream_t s) {
   PanelParams p;
   p.a = a;
   p.ex = ex;
   p.G = G;
   p.R = (a.N + G - 1) / G;
+  p.ntr = ntr;
+  p.ldt = a.ldp;
   hipFuncSetAttribute((const void*)panel_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)lds_bytes);
   void* args[] = {&p};

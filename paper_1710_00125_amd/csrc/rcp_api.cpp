@@ -191,9 +191,10 @@ int rcp_factor(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, ui
   {
     const int Gs = select_grid((int)n, lpad, ncu);
     const int Rs = (int)((n + Gs - 1) / Gs);
-    if ((size_t)l * (Rs | 1) * 8 + (size_t)lpad * 8 + 4096 > 150 * 1024) return RCP_EUNSUPPORTED;
+    if ((size_t)Rs * (l | 1) * 8 + (size_t)lpad * 8 + 4096 > 150 * 1024) return RCP_EUNSUPPORTED;
     size_t lds = 0;
-    panel_grid((int)n, ldp, ncu, &lds);
+    int ngr = 0;
+    panel_grid((int)n, ldp, lpad, ncu, &lds, &ngr);
     if (lds > 150 * 1024) return RCP_EUNSUPPORTED;
   }
   const int Gmax = ncu;
@@ -284,7 +285,8 @@ int rcp_factor(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, ui
     {
       Scope sc(KPanel);
       size_t lds = 0;
-      const int Gp = panel_grid(N, ldp, ncu, &lds);
+      int ngr = 0;
+      const int Gp = panel_grid(N, ldp, lpad, ncu, &lds, &ngr);
       PanelArgs pa;
       pa.A = Ac + K0 + K0 * n;
       pa.ld = n;
@@ -300,8 +302,12 @@ int rcp_factor(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, ui
       pa.n = n;
       pa.srcat = srcat;
       pa.ctrl = ctrl;
+      pa.B = Bc;
+      pa.l = l;
+      pa.lpad = lpad;
+      pa.T = Tm;
       hipMemsetAsync(ex.bar, 0, (size_t)Gmax * 128, s);
-      launch_panel(pa, ex, Gp, lds, s);
+      launch_panel(pa, ex, Gp, ngr, lds, s);
     }
     RCP_CHECK(hipGetLastError());
     RCP_CHECK(hipMemcpyAsync(g_ctrl_host, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
@@ -323,7 +329,6 @@ int rcp_factor(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, ui
     const int N2 = N - m;
     if (N2 > 0) {
       Scope sc(KSketchUpd);
-      launch_sketch_trsm(Bc, lpad, l, srcat, m, Lpanel, ldp, Tm, s);
       launch_sketch_update(Bc, lpad, l, srcat, m, N, Lpanel, ldp, Tm, Bn, s);
     }
     const int Qk = (m + 3) / 4;
