@@ -5,9 +5,11 @@
 // take blocks in the order they obtain a ticket from an atomic counter, so a
 // workgroup only ever waits for blocks whose workgroups are already running;
 // each subtracts the contributions of finished blocks as their "done" flags
-// appear, solves its diagonal block in one wave, publishes its part of the
-// solution and raises its flag.  L is read once per solve direction, in
-// 64 x 64 tiles staged through LDS with coalesced column runs.
+// appear, solves its diagonal block in one wave (lane broadcasts through
+// scalar registers), publishes its part of the solution with agent-scope
+// stores and raises its flag.  L is read once per solve direction, in 64 x 64
+// tiles staged through LDS with coalesced column runs, each staged before
+// the wait for the block it needs.
 #include <climits>
 
 #include "common.h"
@@ -103,38 +105,47 @@ __global__ void dsolve_kernel(int64_t n, int nrhs, const double* __restrict__ D,
   }
 }
 
+// bounded wait for another workgroup's flag (agent-scope loads; no fences:
+// everything the waiter reads afterwards was published with agent-scope
+// stores before the flag)
 __device__ __forceinline__ void wait_flag(const unsigned int* f, unsigned int* abort_word) {
   if (threadIdx.x == 0) {
     unsigned int spins = 0;
-    while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
-      if (__hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-      if (++spins > (1u << 24)) {
-        __hip_atomic_store(abort_word, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        break;
+    while (ld_agent(f) == 0u) {
+      if ((++spins & 1023u) == 0) {
+        if (ld_agent(abort_word)) break;
+        if (spins > (1u << 22)) {
+          st_agent(abort_word, 1u);
+          break;
+        }
       }
       __builtin_amdgcn_s_sleep(1);
     }
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
-__device__ __forceinline__ void raise_flag(unsigned int* f) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_store(f, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ double bcast_lane(double v, int lane) {
+  const unsigned long long u = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, lane);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), lane);
+  return __longlong_as_double(((unsigned long long)hi << 32) | lo);
 }
 
 // Forward (lower = 1): L y = y.  Backward (lower = 0): L^T y = y.
 // sync[0] = ticket counter, sync[1 + k] = done flag of block k, sync[1 + nb]
-// = abort word (raised by a wait that timed out).
+// = abort word (raised by a wait that timed out).  A block's finished values
+// are published with agent-scope stores, then its flag.
 __global__ void __launch_bounds__(256) trsv_chain_kernel(int64_t n, int nrhs,
                                                         const double* __restrict__ L,
                                                         double* __restrict__ Y,
                                                         unsigned int* sync, int lower) {
-  __shared__ double Ls[kBlk][kBlk + 1];   // Ls[col][row] of the staged 64 x 64 tile
-  __shared__ double xs[kMaxRhs][kBlk];
-  __shared__ double part[4][kMaxRhs][kBlk];
+  extern __shared__ double smem[];
+  double (*Ls)[kBlk + 1] = (double (*)[kBlk + 1])smem;                 // off-diagonal tile
+  double (*Ld)[kBlk + 1] = (double (*)[kBlk + 1])(smem + kBlk * (kBlk + 1));   // diagonal tile
+  double (*xs)[kBlk] = (double (*)[kBlk])(smem + 2 * kBlk * (kBlk + 1));
+  double (*part)[kMaxRhs][kBlk] = (double (*)[kMaxRhs][kBlk])(smem + 2 * kBlk * (kBlk + 1) +
+                                                             kMaxRhs * kBlk);
   __shared__ int sh_blk;
   const int tid = threadIdx.x;
   const int64_t nb = (n + kBlk - 1) / kBlk;
@@ -151,23 +162,32 @@ __global__ void __launch_bounds__(256) trsv_chain_kernel(int64_t n, int nrhs,
   double acc[kMaxRhs];
 #pragma unroll
   for (int c = 0; c < kMaxRhs; ++c) acc[c] = 0.0;
+  // the diagonal tile and my right-hand sides do not depend on anyone
+  for (int e = tid; e < kBlk * kBlk; e += 256) {
+    const int rr = e & 63, cc = e >> 6;
+    Ld[cc][rr] = (rr < kn && cc < kn) ? L[(k0 + rr) + (k0 + cc) * n] : 0.0;
+  }
+  double yown[kMaxRhs];
+  if (tid < 64)
+    for (int c = 0; c < nrhs; ++c) yown[c] = (tid < kn) ? Y[c * n + k0 + tid] : 0.0;
 
   const int64_t jfirst = lower ? 0 : K + 1, jlast = lower ? K - 1 : nb - 1;
   for (int64_t jj = jfirst; jj <= jlast; ++jj) {
     const int64_t J = lower ? jj : (nb - 1 - (jj - jfirst));
-    wait_flag(&sync[1 + J], &sync[1 + nb]);
     const int64_t j0 = J * kBlk;
     const int jn = (int)std::min<int64_t>(kBlk, n - j0);
-    // stage the off-diagonal tile: forward L(rows K, cols J), backward L(rows J, cols K)
+    // stage the off-diagonal tile before waiting: forward L(rows K, cols J),
+    // backward L(rows J, cols K)
     const int64_t rbase = lower ? k0 : j0, cbase = lower ? j0 : k0;
     const int rn = lower ? kn : jn, cn = lower ? jn : kn;
     for (int e = tid; e < kBlk * kBlk; e += 256) {
       const int rr = e & 63, cc = e >> 6;
       Ls[cc][rr] = (rr < rn && cc < cn) ? L[(rbase + rr) + (cbase + cc) * n] : 0.0;
     }
+    wait_flag(&sync[1 + J], &sync[1 + nb]);
     for (int e = tid; e < nrhs * kBlk; e += 256) {
       const int c = e / kBlk, t = e % kBlk;
-      xs[c][t] = (t < jn) ? Y[c * n + j0 + t] : 0.0;
+      xs[c][t] = (t < jn) ? ld_agent(&Y[c * n + j0 + t]) : 0.0;
     }
     __syncthreads();
     if (lower) {
@@ -186,34 +206,36 @@ __global__ void __launch_bounds__(256) trsv_chain_kernel(int64_t n, int nrhs,
     __syncthreads();
   }
   for (int c = 0; c < nrhs; ++c) part[grp][c][ro] = acc[c];
-  // stage the diagonal tile
-  for (int e = tid; e < kBlk * kBlk; e += 256) {
-    const int rr = e & 63, cc = e >> 6;
-    Ls[cc][rr] = (rr < kn && cc < kn) ? L[(k0 + rr) + (k0 + cc) * n] : 0.0;
-  }
   __syncthreads();
   if (tid < 64) {
     const int rho = tid;
     for (int c = 0; c < nrhs; ++c) {
       double val = 0.0;
       if (rho < kn)
-        val = Y[c * n + k0 + rho] - ((part[0][c][rho] + part[1][c][rho]) +
-                                     (part[2][c][rho] + part[3][c][rho]));
+        val = yown[c] - ((part[0][c][rho] + part[1][c][rho]) + (part[2][c][rho] + part[3][c][rho]));
       if (lower) {
         for (int t = 0; t < kn; ++t) {
-          const double xt = __shfl(val, t, 64);
-          if (rho > t) val = fma(-Ls[t][rho], xt, val);
+          const double xt = bcast_lane(val, t);
+          if (rho > t) val = fma(-Ld[t][rho], xt, val);
         }
       } else {
         for (int t = kn - 1; t >= 0; --t) {
-          const double xt = __shfl(val, t, 64);
-          if (rho < t) val = fma(-Ls[rho][t], xt, val);
+          const double xt = bcast_lane(val, t);
+          if (rho < t) val = fma(-Ld[rho][t], xt, val);
         }
       }
-      if (rho < kn) Y[c * n + k0 + rho] = val;
+      if (rho < kn) st_agent(&Y[c * n + k0 + rho], val);
     }
   }
-  raise_flag(&sync[1 + K]);
+  // publish: my values are complete at the coherence point before the flag
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (tid == 0) st_agent(&sync[1 + K], 1u);
+}
+
+size_t trsv_lds() {
+  return (size_t)(2 * kBlk * (kBlk + 1) + kMaxRhs * kBlk + 4 * kMaxRhs * kBlk) * sizeof(double);
 }
 
 unsigned grid1d(int64_t total) {
@@ -244,18 +266,20 @@ void launch_solve(int64_t n, const double* L, const double* D, const int8_t* ipi
                   unsigned int* sync, hipStream_t s) {
   if (n <= 0 || nrhs <= 0) return;
   const int64_t nb = (n + kBlk - 1) / kBlk;
+  hipFuncSetAttribute((const void*)trsv_chain_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)trsv_lds());
   for (int64_t c0 = 0; c0 < nrhs; c0 += kMaxRhs) {
     const int nr = (int)std::min<int64_t>(kMaxRhs, nrhs - c0);
     double* Bc = B + c0 * ldb;
     hipLaunchKernelGGL(gather_rows_kernel, dim3(grid1d(n * nr)), dim3(256), 0, s, n, nr, perm, Bc,
                        ldb, Y);
     hipMemsetAsync(sync, 0, solve_sync_words(n) * sizeof(unsigned int), s);
-    hipLaunchKernelGGL(trsv_chain_kernel, dim3((unsigned)nb), dim3(256), 0, s, n, nr, L, Y, sync,
-                       1);
+    hipLaunchKernelGGL(trsv_chain_kernel, dim3((unsigned)nb), dim3(256), trsv_lds(), s, n, nr, L,
+                       Y, sync, 1);
     hipLaunchKernelGGL(dsolve_kernel, dim3(grid1d(n * nr)), dim3(256), 0, s, n, nr, D, ipiv, Y);
     hipMemsetAsync(sync, 0, solve_sync_words(n) * sizeof(unsigned int), s);
-    hipLaunchKernelGGL(trsv_chain_kernel, dim3((unsigned)nb), dim3(256), 0, s, n, nr, L, Y, sync,
-                       0);
+    hipLaunchKernelGGL(trsv_chain_kernel, dim3((unsigned)nb), dim3(256), trsv_lds(), s, n, nr, L,
+                       Y, sync, 0);
     hipLaunchKernelGGL(scatter_rows_kernel, dim3(grid1d(n * nr)), dim3(256), 0, s, n, nr, perm, Y,
                        Bc, ldb);
   }
