@@ -24,6 +24,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_MFMA = 78.6     # TFLOP/s, MI355X dense FP64 matrix
+PEAK_FP32_MFMA = 157.3    # TFLOP/s, dense FP32 matrix
+PEAK_BF16_MFMA = 2500.0   # TFLOP/s, dense BF16 matrix
 PEAK_HBM = 8000.0         # GB/s
 
 
@@ -73,6 +75,72 @@ def cpu_baseline(cfg_name, n_sample):
                       f"one factor+solve in {dt:.1f} s"}
 
 
+def fp64_time(rcp, A, b, cfg):
+    """one FP64 factor + solve, ms (events around the two calls)"""
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    f = rcp.rcp_factor(A, cfg.b, cfg.p, cfg.seed)
+    rcp.rcp_solve(f, b)
+    e1.record()
+    torch.cuda.synchronize()
+    return round(e0.elapsed_time(e1), 3)
+
+
+def mixed_run(rcp, A, b, cfg, name, args, fp64_ms):
+    """Reduced-precision factorization + FP64 GMRES refinement to 1e-13,
+    timed over the same number of steps as the FP64 form."""
+    import torch
+    prec = {"fp32": rcp.RCP_PREC_FP32, "bf16x3": rcp.RCP_PREC_BF16X3}[name]
+    n = A.shape[0]
+
+    def step():
+        f = rcp.rcp_factor_mp(A, cfg.b, cfg.p, cfg.seed, prec)
+        st = rcp.rcp_get_stats()
+        x, info = rcp.rcp_solve_ir(A, f, b, tol=1e-13, max_outer=10, restart=30,
+                                   raise_on_noconv=False)
+        return x, st, info
+
+    for w in range(args.warmup):
+        _log(f"bench: {name} warmup {w + 1}/{args.warmup}")
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    runs = []
+    e0.record()
+    for s in range(args.steps):
+        x, st, info = step()
+        runs.append((st, info))
+        _log(f"bench: {name} step {s + 1}/{args.steps}: factor {st['ms_total']:.1f} ms, "
+             f"update {st['ms_update']:.1f} ms, refinement {info['ms']:.1f} ms "
+             f"({info['outer']} outer, {info['inner']} inner), berr {info['berr']:.2e}")
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    r = A @ x.reshape(n, -1) - b.reshape(n, -1)
+    anorm = A.abs().sum(dim=1).max()
+    berr = (r.abs().max(dim=0).values / (anorm * x.reshape(n, -1).abs().max(dim=0).values)).max().item()
+    st, info = runs[-1]
+    upd_ms = sum(r_[0]["ms_update"] for r_ in runs) / len(runs)
+    peak = PEAK_FP32_MFMA if name == "fp32" else PEAK_BF16_MFMA
+    achieved = st["flops_update"] / (upd_ms * 1e-3) / 1e12 if upd_ms > 0 else 0.0
+    return {
+        "ms_per_step": round(ms, 3),
+        "value": round((n ** 3 / 3.0) / (ms * 1e-3) / 1e12, 4),
+        "unit": "TFLOP/s",
+        "speedup_vs_fp64": round(fp64_ms / ms, 3) if fp64_ms else None,
+        "ms_factor": round(sum(r_[0]["ms_total"] for r_ in runs) / len(runs), 3),
+        "ms_refine": round(sum(r_[1]["ms"] for r_ in runs) / len(runs), 3),
+        "ir_outer": info["outer"], "ir_inner": info["inner"], "converged": info["converged"],
+        "backward_error": berr, "backward_error_reported": info["berr"],
+        "update": {"ms_total": round(upd_ms, 3), "achieved": round(achieved, 3), "peak": peak,
+                   "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                   "achieved_GBps": round(st["bytes_update"] / (upd_ms * 1e-3) / 1e9, 1)
+                   if upd_ms > 0 else 0.0},
+        "n2x2": st["n2x2"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +149,12 @@ def main():
     ap.add_argument("--config", default="householder16384")
     ap.add_argument("--cpu-sample", type=int, default=4096,
                     help="order of the oracle sample (0 skips it)")
+    ap.add_argument("--mixed", default="fp32,bf16x3",
+                    help="reduced-precision forms to time after the FP64 one "
+                         "(comma list of fp32, bf16x3; empty skips them)")
+    ap.add_argument("--cond-sweep", action="store_true",
+                    help="also time the reduced-precision forms on the cond 1e2/1e6/1e10 "
+                         "matrices of the same generator")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (a known "
                          "byte count for calibrating hardware traffic counters) and exit")
@@ -186,6 +260,25 @@ def main():
         "sbkp_cases": stats[-1]["ncase"],
         "kernel_ms": breakdown,
     }
+    del f, x
+    mixed = [m for m in args.mixed.split(",") if m]
+    if mixed:
+        out["mixed"] = {}
+        for name in mixed:
+            out["mixed"][name] = mixed_run(rcp, A, b, cfg, name, args, ms)
+        if args.cond_sweep:
+            out["cond_sweep"] = {}
+            del A
+            for c in ("1e+02", "1e+06", "1e+10"):
+                ccfg = CONFIGS[f"householder16384_cond{c}"]
+                _log(f"bench: generating {ccfg.name}")
+                Ac = torch.from_numpy(ccfg.matrix()).to(dev)
+                bc = torch.from_numpy(ccfg.rhs()).to(dev)
+                out["cond_sweep"][ccfg.name] = {
+                    name: mixed_run(rcp, Ac, bc, ccfg, name, args, None) for name in mixed}
+                fp = fp64_time(rcp, Ac, bc, ccfg)
+                out["cond_sweep"][ccfg.name]["fp64_ms"] = fp
+                del Ac, bc
     if args.cpu_sample > 0:
         _log(f"bench: timing the CPU oracle on n={args.cpu_sample}")
         out["cpu_baseline"] = cpu_baseline(args.config, args.cpu_sample)

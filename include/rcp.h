@@ -41,8 +41,14 @@ extern "C" {
 #define RCP_EDEVICE      (-1001) /* a HIP runtime call failed                */
 #define RCP_ENOMEM       (-1002) /* device workspace could not be allocated  */
 #define RCP_EUNSUPPORTED (-1003) /* size outside what this build supports    */
+#define RCP_ENOCONV      (-1004) /* refinement did not reach the tolerance    */
 
-/* Per-call statistics (filled by every rcp_factor / rcp_solve call). */
+/* Working precisions of rcp_factor_mp. */
+#define RCP_PREC_FP32    1  /* FP32 trailing matrix, L, sketch and update    */
+#define RCP_PREC_BF16X3  2  /* as FP32, but the update multiplies BF16 splits
+                               x = hi + lo: hi*hi + hi*lo + lo*hi, FP32 sums */
+
+/* Per-call statistics (filled by every factor / solve call). */
 typedef struct rcp_stats {
   int64_t n;              /* order of the last factorization                  */
   int64_t nblocks;        /* blocks processed                                 */
@@ -107,6 +113,58 @@ int rcp_factor(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p,
  * 1-based position k (B is then left untouched), or RCP_EDEVICE. */
 int rcp_solve(int64_t n, const double* L, const double* D, const int8_t* ipiv,
               const int64_t* perm, int64_t nrhs, double* B, int64_t ldb);
+
+/* Reduced-precision RCP factorization, meant as the preconditioner of
+ * rcp_solve_ir (the method of Algorithm 1 is unchanged; only the storage and
+ * the products that dominate its cost are narrowed).
+ *   precision  RCP_PREC_FP32 or RCP_PREC_BF16X3: the working copy of A, the
+ *              sketch product B = Omega A and the trailing update
+ *              A22 -= L21 D1 L21^T run in that precision; the pivot tests,
+ *              the multipliers, D and every 2x2 determinant and inverse are
+ *              computed in FP64 from the stored values
+ *   L          FLOAT n x n, ld = n, same structure as in rcp_factor
+ *   other arguments as rcp_factor (argument 7 is precision; perm, L, D,
+ *   ipiv are arguments 8..11).
+ * Pivots may differ from rcp_factor's where rounding in the narrower
+ * precision changes a comparison.  Returns as rcp_factor. */
+int rcp_factor_mp(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p,
+                  uint64_t seed, int32_t precision, int64_t* perm, float* L, double* D,
+                  int8_t* ipiv);
+
+/* rcp_solve with the FLOAT L of rcp_factor_mp: the right-hand sides and all
+ * arithmetic stay FP64, L entries are widened as they are read.  Arguments
+ * and returns as rcp_solve. */
+int rcp_solve_mp(int64_t n, const float* L, const double* D, const int8_t* ipiv,
+                 const int64_t* perm, int64_t nrhs, double* B, int64_t ldb);
+
+/* Result of rcp_solve_ir. */
+typedef struct rcp_ir_result {
+  int32_t outer;   /* residual evaluations after the first solve            */
+  int32_t inner;   /* GMRES iterations, summed over cycles (max over RHS)    */
+  double  berr;    /* max over RHS of ||b - A x||_inf / (||A||_inf ||x||_inf) */
+  double  ms;      /* wall time of the call on the stream                    */
+} rcp_ir_result;
+
+/* Solve A X = B to FP64 accuracy by GMRES-based iterative refinement: the
+ * residual r = B - A X and the update of X are FP64; each correction solves
+ * A d = r by GMRES (restart `restart`, FP64 Krylov vectors, stopping when
+ * ||r - A d||_2 <= 1e-6 ||r||_2) right-preconditioned by the factors of
+ * rcp_factor_mp (applied as in rcp_solve_mp).  The refinement is not part
+ * of the paper's method.
+ *   A        the original n x n matrix (lower triangle read), lda >= max(1,n)
+ *   L..perm  factors of A from rcp_factor_mp
+ *   B        n x nrhs (ldb), not modified;  X: n x nrhs (ldx), written
+ *   tol      stop when every column has backward error <= tol (e.g. 1e-13)
+ *   max_outer  at most this many refinement steps (>= 1)
+ *   restart  GMRES restart length, 1..64
+ *   res      optional (may be NULL), filled on return
+ * Returns 0, -i for a bad argument i, +k for an exactly zero 1x1 pivot,
+ * RCP_ENOCONV if tol was not reached (X holds the last iterate),
+ * RCP_EDEVICE or RCP_ENOMEM. */
+int rcp_solve_ir(int64_t n, const double* A, int64_t lda, const float* L, const double* D,
+                 const int8_t* ipiv, const int64_t* perm, int64_t nrhs, const double* B,
+                 int64_t ldb, double* X, int64_t ldx, double tol, int32_t max_outer,
+                 int32_t restart, rcp_ir_result* res);
 
 #ifdef __cplusplus
 }

@@ -4,14 +4,17 @@ Thin Python binding of the C ABI in ``include/rcp.h`` (librcp.so, built
 in-tree by ``paper_1710_00125_amd.build``).  The functions carry the C names
 and only marshal arguments: torch tensors on the GPU supply device memory and
 the current torch stream is handed to the library; every step of the
-factorization and the solve runs in the library's HIP kernels.  There is no
-fallback: if librcp.so is missing or no GPU is present the calls raise.
+factorization, the solve and the refinement runs in the library's HIP
+kernels.  There is no fallback: if librcp.so is missing or no GPU is present
+the calls raise.
 """
 
-from ._binding import (RCPError, Factors, lib_path, load, rcp_factor, rcp_get_stats,
-                       rcp_omega, rcp_release, rcp_set_profiling, rcp_set_stream, rcp_solve,
-                       exported_symbols)
+from ._binding import (RCP_ENOCONV, RCP_PREC_BF16X3, RCP_PREC_FP32, RCPError, Factors,
+                       exported_symbols, lib_path, load, rcp_factor, rcp_factor_mp,
+                       rcp_get_stats, rcp_omega, rcp_release, rcp_set_profiling, rcp_set_stream,
+                       rcp_solve, rcp_solve_ir, rcp_solve_mp)
 
-__all__ = ["RCPError", "Factors", "lib_path", "load", "rcp_factor", "rcp_get_stats",
-           "rcp_omega", "rcp_release", "rcp_set_profiling", "rcp_set_stream", "rcp_solve",
-           "exported_symbols"]
+__all__ = ["RCP_ENOCONV", "RCP_PREC_BF16X3", "RCP_PREC_FP32", "RCPError", "Factors",
+           "exported_symbols", "lib_path", "load", "rcp_factor", "rcp_factor_mp",
+           "rcp_get_stats", "rcp_omega", "rcp_release", "rcp_set_profiling", "rcp_set_stream",
+           "rcp_solve", "rcp_solve_ir", "rcp_solve_mp"]

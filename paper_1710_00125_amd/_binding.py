@@ -11,6 +11,9 @@ RCP_ENONFINITE = -1000
 RCP_EDEVICE = -1001
 RCP_ENOMEM = -1002
 RCP_EUNSUPPORTED = -1003
+RCP_ENOCONV = -1004
+RCP_PREC_FP32 = 1
+RCP_PREC_BF16X3 = 2
 
 
 class RCPError(RuntimeError):
@@ -30,6 +33,11 @@ class _Stats(ctypes.Structure):
                 ("flops_update", ctypes.c_double), ("bytes_update", ctypes.c_double)]
 
 
+class _IrResult(ctypes.Structure):
+    _fields_ = [("outer", ctypes.c_int32), ("inner", ctypes.c_int32), ("berr", ctypes.c_double),
+                ("ms", ctypes.c_double)]
+
+
 _SIGS = {
     "rcp_set_stream": (ctypes.c_int, [ctypes.c_void_p]),
     "rcp_set_profiling": (ctypes.c_int, [ctypes.c_int32]),
@@ -44,6 +52,19 @@ _SIGS = {
     "rcp_solve": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                  ctypes.c_void_p, ctypes.c_int64]),
+    "rcp_factor_mp": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                                     ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p]),
+    "rcp_solve_mp": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                    ctypes.c_void_p, ctypes.c_int64]),
+    "rcp_solve_ir": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                    ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                    ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.POINTER(_IrResult)]),
 }
 
 
@@ -129,10 +150,11 @@ def rcp_omega(seed, l, n, device="cuda"):
 class Factors:
     n: int
     perm: object     # int64[n]
-    L: object        # n x n (logical view; storage is column-major)
+    L: object        # n x n (logical view; storage is column-major), float64 or float32
     D: object        # float64[2n]
     ipiv: object     # int8[n]
     info: int
+    precision: int = 0   # 0 = FP64, RCP_PREC_FP32, RCP_PREC_BF16X3
 
 
 def rcp_factor(A, b, p, seed):
@@ -158,21 +180,79 @@ def rcp_factor(A, b, p, seed):
     return Factors(n, perm, Lbuf.t(), D, ipiv, info)
 
 
-def rcp_solve(f, B):
-    """X with A X = B from the factors of rcp_factor; B is (n,) or (n, nrhs)."""
+def rcp_factor_mp(A, b, p, seed, precision=RCP_PREC_FP32):
+    """Reduced-precision factorization (FP32 or BF16x3 update); L is float32."""
+    torch = _torch()
+    n = A.shape[0]
+    assert A.dim() == 2 and A.shape[1] == n and A.dtype == torch.float64 and A.is_cuda
+    Acm = A.t().contiguous()
+    dev = A.device
+    perm = torch.empty(n, dtype=torch.int64, device=dev)
+    Lbuf = torch.empty((n, n), dtype=torch.float32, device=dev)
+    D = torch.empty(2 * n, dtype=torch.float64, device=dev)
+    ipiv = torch.empty(n, dtype=torch.int8, device=dev)
+    rcp_set_stream()
+    info = load().rcp_factor_mp(n, _ptr(Acm), max(1, n), int(b), int(p),
+                                ctypes.c_uint64(int(seed) & (2**64 - 1)), int(precision),
+                                _ptr(perm), _ptr(Lbuf), _ptr(D), _ptr(ipiv))
+    _check("rcp_factor_mp", info, ok_positive=True)
+    return Factors(n, perm, Lbuf.t(), D, ipiv, info, int(precision))
+
+
+def _rhs_cm(B):
+    """(column-major n x nrhs buffer, vec flag): always a fresh copy so that
+    the caller's B is never overwritten (B.t().contiguous() can alias B)."""
     torch = _torch()
     vec = B.dim() == 1
     Bm = B[:, None] if vec else B
     n, nrhs = Bm.shape
-    # (nrhs, n) = column-major n x nrhs; always a fresh buffer so that the
-    # caller's B is never overwritten (B.t().contiguous() can alias B)
     Bcm = torch.empty((nrhs, n), dtype=torch.float64, device=Bm.device)
     Bcm.copy_(Bm.t())
+    return Bcm, vec
+
+
+def rcp_solve(f, B):
+    """X with A X = B from the factors of rcp_factor or rcp_factor_mp;
+    B is (n,) or (n, nrhs), float64."""
+    Bcm, vec = _rhs_cm(B)
+    nrhs, n = Bcm.shape
     Lcm = f.L.t()                              # the column-major storage itself
     assert Lcm.is_contiguous()
     rcp_set_stream()
-    code = load().rcp_solve(n, _ptr(Lcm), _ptr(f.D), _ptr(f.ipiv), _ptr(f.perm), nrhs,
-                            _ptr(Bcm), max(1, n))
-    _check("rcp_solve", code)
+    fn = "rcp_solve_mp" if f.precision else "rcp_solve"
+    code = getattr(load(), fn)(n, _ptr(Lcm), _ptr(f.D), _ptr(f.ipiv), _ptr(f.perm), nrhs,
+                               _ptr(Bcm), max(1, n))
+    _check(fn, code)
     X = Bcm.t()
     return X[:, 0] if vec else X
+
+
+def rcp_solve_mp(f, B):
+    """rcp_solve for the float32 factors of rcp_factor_mp."""
+    assert f.precision, "rcp_solve_mp needs the factors of rcp_factor_mp"
+    return rcp_solve(f, B)
+
+
+def rcp_solve_ir(A, f, B, tol=1e-13, max_outer=10, restart=30, raise_on_noconv=True):
+    """FP64 solution of A X = B by GMRES-based refinement preconditioned by the
+    reduced-precision factors f.  Returns (X, info dict)."""
+    torch = _torch()
+    assert f.precision, "rcp_solve_ir needs the factors of rcp_factor_mp"
+    n = A.shape[0]
+    Acm = A.t().contiguous()
+    Bcm, vec = _rhs_cm(B)
+    nrhs = Bcm.shape[0]
+    Xcm = torch.empty_like(Bcm)
+    Lcm = f.L.t()
+    assert Lcm.is_contiguous()
+    res = _IrResult()
+    rcp_set_stream()
+    code = load().rcp_solve_ir(n, _ptr(Acm), max(1, n), _ptr(Lcm), _ptr(f.D), _ptr(f.ipiv),
+                               _ptr(f.perm), nrhs, _ptr(Bcm), max(1, n), _ptr(Xcm), max(1, n),
+                               float(tol), int(max_outer), int(restart), ctypes.byref(res))
+    info = {"outer": res.outer, "inner": res.inner, "berr": res.berr, "ms": res.ms,
+            "converged": code == 0}
+    if code != RCP_ENOCONV or raise_on_noconv:
+        _check("rcp_solve_ir", code)
+    X = Xcm.t()
+    return (X[:, 0] if vec else X), info

@@ -5,7 +5,8 @@
 //     T = B~_1 L11^{-T} is built column by column by the panel kernel;
 //   * the commit of the block: the block's interchanges applied to the
 //     permutation, the block's columns of L stored, and L21 and W21 = L21 D1
-//     packed in matrix-core fragment order for the trailing update.
+//     packed in matrix-core fragment order for the trailing update (FP64,
+//     FP32, or BF16 hi/lo pairs by working precision).
 //
 // Inside a block every array is indexed by source (position at block start);
 // srcat[i] is the source that ends at block position i, so the first m
@@ -92,12 +93,15 @@ __device__ __forceinline__ double w_of_row(const double* __restrict__ x, const d
   return fma(x[t - 1], Dg[n + gt - 1], x[t] * Dg[gt]);
 }
 
+// FP64 / FP32 packing for the K = 4 matrix-core steps: element e of the
+// packed arrays is ((g * Qk + qk) * 64 + lane), holding row 16 g + lane % 16
+// and k = 4 qk + lane / 16.
+template <typename TF>
 __global__ void commit_pack_kernel(const int* __restrict__ srcat, int m, int N, int K0, int64_t n,
                                    const double* __restrict__ Lp, int ldp,
                                    const double* __restrict__ Dg, const int8_t* __restrict__ ipiv,
-                                   double* __restrict__ L21p, double* __restrict__ W21p, int Qk,
+                                   TF* __restrict__ L21p, TF* __restrict__ W21p, int Qk,
                                    int rows_pad, int* __restrict__ rowsrc) {
-  // element e of the packed arrays: ((g * Qk + qk) * 64 + lane)
   const int64_t total = (int64_t)rows_pad * Qk * 4;
   const int N2 = N - m;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
@@ -114,26 +118,79 @@ __global__ void commit_pack_kernel(const int* __restrict__ srcat, int m, int N, 
       lv = x[t];
       wv = w_of_row(x, Dg, ipiv, n, K0, t);
     }
-    L21p[e] = lv;
-    W21p[e] = wv;
+    L21p[e] = (TF)lv;
+    W21p[e] = (TF)wv;
   }
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N2;
        i += (int64_t)gridDim.x * blockDim.x)
     rowsrc[i] = srcat[m + i];
 }
 
+// BF16 split packing for the K = 32 matrix-core steps: x = hi + lo with
+// hi = bf16(x) and lo = bf16(x - hi).  Fragment (g, qk) is 2 KB: 64 lanes x
+// 8 hi values, then 64 lanes x 8 lo values; lane l holds row 16 g + l % 16
+// and k = 32 qk + 8 (l / 16) + e.
+__device__ __forceinline__ void split_bf16(double x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)(float)x;
+  lo = (__bf16)(float)(x - (double)(float)hi);
+}
+
+__global__ void commit_pack_bf16x3_kernel(const int* __restrict__ srcat, int m, int N, int K0,
+                                          int64_t n, const double* __restrict__ Lp, int ldp,
+                                          const double* __restrict__ Dg,
+                                          const int8_t* __restrict__ ipiv, rcp_bf8* __restrict__ L21p,
+                                          rcp_bf8* __restrict__ W21p, int Qk, int rows_pad,
+                                          int* __restrict__ rowsrc) {
+  const int64_t total = (int64_t)(rows_pad / 16) * Qk * 64;
+  const int N2 = N - m;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = (int)(e & 63);
+    const int64_t frag = e >> 6;
+    const int qk = (int)(frag % Qk);
+    const int g = (int)(frag / Qk);
+    const int row = 16 * g + (lane & 15);
+    rcp_bf8 lh, ll, wh, wl;
+    const double* x = (row < N2) ? Lp + (size_t)srcat[m + row] * ldp : nullptr;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = 32 * qk + 8 * (lane >> 4) + u;
+      double lv = 0.0, wv = 0.0;
+      if (x && t < m) {
+        lv = x[t];
+        wv = w_of_row(x, Dg, ipiv, n, K0, t);
+      }
+      __bf16 h, lo;
+      split_bf16(lv, h, lo);
+      lh[u] = h;
+      ll[u] = lo;
+      split_bf16(wv, h, lo);
+      wh[u] = h;
+      wl[u] = lo;
+    }
+    L21p[frag * 128 + lane] = lh;
+    L21p[frag * 128 + 64 + lane] = ll;
+    W21p[frag * 128 + lane] = wh;
+    W21p[frag * 128 + 64 + lane] = wl;
+  }
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N2;
+       i += (int64_t)gridDim.x * blockDim.x)
+    rowsrc[i] = srcat[m + i];
+}
+
+template <typename TL>
 __global__ void commit_rows_kernel(const int* __restrict__ srcat, int m, int N, int K0, int64_t n,
                                    const double* __restrict__ Lp, int ldp,
                                    const int64_t* __restrict__ Pcur, int64_t* __restrict__ Pnext,
-                                   double* __restrict__ Lwork) {
+                                   TL* __restrict__ Lwork) {
   // one workgroup per block position i: the block's L entries of the source
   // that ends at i go to row P(original index) of Lwork
   for (int i = blockIdx.x; i < N; i += gridDim.x) {
     const int s = srcat[i];
     const int64_t orig = Pcur[K0 + s];
     const double* x = Lp + (size_t)s * ldp;
-    double* dst = Lwork + orig * n + K0;
-    for (int t = threadIdx.x; t < m; t += blockDim.x) dst[t] = x[t];
+    TL* dst = Lwork + orig * n + K0;
+    for (int t = threadIdx.x; t < m; t += blockDim.x) dst[t] = (TL)x[t];
     if (threadIdx.x == 0) Pnext[K0 + i] = orig;
   }
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < K0;
@@ -156,19 +213,41 @@ void launch_sketch_update(const double* B, int lpad, int l, const int* srcat, in
                      B, lpad, l, srcat, m, N, Lpanel, ldp, T, Bnext);
 }
 
+int update_k_frags(int prec, int m) { return prec == kPrecBF16x3 ? (m + 31) / 32 : (m + 3) / 4; }
+
+size_t update_pack_bytes(int prec, int64_t rows_pad, int Qk) {
+  if (prec == kPrecBF16x3) return (size_t)(rows_pad / 16) * Qk * 2048;
+  return (size_t)rows_pad * Qk * 4 * prec_elem_bytes(prec);
+}
+
 void launch_commit(const int* srcat, int m, int N, int K0, int64_t n, const double* Lpanel,
                    int ldp, const double* Dg, const int8_t* ipiv, const int64_t* Pcur,
-                   int64_t* Pnext, double* Lwork, double* L21p, double* W21p, int Qk,
+                   int64_t* Pnext, void* Lwork, int prec, void* L21p, void* W21p, int Qk,
                    int rows_pad, int* rowsrc, hipStream_t s) {
   if (N - m > 0) {
-    const int64_t total = (int64_t)rows_pad * Qk * 4;
+    const int64_t total = prec == kPrecBF16x3 ? (int64_t)(rows_pad / 16) * Qk * 64
+                                              : (int64_t)rows_pad * Qk * 4;
     const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 8192);
-    hipLaunchKernelGGL(commit_pack_kernel, dim3(blocks), dim3(256), 0, s, srcat, m, N, K0, n,
-                       Lpanel, ldp, Dg, ipiv, L21p, W21p, Qk, rows_pad, rowsrc);
+    if (prec == kPrecF64)
+      hipLaunchKernelGGL(commit_pack_kernel<double>, dim3(blocks), dim3(256), 0, s, srcat, m, N,
+                         K0, n, Lpanel, ldp, Dg, ipiv, (double*)L21p, (double*)W21p, Qk,
+                         rows_pad, rowsrc);
+    else if (prec == kPrecF32)
+      hipLaunchKernelGGL(commit_pack_kernel<float>, dim3(blocks), dim3(256), 0, s, srcat, m, N,
+                         K0, n, Lpanel, ldp, Dg, ipiv, (float*)L21p, (float*)W21p, Qk, rows_pad,
+                         rowsrc);
+    else
+      hipLaunchKernelGGL(commit_pack_bf16x3_kernel, dim3(blocks), dim3(256), 0, s, srcat, m, N,
+                         K0, n, Lpanel, ldp, Dg, ipiv, (rcp_bf8*)L21p, (rcp_bf8*)W21p, Qk,
+                         rows_pad, rowsrc);
   }
   const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(N, 8192));
-  hipLaunchKernelGGL(commit_rows_kernel, dim3(blocks), dim3(128), 0, s, srcat, m, N, K0, n,
-                     Lpanel, ldp, Pcur, Pnext, Lwork);
+  if (prec == kPrecF64)
+    hipLaunchKernelGGL(commit_rows_kernel<double>, dim3(blocks), dim3(128), 0, s, srcat, m, N, K0,
+                       n, Lpanel, ldp, Pcur, Pnext, (double*)Lwork);
+  else
+    hipLaunchKernelGGL(commit_rows_kernel<float>, dim3(blocks), dim3(128), 0, s, srcat, m, N, K0,
+                       n, Lpanel, ldp, Pcur, Pnext, (float*)Lwork);
 }
 
 }  // namespace rcp

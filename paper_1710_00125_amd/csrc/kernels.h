@@ -10,6 +10,16 @@ namespace rcp {
 constexpr int kMaxL = 512;
 constexpr int kMaxB = 128;
 
+// Working precision of a factorization: the trailing matrix, the stored L
+// and the operands of the trailing update.  The panel arithmetic, D and the
+// 2x2 pivot determinants and inverses stay FP64 in every mode.
+enum Prec : int {
+  kPrecF64 = 0,     // everything FP64 (the plain method)
+  kPrecF32 = 1,     // FP32 storage, FP32 matrix-core update and sketch
+  kPrecBF16x3 = 2,  // FP32 storage, update as three BF16 products (hi*hi + hi*lo + lo*hi)
+};
+inline size_t prec_elem_bytes(int prec) { return prec == kPrecF64 ? 8 : 4; }
+
 // Device-resident control block of one factorization.
 struct Ctrl {
   int m;            // columns eliminated by the last panel (b or b+1)
@@ -40,12 +50,15 @@ void launch_omega(uint64_t seed, int l, int64_t n, double* out, int transposed, 
                   hipStream_t s);
 
 // ---- sketch.hip
-// Acur (n x n, ld n, lower) <- lower triangle of A (lda)
-void launch_copy_lower(int64_t n, const double* A, int64_t lda, double* Acur, hipStream_t s);
+// Acur (n x n, ld n, lower; double or float by prec) <- lower triangle of A (lda)
+void launch_copy_lower(int64_t n, const double* A, int64_t lda, void* Acur, int prec,
+                       hipStream_t s);
 // B (lpad x n column-major, B(r,j) at j*lpad + r) = Omega * sym(A)
-// using Omega^T (n x lpad) and a split-K partial buffer of ksplit*n*lpad doubles.
-void launch_sketch(int64_t n, const double* Acur, int64_t ld, const double* OmT, int lpad,
-                   double* B, double* partial, int ksplit, hipStream_t s);
+// using Omega^T (n x lpad) and a split-K partial buffer of ksplit*n*lpad doubles;
+// FP64 matrix cores for prec == kPrecF64, FP32 matrix cores otherwise
+// (Acur then holds floats).
+void launch_sketch(int64_t n, const void* Acur, int prec, int64_t ld, const double* OmT,
+                   int lpad, double* B, double* partial, int ksplit, hipStream_t s);
 // ctrl->nonfinite |= any entry of B (first l rows) is NaN/Inf
 void launch_check_finite(int64_t n, const double* B, int lpad, int l, Ctrl* ctrl, hipStream_t s);
 void launch_iota64(int64_t n, int64_t* P, hipStream_t s);
@@ -60,7 +73,8 @@ void launch_select(const double* B, int lpad, int l, int N, int bb, int* posof, 
 
 // ---- panel.hip  (SBKP elimination of one block)
 struct PanelArgs {
-  const double* A;    // trailing block at block start (lower, ld)
+  const void* A;      // trailing block at block start (lower, ld; float unless prec == F64)
+  int prec;
   int64_t ld;
   int N;              // trailing order at block start
   int bb;             // min(b, N)
@@ -88,27 +102,65 @@ void launch_sketch_update(const double* B, int lpad, int l, const int* srcat, in
                           const double* Lpanel, int ldp, const double* T, double* Bnext,
                           hipStream_t s);
 // Pack L21 and W21 = L21 D1 (rows srcat[m..N)) in MFMA fragment order,
-// write the block's rows of Lwork (row-major n x n by original index) and
-// Pnext, and the gather map rowsrc[i] = srcat[m + i].
+// write the block's rows of Lwork (row-major n x n by original index, element
+// type by prec) and Pnext, and the gather map rowsrc[i] = srcat[m + i].
+// Qk = number of k fragments (update_k_frags(prec, m)).
+int update_k_frags(int prec, int m);
+size_t update_pack_bytes(int prec, int64_t rows_pad, int Qk);
 void launch_commit(const int* srcat, int m, int N, int K0, int64_t n, const double* Lpanel,
                    int ldp, const double* Dg, const int8_t* ipiv, const int64_t* Pcur,
-                   int64_t* Pnext, double* Lwork, double* L21p, double* W21p, int Qk,
+                   int64_t* Pnext, void* Lwork, int prec, void* L21p, void* W21p, int Qk,
                    int rows_pad, int* rowsrc, hipStream_t s);
 
-// ---- update.hip  (trailing Schur complement, FP64 MFMA)
+// ---- update.hip  (trailing Schur complement on the matrix cores)
 // Anext(i, j) = Acur(rowsrc[i], rowsrc[j]) - sum_t L21(i,t) W21(j,t), 0 <= j <= i < N2
-void launch_update(const double* Acur, double* Anext, int64_t ld, const int* rowsrc, int N2,
-                   const double* L21p, const double* W21p, int Qk, hipStream_t s);
+void launch_update(const void* Acur, void* Anext, int64_t ld, const int* rowsrc, int N2,
+                   const void* L21p, const void* W21p, int Qk, int prec, hipStream_t s);
 
 // ---- solve.hip
-// L (n x n col-major) from Lwork rows by original index, final perm P.
-void launch_finalize_L(int64_t n, const double* Lwork, const int64_t* P, const int8_t* ipiv,
-                       double* L, hipStream_t s);
+// L (n x n col-major) from Lwork rows by original index, final perm P
+// (double when l_f32 == 0, float otherwise, for both Lwork and L).
+void launch_finalize_L(int64_t n, const void* Lwork, const int64_t* P, const int8_t* ipiv,
+                       void* L, int l_f32, hipStream_t s);
 void launch_find_zero_pivot(int64_t n, const double* D, const int8_t* ipiv, int* out,
                             hipStream_t s);
-void launch_solve(int64_t n, const double* L, const double* D, const int8_t* ipiv,
+// B <- A^{-1} B with the factors (L double when l_f32 == 0, float otherwise;
+// the right-hand sides and all arithmetic stay FP64).
+void launch_solve(int64_t n, const void* L, int l_f32, const double* D, const int8_t* ipiv,
                   const int64_t* perm, int64_t nrhs, double* B, int64_t ldb, double* Y,
                   unsigned int* sync, hipStream_t s);
 size_t solve_sync_words(int64_t n);
+
+// ---- refine.hip  (FP64 pieces of GMRES-based iterative refinement)
+// out(:, c) = A X(:, c) (mode 0) or B(:, c) - A X(:, c) (mode 1), A symmetric
+// from its lower triangle (lda), nr <= 4; abs_mode: row sums of |A| (nr = 1,
+// X unused).  work: symv_work_doubles(n, nr) doubles.
+size_t symv_work_doubles(int64_t n, int nr);
+void launch_symv(int64_t n, const double* A, int64_t lda, const double* X, int64_t ldx, int nr,
+                 int abs_mode, const double* B, int64_t ldb, double* out, int64_t ldo, int mode,
+                 double* work, hipStream_t s);
+// out[c] = max |V(:, c)| as the bit pattern of a double (out zeroed by the caller)
+void launch_absmax(int64_t n, int nr, const double* V, int64_t ldv, unsigned long long* out,
+                   hipStream_t s);
+// Krylov basis V: column (k, c) at V + (k * nr + c) * n; vectors W: (c) at W + c * n
+size_t gmres_dot_doubles(int m, int nr);
+void launch_mdot(int64_t n, int nr, int kk, const double* V, const double* W, double* part,
+                 double* h, double* hacc, hipStream_t s);
+void launch_mgs_sub(int64_t n, int nr, int kk, const double* V, const double* h, double* W,
+                    hipStream_t s);
+void launch_norm2(int64_t n, int nr, const double* W, double* part, double* nrm, hipStream_t s);
+void launch_scale(int64_t n, int nr, const double* src, const double* nrm, double* dst,
+                  hipStream_t s);
+void launch_axpy(int64_t n, int nr, const double* d, double* x, hipStream_t s);   // x += d
+size_t gmres_state_bytes(int nr);
+void launch_gmres_start(int nr, int m, const double* nrm, void* st, double* g, hipStream_t s);
+void launch_givens(int nr, int m, int k, const double* h, const double* nrm, double* hcol,
+                   void* st, double* g, double* cs, double* sn, double* R, double tol_in,
+                   hipStream_t s);
+void launch_lsq_update(int64_t n, int nr, int m, const void* st, const double* g, const double* R,
+                       double* y, int* kk, const double* V, double* X, int64_t ldx,
+                       hipStream_t s);
+int gmres_state_active(const void* host_st, int c);
+int gmres_state_iters(const void* host_st, int c);
 
 }  // namespace rcp

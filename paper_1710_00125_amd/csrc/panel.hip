@@ -116,6 +116,9 @@ __device__ __forceinline__ Rec block_best_rec(Rec r, Rec* sh) {
   return best;
 }
 
+// TA: element type of the stored trailing matrix (double, or float in the
+// reduced-precision modes; values are widened to FP64 on load)
+template <typename TA>
 __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
   const PanelArgs& a = P.a;
   extern __shared__ double smem[];
@@ -155,7 +158,7 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
   const int rho = tid >> 2;       // row within a pass
   const int grp16 = tid >> 4;     // 16-lane group (T rows)
   const int l16 = tid & 15;
-  const double* A = a.A;
+  const TA* A = (const TA*)a.A;
   const int64_t ld = a.ld;
   const int lpad = a.lpad;
   const int tr0 = P.G - 1 - g;    // my rows of T: tr0, tr0 + G, ... (< lpad)
@@ -518,11 +521,11 @@ void launch_panel(const PanelArgs& a, Exchange ex, int G, int ntr, size_t lds_by
   p.R = (a.N + G - 1) / G;
   p.ntr = ntr;
   p.ldt = a.ldp;
-  hipFuncSetAttribute((const void*)panel_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)lds_bytes);
+  const void* k = a.prec == kPrecF64 ? (const void*)panel_kernel<double>
+                                     : (const void*)panel_kernel<float>;
+  hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
   void* args[] = {&p};
-  hipLaunchCooperativeKernel((const void*)panel_kernel, dim3(G), dim3(kThreads), args, lds_bytes,
-                             s);
+  hipLaunchCooperativeKernel(k, dim3(G), dim3(kThreads), args, lds_bytes, s);
 }
 
 }  // namespace rcp

@@ -163,17 +163,15 @@ int rcp_omega(uint64_t seed, int32_t l, int64_t n, double* out) {
   return 0;
 }
 
-int rcp_factor(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, uint64_t seed,
-               int64_t* perm, double* L, double* D, int8_t* ipiv) {
-  if (n < 0) return -1;
-  if (!A && n > 0) return -2;
-  if (lda < std::max<int64_t>(1, n)) return -3;
-  if (b < 1 || b > kMaxB) return -4;
-  if (p < 0 || b + p > kMaxL) return -5;
-  if (n > 0 && !perm) return -7;
-  if (n > 0 && !L) return -8;
-  if (n > 0 && !D) return -9;
-  if (n > 0 && !ipiv) return -10;
+}  // extern "C"
+
+namespace {
+
+// The block loop of Algorithm 1 for every working precision.  Argument
+// positions in the error codes follow rcp_factor; argument errors of the
+// outputs are reported by the callers.
+int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, uint64_t seed,
+                int prec, int64_t* perm, void* L, double* D, int8_t* ipiv) {
   memset(&g_stats, 0, sizeof(g_stats));
   g_stats.n = n;
   if (n == 0) return 0;
@@ -184,7 +182,6 @@ int rcp_factor(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, ui
   const int ldp = (b + 2) | 1;
   const int ncu = num_cus();
   const int ksplit = 4;
-  const int Qmax = (b + 1 + 3) / 4;
   const int64_t rows_pad_max = (n + 127) / 128 * 128;
 
   // feasibility of the LDS-resident panels for the first (largest) block
@@ -201,8 +198,10 @@ int rcp_factor(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, ui
   const int vec_stride = std::max(lpad, ldp);
 
   const size_t nn = (size_t)n * n;
-  size_t bytes = 3 * al(nn * 8) + al((size_t)n * lpad * 8) * (2 + 1 + ksplit) +
-                 al((size_t)n * ldp * 8) + 2 * al((size_t)rows_pad_max * Qmax * 4 * 8) +
+  const size_t esz = prec_elem_bytes(prec);
+  const size_t pack_bytes = update_pack_bytes(prec, rows_pad_max, update_k_frags(prec, b + 1));
+  size_t bytes = 3 * al(nn * esz) + al((size_t)n * lpad * 8) * (2 + 1 + ksplit) +
+                 al((size_t)n * ldp * 8) + 2 * al(pack_bytes) +
                  al((size_t)lpad * (b + 2) * 8) + 2 * al((size_t)n * 8) + 3 * al((size_t)n * 4) +
                  al((size_t)(b + 2) * 4) + al(sizeof(Ctrl)) + 3 * al((size_t)2 * Gmax * 8) +
                  2 * al((size_t)2 * Gmax * 4) + al((size_t)2 * Gmax * vec_stride * 8) + al((size_t)Gmax * 128) +
@@ -210,16 +209,16 @@ int rcp_factor(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, ui
   int dev = 0;
   hipGetDevice(&dev);
   if (!g_fact.reserve(bytes, dev)) return RCP_ENOMEM;
-  double* Acur = g_fact.take<double>(nn);
-  double* Anext = g_fact.take<double>(nn);
-  double* Lwork = g_fact.take<double>(nn);
+  char* Acur = g_fact.take<char>(nn * esz);
+  char* Anext = g_fact.take<char>(nn * esz);
+  char* Lwork = g_fact.take<char>(nn * esz);
   double* OmT = g_fact.take<double>((size_t)n * lpad);
   double* Bcur = g_fact.take<double>((size_t)n * lpad);
   double* Bnext = g_fact.take<double>((size_t)n * lpad);
   double* partial = g_fact.take<double>((size_t)n * lpad * ksplit);
   double* Lpanel = g_fact.take<double>((size_t)n * ldp);
-  double* L21p = g_fact.take<double>((size_t)rows_pad_max * Qmax * 4);
-  double* W21p = g_fact.take<double>((size_t)rows_pad_max * Qmax * 4);
+  char* L21p = g_fact.take<char>(pack_bytes);
+  char* W21p = g_fact.take<char>(pack_bytes);
   double* Tm = g_fact.take<double>((size_t)lpad * (b + 2));
   int64_t* P0 = g_fact.take<int64_t>(n);
   int64_t* P1 = g_fact.take<int64_t>(n);
@@ -257,8 +256,8 @@ int rcp_factor(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, ui
   }
   {
     Scope sc(KSketch);
-    launch_copy_lower(n, A, lda, Acur, s);
-    launch_sketch(n, Acur, n, OmT, lpad, Bcur, partial, ksplit, s);
+    launch_copy_lower(n, A, lda, Acur, prec, s);
+    launch_sketch(n, Acur, prec, n, OmT, lpad, Bcur, partial, ksplit, s);
     launch_check_finite(n, Bcur, lpad, l, ctrl, s);
     launch_iota64(n, P0, s);
   }
@@ -266,8 +265,8 @@ int rcp_factor(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, ui
 
   int64_t* Pc = P0;
   int64_t* Pn = P1;
-  double* Ac = Acur;
-  double* An = Anext;
+  char* Ac = Acur;
+  char* An = Anext;
   double* Bc = Bcur;
   double* Bn = Bnext;
   int64_t K0 = 0;
@@ -288,7 +287,8 @@ int rcp_factor(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, ui
       int ngr = 0;
       const int Gp = panel_grid(N, ldp, lpad, ncu, &lds, &ngr);
       PanelArgs pa;
-      pa.A = Ac + K0 + K0 * n;
+      pa.A = Ac + (size_t)(K0 + K0 * n) * esz;
+      pa.prec = prec;
       pa.ld = n;
       pa.N = N;
       pa.bb = bb;
@@ -331,19 +331,20 @@ int rcp_factor(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, ui
       Scope sc(KSketchUpd);
       launch_sketch_update(Bc, lpad, l, srcat, m, N, Lpanel, ldp, Tm, Bn, s);
     }
-    const int Qk = (m + 3) / 4;
+    const int Qk = update_k_frags(prec, m);
     const int rows_pad = (N2 + 127) / 128 * 128;
     {
       Scope sc(KCommit);
-      launch_commit(srcat, m, N, (int)K0, n, Lpanel, ldp, D, ipiv, Pc, Pn, Lwork, L21p, W21p, Qk,
-                    rows_pad, rowsrc, s);
+      launch_commit(srcat, m, N, (int)K0, n, Lpanel, ldp, D, ipiv, Pc, Pn, Lwork, prec, L21p,
+                    W21p, Qk, rows_pad, rowsrc, s);
     }
     if (N2 > 0) {
       Scope sc(KUpdate);
-      launch_update(Ac + K0 + K0 * n, An + K1 + K1 * n, n, rowsrc, N2, L21p, W21p, Qk, s);
+      launch_update(Ac + (size_t)(K0 + K0 * n) * esz, An + (size_t)(K1 + K1 * n) * esz, n, rowsrc,
+                    N2, L21p, W21p, Qk, prec, s);
       g_stats.launches_update += 1;
       g_stats.flops_update += (double)N2 * (N2 + 1) * m;           // lower triangle, 2m per entry
-      g_stats.bytes_update += (double)N2 * (N2 + 1) / 2 * 16.0;    // read + write of each entry
+      g_stats.bytes_update += (double)N2 * (N2 + 1) / 2 * 2.0 * esz;   // read + write of each entry
     }
     RCP_CHECK(hipGetLastError());
     std::swap(Pc, Pn);
@@ -354,7 +355,7 @@ int rcp_factor(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, ui
   }
   if (status == 0) {
     Scope sc(KFinal);
-    launch_finalize_L(n, Lwork, Pc, ipiv, L, s);
+    launch_finalize_L(n, Lwork, Pc, ipiv, L, prec != kPrecF64, s);
     RCP_CHECK(hipMemcpyAsync(perm, Pc, n * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
     RCP_CHECK(hipMemcpyAsync(g_ctrl_host, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
   }
@@ -375,8 +376,19 @@ int rcp_factor(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, ui
   return 0;
 }
 
-int rcp_solve(int64_t n, const double* L, const double* D, const int8_t* ipiv,
-              const int64_t* perm, int64_t nrhs, double* B, int64_t ldb) {
+// first exactly zero 1x1 pivot (1-based), INT_MAX if none, or an RCP_E* code
+int zero_pivot(int64_t n, const double* D, const int8_t* ipiv, int* zp, hipStream_t s) {
+  const int big = INT_MAX;
+  RCP_CHECK(hipMemcpyAsync(zp, &big, sizeof(int), hipMemcpyHostToDevice, s));
+  launch_find_zero_pivot(n, D, ipiv, zp, s);
+  int zhost = 0;
+  RCP_CHECK(hipMemcpyAsync(&zhost, zp, sizeof(int), hipMemcpyDeviceToHost, s));
+  RCP_CHECK(hipStreamSynchronize(s));
+  return zhost;
+}
+
+int solve_impl(int64_t n, const void* L, int l_f32, const double* D, const int8_t* ipiv,
+               const int64_t* perm, int64_t nrhs, double* B, int64_t ldb) {
   if (n < 0) return -1;
   if (n > 0 && !L) return -2;
   if (n > 0 && !D) return -3;
@@ -395,15 +407,8 @@ int rcp_solve(int64_t n, const double* L, const double* D, const int8_t* ipiv,
   unsigned int* sync = g_solve.take<unsigned int>(words);
   int* zp = g_solve.take<int>(16);
   hipStream_t s = g_stream;
-  if (!g_ctrl_host) {
-    if (hipHostMalloc((void**)&g_ctrl_host, sizeof(Ctrl)) != hipSuccess) return RCP_EDEVICE;
-  }
-  const int big = INT_MAX;
-  RCP_CHECK(hipMemcpyAsync(zp, &big, sizeof(int), hipMemcpyHostToDevice, s));
-  launch_find_zero_pivot(n, D, ipiv, zp, s);
-  int zhost = 0;
-  RCP_CHECK(hipMemcpyAsync(&zhost, zp, sizeof(int), hipMemcpyDeviceToHost, s));
-  RCP_CHECK(hipStreamSynchronize(s));
+  const int zhost = zero_pivot(n, D, ipiv, zp, s);
+  if (zhost < 0) return zhost;
   if (zhost != INT_MAX) return zhost;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (g_prof) {
@@ -411,7 +416,7 @@ int rcp_solve(int64_t n, const double* L, const double* D, const int8_t* ipiv,
     hipEventCreate(&e1);
     hipEventRecord(e0, s);
   }
-  launch_solve(n, L, D, ipiv, perm, nrhs, B, ldb, Y, sync, s);
+  launch_solve(n, L, l_f32, D, ipiv, perm, nrhs, B, ldb, Y, sync, s);
   if (g_prof) hipEventRecord(e1, s);
   RCP_CHECK(hipGetLastError());
   unsigned int abort_word = 0;
@@ -427,6 +432,237 @@ int rcp_solve(int64_t n, const double* L, const double* D, const int8_t* ipiv,
     hipEventDestroy(e1);
   }
   return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rcp_factor(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, uint64_t seed,
+               int64_t* perm, double* L, double* D, int8_t* ipiv) {
+  if (n < 0) return -1;
+  if (!A && n > 0) return -2;
+  if (lda < std::max<int64_t>(1, n)) return -3;
+  if (b < 1 || b > kMaxB) return -4;
+  if (p < 0 || b + p > kMaxL) return -5;
+  if (n > 0 && !perm) return -7;
+  if (n > 0 && !L) return -8;
+  if (n > 0 && !D) return -9;
+  if (n > 0 && !ipiv) return -10;
+  return factor_impl(n, A, lda, b, p, seed, kPrecF64, perm, L, D, ipiv);
+}
+
+int rcp_factor_mp(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, uint64_t seed,
+                  int32_t precision, int64_t* perm, float* L, double* D, int8_t* ipiv) {
+  if (n < 0) return -1;
+  if (!A && n > 0) return -2;
+  if (lda < std::max<int64_t>(1, n)) return -3;
+  if (b < 1 || b > kMaxB) return -4;
+  if (p < 0 || b + p > kMaxL) return -5;
+  if (precision != RCP_PREC_FP32 && precision != RCP_PREC_BF16X3) return -7;
+  if (n > 0 && !perm) return -8;
+  if (n > 0 && !L) return -9;
+  if (n > 0 && !D) return -10;
+  if (n > 0 && !ipiv) return -11;
+  const int prec = precision == RCP_PREC_FP32 ? kPrecF32 : kPrecBF16x3;
+  return factor_impl(n, A, lda, b, p, seed, prec, perm, L, D, ipiv);
+}
+
+int rcp_solve(int64_t n, const double* L, const double* D, const int8_t* ipiv,
+              const int64_t* perm, int64_t nrhs, double* B, int64_t ldb) {
+  return solve_impl(n, L, 0, D, ipiv, perm, nrhs, B, ldb);
+}
+
+int rcp_solve_mp(int64_t n, const float* L, const double* D, const int8_t* ipiv,
+                 const int64_t* perm, int64_t nrhs, double* B, int64_t ldb) {
+  return solve_impl(n, L, 1, D, ipiv, perm, nrhs, B, ldb);
+}
+
+// GMRES-IR: x0 = M^{-1} b; repeat { r = b - A x (FP64); stop if the
+// backward error is <= tol; solve A d = r by GMRES right-preconditioned with
+// M = L D L^T (FP64 Krylov vectors, classical Gram-Schmidt applied twice,
+// inner stop ||r - A d||_2 <= 1e-6 ||r||_2); x += d }.  Right
+// preconditioning minimises the true residual, which is what the backward
+// error measures; with a left preconditioner the M^{-1}-weighted residual
+// can meet its tolerance while the true one stalls when A is ill
+// conditioned.  Up to four right-hand sides run in lockstep, each with its
+// own Krylov space.
+int rcp_solve_ir(int64_t n, const double* A, int64_t lda, const float* L, const double* D,
+                 const int8_t* ipiv, const int64_t* perm, int64_t nrhs, const double* B,
+                 int64_t ldb, double* X, int64_t ldx, double tol, int32_t max_outer,
+                 int32_t restart, rcp_ir_result* res) {
+  if (n < 0) return -1;
+  if (n > 0 && !A) return -2;
+  if (lda < std::max<int64_t>(1, n)) return -3;
+  if (n > 0 && !L) return -4;
+  if (n > 0 && !D) return -5;
+  if (n > 0 && !ipiv) return -6;
+  if (n > 0 && !perm) return -7;
+  if (nrhs < 0) return -8;
+  if (n > 0 && nrhs > 0 && !B) return -9;
+  if (ldb < std::max<int64_t>(1, n)) return -10;
+  if (n > 0 && nrhs > 0 && !X) return -11;
+  if (ldx < std::max<int64_t>(1, n)) return -12;
+  if (!(tol > 0.0)) return -13;
+  if (max_outer < 1) return -14;
+  if (restart < 1 || restart > 64) return -15;
+  if (res) memset(res, 0, sizeof(*res));
+  if (n == 0 || nrhs == 0) return 0;
+  hipStream_t s = g_stream;
+  int dev = 0;
+  hipGetDevice(&dev);
+  const int m = restart;
+  const int NR = 4;
+  const double tol_in = 1e-6;
+  const size_t words = solve_sync_words(n);
+  const size_t nvec = (size_t)n * NR;
+  const size_t bytes = al(nvec * 8) * 5 + al((size_t)(m + 1) * nvec * 8) +
+                       al(symv_work_doubles(n, NR) * 8) + al(gmres_dot_doubles(m + 1, NR) * 8) +
+                       al((size_t)(m + 2) * NR * 8) * 3 + al((size_t)NR * (m + 1) * 8) * 3 +
+                       al((size_t)NR * m * m * 8) + al(NR * 8) * 2 + al(NR * 4) +
+                       al(gmres_state_bytes(NR)) + al(4 * 8) + al(words * 4) + al(64) + 4096;
+  if (!g_solve.reserve(bytes, dev)) return RCP_ENOMEM;
+  double* Y = g_solve.take<double>(nvec);          // solve scratch
+  double* xk = g_solve.take<double>(nvec);         // current iterate
+  double* r = g_solve.take<double>(nvec);          // residual / preconditioned residual
+  double* w = g_solve.take<double>(nvec);          // Arnoldi vector
+  double* bb = g_solve.take<double>(nvec);         // right-hand sides, ld n
+  double* V = g_solve.take<double>((size_t)(m + 1) * nvec);
+  double* swork = g_solve.take<double>(symv_work_doubles(n, NR));
+  double* part = g_solve.take<double>(gmres_dot_doubles(m + 1, NR));
+  double* h = g_solve.take<double>((size_t)(m + 2) * NR);
+  double* h2 = g_solve.take<double>((size_t)(m + 2) * NR);
+  double* hcol = g_solve.take<double>((size_t)(m + 2) * NR);
+  double* g = g_solve.take<double>((size_t)NR * (m + 1));
+  double* cs = g_solve.take<double>((size_t)NR * (m + 1));
+  double* sn = g_solve.take<double>((size_t)NR * (m + 1));
+  double* R = g_solve.take<double>((size_t)NR * m * m);
+  double* nrm = g_solve.take<double>(NR);
+  double* yls = g_solve.take<double>((size_t)NR * (m + 1));
+  int* kk = g_solve.take<int>(NR);
+  void* st = g_solve.take<char>(gmres_state_bytes(NR));
+  unsigned long long* mx = g_solve.take<unsigned long long>(4);
+  unsigned int* sync = g_solve.take<unsigned int>(words);
+  int* zp = g_solve.take<int>(16);
+  (void)yls;
+
+  const int zhost = zero_pivot(n, D, ipiv, zp, s);
+  if (zhost < 0) return zhost;
+  if (zhost != INT_MAX) return zhost;
+  hipEvent_t t0, t1;
+  hipEventCreate(&t0);
+  hipEventCreate(&t1);
+  hipEventRecord(t0, s);
+
+  // ||A||_inf (row sums of |A|)
+  unsigned long long mxh[4] = {0, 0, 0, 0};
+  RCP_CHECK(hipMemsetAsync(mx, 0, 4 * 8, s));
+  launch_symv(n, A, lda, nullptr, n, 1, 1, nullptr, n, w, n, 0, swork, s);
+  launch_absmax(n, 1, w, n, mx, s);
+  RCP_CHECK(hipMemcpyAsync(mxh, mx, 8, hipMemcpyDeviceToHost, s));
+  RCP_CHECK(hipStreamSynchronize(s));
+  double anorm;
+  memcpy(&anorm, &mxh[0], 8);
+
+  auto precond = [&](double* v, int nr) {   // v <- M^{-1} v, ld n
+    launch_solve(n, L, 1, D, ipiv, perm, nr, v, n, Y, sync, s);
+  };
+  std::vector<char> st_host(gmres_state_bytes(NR));
+  int status = 0;
+  int outer_max = 0, inner_max = 0;
+  double berr_max = 0.0;
+  for (int64_t c0 = 0; c0 < nrhs && status == 0; c0 += NR) {
+    const int nr = (int)std::min<int64_t>(NR, nrhs - c0);
+    RCP_CHECK(hipMemcpy2DAsync(bb, n * 8, B + c0 * ldb, ldb * 8, n * 8, nr,
+                               hipMemcpyDeviceToDevice, s));
+    RCP_CHECK(hipMemcpyAsync(xk, bb, (size_t)n * nr * 8, hipMemcpyDeviceToDevice, s));
+    precond(xk, nr);
+    int outer = 0, inner = 0;
+    double berr = 0.0;
+    bool done = false;
+    for (;;) {
+      // r = b - A x and the backward error of every column
+      launch_symv(n, A, lda, xk, n, nr, 0, bb, n, r, n, 1, swork, s);
+      RCP_CHECK(hipMemsetAsync(mx, 0, 4 * 8, s));
+      launch_absmax(n, nr, r, n, mx, s);
+      RCP_CHECK(hipMemcpyAsync(mxh, mx, 4 * 8, hipMemcpyDeviceToHost, s));
+      RCP_CHECK(hipStreamSynchronize(s));
+      double rn[4], xn[4];
+      for (int c = 0; c < nr; ++c) memcpy(&rn[c], &mxh[c], 8);
+      RCP_CHECK(hipMemsetAsync(mx, 0, 4 * 8, s));
+      launch_absmax(n, nr, xk, n, mx, s);
+      RCP_CHECK(hipMemcpyAsync(mxh, mx, 4 * 8, hipMemcpyDeviceToHost, s));
+      RCP_CHECK(hipStreamSynchronize(s));
+      berr = 0.0;
+      for (int c = 0; c < nr; ++c) {
+        memcpy(&xn[c], &mxh[c], 8);
+        const double den = anorm * xn[c];
+        const double be = den > 0.0 ? rn[c] / den : (rn[c] > 0.0 ? INFINITY : 0.0);
+        berr = std::max(berr, be);
+      }
+      if (berr <= tol) {
+        done = true;
+        break;
+      }
+      if (outer >= max_outer) break;
+      ++outer;
+      // one GMRES cycle on A M^{-1} y = r (right preconditioning: the true
+      // residual is the one minimised), then d = M^{-1} V y
+      launch_norm2(n, nr, r, part, nrm, s);
+      launch_gmres_start(nr, m, nrm, st, g, s);
+      launch_scale(n, nr, r, nrm, V, s);
+      for (int k = 0; k < m; ++k) {
+        const double* vk = V + (size_t)k * nr * n;
+        RCP_CHECK(hipMemcpyAsync(w, vk, (size_t)n * nr * 8, hipMemcpyDeviceToDevice, s));
+        precond(w, nr);
+        launch_symv(n, A, lda, w, n, nr, 0, nullptr, n, w, n, 0, swork, s);
+        launch_mdot(n, nr, k + 1, V, w, part, h, nullptr, s);
+        launch_mgs_sub(n, nr, k + 1, V, h, w, s);
+        launch_mdot(n, nr, k + 1, V, w, part, h2, h, s);
+        launch_mgs_sub(n, nr, k + 1, V, h2, w, s);
+        launch_norm2(n, nr, w, part, nrm, s);
+        launch_givens(nr, m, k, h, nrm, hcol, st, g, cs, sn, R, tol_in, s);
+        launch_scale(n, nr, w, nrm, V + (size_t)(k + 1) * nr * n, s);
+        RCP_CHECK(hipMemcpyAsync(st_host.data(), st, gmres_state_bytes(nr), hipMemcpyDeviceToHost,
+                                 s));
+        RCP_CHECK(hipStreamSynchronize(s));
+        bool any = false;
+        for (int c = 0; c < nr; ++c) any = any || gmres_state_active(st_host.data(), c);
+        if (!any) break;
+      }
+      int it = 0;
+      for (int c = 0; c < nr; ++c) it = std::max(it, gmres_state_iters(st_host.data(), c));
+      inner += it;
+      // w = V y, then x += M^{-1} w
+      RCP_CHECK(hipMemsetAsync(w, 0, (size_t)n * nr * 8, s));
+      launch_lsq_update(n, nr, m, st, g, R, yls, kk, V, w, n, s);
+      precond(w, nr);
+      launch_axpy(n, nr, w, xk, s);
+    }
+    RCP_CHECK(hipMemcpy2DAsync(X + c0 * ldx, ldx * 8, xk, n * 8, n * 8, nr,
+                               hipMemcpyDeviceToDevice, s));
+    RCP_CHECK(hipGetLastError());
+    outer_max = std::max(outer_max, outer);
+    inner_max = std::max(inner_max, inner);
+    berr_max = std::max(berr_max, berr);
+    if (!done) status = RCP_ENOCONV;
+  }
+  hipEventRecord(t1, s);
+  RCP_CHECK(hipStreamSynchronize(s));
+  unsigned int abort_word = 0;
+  RCP_CHECK(hipMemcpy(&abort_word, sync + (words - 1), sizeof(unsigned int), hipMemcpyDeviceToHost));
+  float ms = 0.f;
+  hipEventElapsedTime(&ms, t0, t1);
+  hipEventDestroy(t0);
+  hipEventDestroy(t1);
+  if (res) {
+    res->outer = outer_max;
+    res->inner = inner_max;
+    res->berr = berr_max;
+    res->ms = ms;
+  }
+  if (abort_word) return RCP_EDEVICE;
+  return status;
 }
 
 }  // extern "C"

@@ -1,5 +1,6 @@
-// The sketch B = Omega A (Section 3; computed once by Algorithm 1) as an
-// FP64 matrix-core product, plus the small set-up kernels of a factorization.
+// The sketch B = Omega A (Section 3; computed once by Algorithm 1) as a
+// matrix-core product (FP64, or FP32 in the reduced-precision modes), plus
+// the small set-up kernels of a factorization.
 //
 // B is kept column-major with lpad (l rounded up to 16) rows so that column
 // j of B -- the sketch of column j of A -- is one contiguous run of lpad
@@ -20,13 +21,17 @@ constexpr int kTJ = 64;    // output rows (j) per workgroup
 constexpr int kTK = 32;    // contraction chunk (i)
 constexpr int kTC = 160;   // output columns (r) per workgroup (10 fragments)
 
-__global__ void __launch_bounds__(256) sketch_partial_kernel(int64_t n, const double* __restrict__ A,
+// TA = double: FP64 matrix cores; TA = float: FP32 matrix cores (Omega is
+// rounded to FP32 as it is staged).  Partial sums are written in FP64.
+template <typename TA>
+__global__ void __launch_bounds__(256) sketch_partial_kernel(int64_t n, const TA* __restrict__ A,
                                                              int64_t ld,
                                                              const double* __restrict__ OmT,
                                                              int lpad, double* __restrict__ P,
                                                              int64_t kchunk) {
-  __shared__ double As[kTJ][kTK + 1];
-  __shared__ double Bs[kTK][kTC + 2];
+  typedef typename MfmaAcc<TA>::type Acc;
+  __shared__ TA As[kTJ][kTK + 1];
+  __shared__ TA Bs[kTK][kTC + 2];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = tid >> 6;
@@ -37,9 +42,9 @@ __global__ void __launch_bounds__(256) sketch_partial_kernel(int64_t n, const do
   const int ncols = std::min(kTC, lpad - c0);
   const int nf = ncols / 16;
 
-  rcp_d4 acc[kTC / 16];
+  Acc acc[kTC / 16];
 #pragma unroll
-  for (int f = 0; f < kTC / 16; ++f) acc[f] = rcp_d4{0.0, 0.0, 0.0, 0.0};
+  for (int f = 0; f < kTC / 16; ++f) acc[f] = Acc{0, 0, 0, 0};
 
   for (int64_t i0 = kbeg; i0 < kend; i0 += kTK) {
     // ---- stage A tile (rows j0.., cols i0..) of the symmetric matrix
@@ -55,7 +60,7 @@ __global__ void __launch_bounds__(256) sketch_partial_kernel(int64_t n, const do
         ii = e / kTJ;
       }
       const int64_t j = j0 + jj, i = i0 + ii;
-      double v = 0.0;
+      TA v = 0;
       if (j < n && i < kend) v = (j >= i) ? A[j + i * ld] : A[i + j * ld];
       As[jj][ii] = v;
     }
@@ -64,16 +69,16 @@ __global__ void __launch_bounds__(256) sketch_partial_kernel(int64_t n, const do
     for (int e = tid; e < kTK * ncols; e += 256) {
       const int ii = e / ncols, cc = e - ii * ncols;
       const int64_t i = i0 + ii;
-      Bs[ii][cc] = (i < kend) ? OmT[i * lpad + c0 + cc] : 0.0;
+      Bs[ii][cc] = (i < kend) ? (TA)OmT[i * lpad + c0 + cc] : (TA)0;
     }
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < kTK / 4; ++kk) {
-      const double a = As[16 * w + frag_row(lane)][4 * kk + frag_k(lane)];
+      const TA a = As[16 * w + frag_row(lane)][4 * kk + frag_k(lane)];
 #pragma unroll
       for (int f = 0; f < kTC / 16; ++f) {
         if (f < nf) {
-          const double b = Bs[4 * kk + frag_k(lane)][16 * f + frag_col(lane)];
+          const TA b = Bs[4 * kk + frag_k(lane)][16 * f + frag_col(lane)];
           acc[f] = mfma16x16x4(a, b, acc[f]);
         }
       }
@@ -86,8 +91,8 @@ __global__ void __launch_bounds__(256) sketch_partial_kernel(int64_t n, const do
     if (f < nf) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t j = j0 + 16 * w + acc_row(lane, v);
-        if (j < n) Pz[j * lpad + c0 + 16 * f + acc_col(lane)] = acc[f][v];
+        const int64_t j = j0 + 16 * w + MfmaAcc<TA>::row(lane, v);
+        if (j < n) Pz[j * lpad + c0 + 16 * f + acc_col(lane)] = (double)acc[f][v];
       }
     }
   }
@@ -103,11 +108,12 @@ __global__ void sketch_reduce_kernel(int64_t total, int ksplit, int64_t stride,
   }
 }
 
+template <typename TA>
 __global__ void copy_lower_kernel(int64_t n, const double* __restrict__ A, int64_t lda,
-                                  double* __restrict__ Acur) {
+                                  TA* __restrict__ Acur) {
   // one workgroup per column, rows j..n-1
   for (int64_t j = blockIdx.x; j < n; j += gridDim.x) {
-    for (int64_t i = j + threadIdx.x; i < n; i += blockDim.x) Acur[i + j * n] = A[i + j * lda];
+    for (int64_t i = j + threadIdx.x; i < n; i += blockDim.x) Acur[i + j * n] = (TA)A[i + j * lda];
   }
 }
 
@@ -137,21 +143,30 @@ unsigned grid1d(int64_t total, int threads = 256, int64_t cap = 65536) {
 
 }  // namespace
 
-void launch_copy_lower(int64_t n, const double* A, int64_t lda, double* Acur, hipStream_t s) {
+void launch_copy_lower(int64_t n, const double* A, int64_t lda, void* Acur, int prec,
+                       hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(copy_lower_kernel, dim3((unsigned)std::min<int64_t>(n, 65536)), dim3(256),
-                     0, s, n, A, lda, Acur);
+  const dim3 grid((unsigned)std::min<int64_t>(n, 65536));
+  if (prec == kPrecF64)
+    hipLaunchKernelGGL(copy_lower_kernel<double>, grid, dim3(256), 0, s, n, A, lda,
+                       (double*)Acur);
+  else
+    hipLaunchKernelGGL(copy_lower_kernel<float>, grid, dim3(256), 0, s, n, A, lda, (float*)Acur);
 }
 
-void launch_sketch(int64_t n, const double* Acur, int64_t ld, const double* OmT, int lpad,
-                   double* B, double* partial, int ksplit, hipStream_t s) {
+void launch_sketch(int64_t n, const void* Acur, int prec, int64_t ld, const double* OmT,
+                   int lpad, double* B, double* partial, int ksplit, hipStream_t s) {
   if (n <= 0) return;
   int64_t kchunk = (n + ksplit - 1) / ksplit;
   kchunk = (kchunk + kTK - 1) / kTK * kTK;
   const int ks = (int)((n + kchunk - 1) / kchunk);
   dim3 grid((unsigned)((n + kTJ - 1) / kTJ), (unsigned)ks, (unsigned)((lpad + kTC - 1) / kTC));
-  hipLaunchKernelGGL(sketch_partial_kernel, grid, dim3(256), 0, s, n, Acur, ld, OmT, lpad,
-                     ks == 1 ? B : partial, kchunk);
+  if (prec == kPrecF64)
+    hipLaunchKernelGGL(sketch_partial_kernel<double>, grid, dim3(256), 0, s, n,
+                       (const double*)Acur, ld, OmT, lpad, ks == 1 ? B : partial, kchunk);
+  else
+    hipLaunchKernelGGL(sketch_partial_kernel<float>, grid, dim3(256), 0, s, n, (const float*)Acur,
+                       ld, OmT, lpad, ks == 1 ? B : partial, kchunk);
   if (ks > 1) {
     const int64_t total = n * lpad;
     hipLaunchKernelGGL(sketch_reduce_kernel, dim3(grid1d(total)), dim3(256), 0, s, total, ks,

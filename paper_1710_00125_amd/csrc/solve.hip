@@ -25,11 +25,12 @@ constexpr int kMaxRhs = 8;
 // L(i, c) for the final order: row i of L is row P[i] (original index) of
 // Lwork, whose column c holds the multiplier of the pivot at position c.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) finalize_L_kernel(int64_t n, const double* __restrict__ Lwork,
+template <typename TL>
+__global__ void __launch_bounds__(256) finalize_L_kernel(int64_t n, const TL* __restrict__ Lwork,
                                                         const int64_t* __restrict__ P,
                                                         const int8_t* __restrict__ ipiv,
-                                                        double* __restrict__ L) {
-  __shared__ double tile[kBlk][kBlk + 1];
+                                                        TL* __restrict__ L) {
+  __shared__ TL tile[kBlk][kBlk + 1];
   const int64_t nb = (n + kBlk - 1) / kBlk;
   const int64_t I = blockIdx.x % nb, C = blockIdx.x / nb;   // row tile, column tile
   const int64_t i0 = I * kBlk, c0 = C * kBlk;
@@ -39,7 +40,7 @@ __global__ void __launch_bounds__(256) finalize_L_kernel(int64_t n, const double
     for (int e = tid; e < kBlk * kBlk; e += 256) {
       const int ii = e / kBlk, cc = e % kBlk;
       const int64_t i = i0 + ii, c = c0 + cc;
-      double v = 0.0;
+      TL v = 0;
       if (i < n && c < n && c < i) v = Lwork[P[i] * n + c];
       tile[ii][cc] = v;
     }
@@ -49,10 +50,10 @@ __global__ void __launch_bounds__(256) finalize_L_kernel(int64_t n, const double
     const int ii = e % kBlk, cc = e / kBlk;
     const int64_t i = i0 + ii, c = c0 + cc;
     if (i >= n || c >= n) continue;
-    double v;
-    if (c > i) v = 0.0;
-    else if (c == i) v = 1.0;
-    else if (i == c + 1 && ipiv[c] == 2) v = 0.0;
+    TL v;
+    if (c > i) v = 0;
+    else if (c == i) v = 1;
+    else if (i == c + 1 && ipiv[c] == 2) v = 0;
     else v = tile[ii][cc];
     L[i + c * n] = v;
   }
@@ -136,8 +137,9 @@ __device__ __forceinline__ double bcast_lane(double v, int lane) {
 // sync[0] = ticket counter, sync[1 + k] = done flag of block k, sync[1 + nb]
 // = abort word (raised by a wait that timed out).  A block's finished values
 // are published with agent-scope stores, then its flag.
+template <typename TL>
 __global__ void __launch_bounds__(256) trsv_chain_kernel(int64_t n, int nrhs,
-                                                        const double* __restrict__ L,
+                                                        const TL* __restrict__ L,
                                                         double* __restrict__ Y,
                                                         unsigned int* sync, int lower) {
   extern __shared__ double smem[];
@@ -165,7 +167,7 @@ __global__ void __launch_bounds__(256) trsv_chain_kernel(int64_t n, int nrhs,
   // the diagonal tile and my right-hand sides do not depend on anyone
   for (int e = tid; e < kBlk * kBlk; e += 256) {
     const int rr = e & 63, cc = e >> 6;
-    Ld[cc][rr] = (rr < kn && cc < kn) ? L[(k0 + rr) + (k0 + cc) * n] : 0.0;
+    Ld[cc][rr] = (rr < kn && cc < kn) ? (double)L[(k0 + rr) + (k0 + cc) * n] : 0.0;
   }
   double yown[kMaxRhs];
   if (tid < 64)
@@ -182,7 +184,7 @@ __global__ void __launch_bounds__(256) trsv_chain_kernel(int64_t n, int nrhs,
     const int rn = lower ? kn : jn, cn = lower ? jn : kn;
     for (int e = tid; e < kBlk * kBlk; e += 256) {
       const int rr = e & 63, cc = e >> 6;
-      Ls[cc][rr] = (rr < rn && cc < cn) ? L[(rbase + rr) + (cbase + cc) * n] : 0.0;
+      Ls[cc][rr] = (rr < rn && cc < cn) ? (double)L[(rbase + rr) + (cbase + cc) * n] : 0.0;
     }
     wait_flag(&sync[1 + J], &sync[1 + nb]);
     for (int e = tid; e < nrhs * kBlk; e += 256) {
@@ -245,12 +247,17 @@ unsigned grid1d(int64_t total) {
 
 }  // namespace
 
-void launch_finalize_L(int64_t n, const double* Lwork, const int64_t* P, const int8_t* ipiv,
-                       double* L, hipStream_t s) {
+void launch_finalize_L(int64_t n, const void* Lwork, const int64_t* P, const int8_t* ipiv,
+                       void* L, int l_f32, hipStream_t s) {
   if (n <= 0) return;
   const int64_t nb = (n + kBlk - 1) / kBlk;
-  hipLaunchKernelGGL(finalize_L_kernel, dim3((unsigned)(nb * nb)), dim3(256), 0, s, n, Lwork, P,
-                     ipiv, L);
+  const dim3 grid((unsigned)(nb * nb));
+  if (l_f32)
+    hipLaunchKernelGGL(finalize_L_kernel<float>, grid, dim3(256), 0, s, n, (const float*)Lwork, P,
+                       ipiv, (float*)L);
+  else
+    hipLaunchKernelGGL(finalize_L_kernel<double>, grid, dim3(256), 0, s, n, (const double*)Lwork,
+                       P, ipiv, (double*)L);
 }
 
 void launch_find_zero_pivot(int64_t n, const double* D, const int8_t* ipiv, int* out,
@@ -261,25 +268,32 @@ void launch_find_zero_pivot(int64_t n, const double* D, const int8_t* ipiv, int*
 
 size_t solve_sync_words(int64_t n) { return (size_t)(2 + (n + kBlk - 1) / kBlk); }
 
-void launch_solve(int64_t n, const double* L, const double* D, const int8_t* ipiv,
+void launch_solve(int64_t n, const void* L, int l_f32, const double* D, const int8_t* ipiv,
                   const int64_t* perm, int64_t nrhs, double* B, int64_t ldb, double* Y,
                   unsigned int* sync, hipStream_t s) {
   if (n <= 0 || nrhs <= 0) return;
   const int64_t nb = (n + kBlk - 1) / kBlk;
-  hipFuncSetAttribute((const void*)trsv_chain_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)trsv_lds());
+  const void* kern = l_f32 ? (const void*)trsv_chain_kernel<float>
+                           : (const void*)trsv_chain_kernel<double>;
+  hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)trsv_lds());
+  auto trsv = [&](int lower, int nr) {
+    if (l_f32)
+      hipLaunchKernelGGL(trsv_chain_kernel<float>, dim3((unsigned)nb), dim3(256), trsv_lds(), s, n,
+                         nr, (const float*)L, Y, sync, lower);
+    else
+      hipLaunchKernelGGL(trsv_chain_kernel<double>, dim3((unsigned)nb), dim3(256), trsv_lds(), s,
+                         n, nr, (const double*)L, Y, sync, lower);
+  };
   for (int64_t c0 = 0; c0 < nrhs; c0 += kMaxRhs) {
     const int nr = (int)std::min<int64_t>(kMaxRhs, nrhs - c0);
     double* Bc = B + c0 * ldb;
     hipLaunchKernelGGL(gather_rows_kernel, dim3(grid1d(n * nr)), dim3(256), 0, s, n, nr, perm, Bc,
                        ldb, Y);
     hipMemsetAsync(sync, 0, solve_sync_words(n) * sizeof(unsigned int), s);
-    hipLaunchKernelGGL(trsv_chain_kernel, dim3((unsigned)nb), dim3(256), trsv_lds(), s, n, nr, L,
-                       Y, sync, 1);
+    trsv(1, nr);
     hipLaunchKernelGGL(dsolve_kernel, dim3(grid1d(n * nr)), dim3(256), 0, s, n, nr, D, ipiv, Y);
     hipMemsetAsync(sync, 0, solve_sync_words(n) * sizeof(unsigned int), s);
-    hipLaunchKernelGGL(trsv_chain_kernel, dim3((unsigned)nb), dim3(256), trsv_lds(), s, n, nr, L,
-                       Y, sync, 0);
+    trsv(0, nr);
     hipLaunchKernelGGL(scatter_rows_kernel, dim3(grid1d(n * nr)), dim3(256), 0, s, n, nr, perm, Y,
                        Bc, ldb);
   }

@@ -1,7 +1,8 @@
 // rcp_update: the delayed Schur complement update of Algorithm 1,
 //     A22 <- A22 - L21 D1 L21^T = A22 - L21 W21^T,
 // on the lower triangle only (n^3/3 flops over the whole factorization,
-// Section 3.2), in FP64 on the matrix cores.
+// Section 3.2), on the matrix cores: FP64, FP32, or FP32 accumulation of
+// three BF16 products of the split operands.
 //
 // The block's interchanges are applied on the fly: the kernel reads the
 // block-start matrix Acur at the source of each position (rowsrc) and writes
@@ -36,12 +37,62 @@ __device__ __forceinline__ void tile_of(int64_t id, int& I, int& J) {
   J = (int)(id - i * (i + 1) / 2);
 }
 
-__global__ void __launch_bounds__(256, 2) update_kernel(const double* __restrict__ Acur,
-                                                        double* __restrict__ Anext, int64_t ld,
-                                                        const int* __restrict__ rowsrc, int N2,
-                                                        const double* __restrict__ L21p,
-                                                        const double* __restrict__ W21p, int Qk,
-                                                        int64_t ntiles) {
+// Operand packings (one fragment = one 16-row group at one k step):
+//   F64:    64 doubles per fragment, K = 4 per step
+//   F32:    64 floats per fragment, K = 4 per step
+//   BF16x3: 64 x 8 BF16 hi values then 64 x 8 lo values, K = 32 per step,
+//           three products per step: lo*hi + hi*lo + hi*hi
+struct PackF64 {
+  typedef double TA;
+  typedef double Frag;
+  typedef rcp_d4 Acc;
+  static constexpr int kFragElems = 64;
+  static __device__ __forceinline__ Frag load(const Frag* p) { return *p; }
+  static __device__ __forceinline__ Acc mma(Frag a, Frag b, Acc c) { return mfma16x16x4(a, b, c); }
+};
+struct PackF32 {
+  typedef float TA;
+  typedef float Frag;
+  typedef rcp_f4 Acc;
+  static constexpr int kFragElems = 64;
+  static __device__ __forceinline__ Frag load(const Frag* p) { return *p; }
+  static __device__ __forceinline__ Acc mma(Frag a, Frag b, Acc c) { return mfma16x16x4(a, b, c); }
+};
+struct Bf16Pair {
+  rcp_bf8 hi, lo;
+};
+struct PackBF16x3 {
+  typedef float TA;
+  typedef Bf16Pair Frag;
+  typedef rcp_f4 Acc;
+  static constexpr int kFragElems = 128;   // in units of rcp_bf8
+  static __device__ __forceinline__ Frag load(const rcp_bf8* p) { return Frag{p[0], p[64]}; }
+  static __device__ __forceinline__ Acc mma(const Frag& a, const Frag& b, Acc c) {
+    c = mfma16x16x32(a.lo, b.hi, c);
+    c = mfma16x16x32(a.hi, b.lo, c);
+    return mfma16x16x32(a.hi, b.hi, c);
+  }
+};
+template <typename P>
+struct PackElem {
+  typedef typename P::Frag type;
+};
+template <>
+struct PackElem<PackBF16x3> {
+  typedef rcp_bf8 type;
+};
+
+template <typename P>
+__global__ void __launch_bounds__(256, 2) update_kernel(const typename P::TA* __restrict__ Acur,
+                                                        typename P::TA* __restrict__ Anext,
+                                                        int64_t ld, const int* __restrict__ rowsrc,
+                                                        int N2,
+                                                        const typename PackElem<P>::type* __restrict__ L21p,
+                                                        const typename PackElem<P>::type* __restrict__ W21p,
+                                                        int Qk, int64_t ntiles) {
+  typedef typename P::TA TA;
+  typedef typename P::Frag Frag;
+  typedef typename P::Acc Acc;
   // XCD-aware numbering: hardware block b runs on XCD b % 8
   const int64_t b = blockIdx.x;
   const int64_t per = (ntiles + kXcd - 1) / kXcd;
@@ -58,34 +109,35 @@ __global__ void __launch_bounds__(256, 2) update_kernel(const double* __restrict
   if (r0 >= N2 || c0 >= N2) return;
 
   const int g0 = r0 / 16, h0 = c0 / 16;
-  const double* pa = L21p + ((int64_t)g0 * Qk) * 64 + lane;
-  const double* pb = W21p + ((int64_t)h0 * Qk) * 64 + lane;
-  const int64_t gstride = (int64_t)Qk * 64;
+  constexpr int FE = P::kFragElems;
+  const auto* pa = L21p + ((int64_t)g0 * Qk) * FE + lane;
+  const auto* pb = W21p + ((int64_t)h0 * Qk) * FE + lane;
+  const int64_t gstride = (int64_t)Qk * FE;
 
-  rcp_d4 acc[4][4];
+  Acc acc[4][4];
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) acc[x][y] = rcp_d4{0.0, 0.0, 0.0, 0.0};
+    for (int y = 0; y < 4; ++y) acc[x][y] = Acc{0, 0, 0, 0};
 
-  double a_cur[4], b_cur[4], a_nxt[4], b_nxt[4];
+  Frag a_cur[4], b_cur[4], a_nxt[4], b_nxt[4];
 #pragma unroll
   for (int x = 0; x < 4; ++x) {
-    a_cur[x] = pa[x * gstride];
-    b_cur[x] = pb[x * gstride];
+    a_cur[x] = P::load(pa + x * gstride);
+    b_cur[x] = P::load(pb + x * gstride);
   }
   for (int q = 0; q < Qk; ++q) {
     if (q + 1 < Qk) {
 #pragma unroll
       for (int x = 0; x < 4; ++x) {
-        a_nxt[x] = pa[x * gstride + (q + 1) * 64];
-        b_nxt[x] = pb[x * gstride + (q + 1) * 64];
+        a_nxt[x] = P::load(pa + x * gstride + (q + 1) * FE);
+        b_nxt[x] = P::load(pb + x * gstride + (q + 1) * FE);
       }
     }
 #pragma unroll
     for (int x = 0; x < 4; ++x)
 #pragma unroll
-      for (int y = 0; y < 4; ++y) acc[x][y] = mfma16x16x4(b_cur[y], a_cur[x], acc[x][y]);
+      for (int y = 0; y < 4; ++y) acc[x][y] = P::mma(b_cur[y], a_cur[x], acc[x][y]);
 #pragma unroll
     for (int x = 0; x < 4; ++x) {
       a_cur[x] = a_nxt[x];
@@ -94,9 +146,9 @@ __global__ void __launch_bounds__(256, 2) update_kernel(const double* __restrict
   }
 
   // acc[x][y] holds the 16 x 16 block (j, i) = (W L^T)(c0 + 16y.., r0 + 16x..):
-  // lane l, element v is column j = c0 + 16y + l/16 + 4v, row i = r0 + 16x + l%16,
-  // so 16 consecutive lanes cover 16 consecutive rows of one column.
-  // C = Acur(rowsrc(i), rowsrc(j)) - acc, written to Anext(i, j)
+  // lane l, element v is column j = c0 + 16y + MfmaAcc<TA>::row(l, v), row
+  // i = r0 + 16x + l%16, so 16 consecutive lanes cover 16 consecutive rows of
+  // one column.  C = Acur(rowsrc(i), rowsrc(j)) - acc, written to Anext(i, j)
 #pragma unroll
   for (int x = 0; x < 4; ++x) {
     const int i = r0 + 16 * x + acc_col(lane);
@@ -106,10 +158,10 @@ __global__ void __launch_bounds__(256, 2) update_kernel(const double* __restrict
     for (int y = 0; y < 4; ++y) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int j = c0 + 16 * y + acc_row(lane, v);
+        const int j = c0 + 16 * y + MfmaAcc<TA>::row(lane, v);
         if (j < N2) {
           const int64_t sj = rowsrc[j];
-          const double a = (si >= sj) ? Acur[si + sj * ld] : Acur[sj + si * ld];
+          const TA a = (si >= sj) ? Acur[si + sj * ld] : Acur[sj + si * ld];
           Anext[i + (int64_t)j * ld] = a - acc[x][y][v];
         }
       }
@@ -119,14 +171,25 @@ __global__ void __launch_bounds__(256, 2) update_kernel(const double* __restrict
 
 }  // namespace
 
-void launch_update(const double* Acur, double* Anext, int64_t ld, const int* rowsrc, int N2,
-                   const double* L21p, const double* W21p, int Qk, hipStream_t s) {
+void launch_update(const void* Acur, void* Anext, int64_t ld, const int* rowsrc, int N2,
+                   const void* L21p, const void* W21p, int Qk, int prec, hipStream_t s) {
   if (N2 <= 0) return;
   const int64_t T = (N2 + kTile - 1) / kTile;
   const int64_t ntiles = T * (T + 1) / 2;
   const int64_t per = (ntiles + kXcd - 1) / kXcd;
-  hipLaunchKernelGGL(update_kernel, dim3((unsigned)(per * kXcd)), dim3(256), 0, s, Acur, Anext,
-                     ld, rowsrc, N2, L21p, W21p, Qk, ntiles);
+  const dim3 grid((unsigned)(per * kXcd));
+  if (prec == kPrecF64)
+    hipLaunchKernelGGL(update_kernel<PackF64>, grid, dim3(256), 0, s, (const double*)Acur,
+                       (double*)Anext, ld, rowsrc, N2, (const double*)L21p, (const double*)W21p,
+                       Qk, ntiles);
+  else if (prec == kPrecF32)
+    hipLaunchKernelGGL(update_kernel<PackF32>, grid, dim3(256), 0, s, (const float*)Acur,
+                       (float*)Anext, ld, rowsrc, N2, (const float*)L21p, (const float*)W21p, Qk,
+                       ntiles);
+  else
+    hipLaunchKernelGGL(update_kernel<PackBF16x3>, grid, dim3(256), 0, s, (const float*)Acur,
+                       (float*)Anext, ld, rowsrc, N2, (const rcp_bf8*)L21p, (const rcp_bf8*)W21p,
+                       Qk, ntiles);
 }
 
 }  // namespace rcp

@@ -60,3 +60,31 @@ def test_argument_errors_without_gpu():
     assert lib.rcp_omega(0, -1, 4, null) == -2
     assert lib.rcp_omega(0, 2, -4, null) == -3
     assert lib.rcp_omega(0, 2, 4, null) == -4
+
+
+def test_mixed_precision_argument_errors_without_gpu():
+    import paper_1710_00125_amd as pkg
+    if not os.path.exists(pkg.lib_path()):
+        pytest.skip("librcp.so not built")
+    lib = pkg.load()
+    null = ctypes.c_void_p(0)
+    one = ctypes.c_void_p(8)
+    f = lib.rcp_factor_mp
+    assert f(-1, null, 1, 4, 2, 0, 1, null, null, null, null) == -1
+    assert f(4, one, 3, 4, 2, 0, 1, one, one, one, one) == -3
+    assert f(4, one, 4, 4, 2, 0, 0, one, one, one, one) == -7
+    assert f(4, one, 4, 4, 2, 0, 3, one, one, one, one) == -7
+    assert f(4, one, 4, 4, 2, 0, 2, null, one, one, one) == -8
+    assert f(4, one, 4, 4, 2, 0, 2, one, one, one, null) == -11
+    assert f(0, null, 1, 4, 2, 0, 1, null, null, null, null) == 0
+    assert lib.rcp_solve_mp(4, one, one, one, one, 1, one, 3) == -8
+    ir = lib.rcp_solve_ir
+    args = [4, one, 4, one, one, one, one, 1, one, 4, one, 4, 1e-13, 5, 20, None]
+    for pos, val, code in [(0, -1, -1), (2, 3, -3), (7, -1, -8), (9, 3, -10), (11, 3, -12),
+                           (12, 0.0, -13), (13, 0, -14), (14, 0, -15), (14, 65, -15)]:
+        a = list(args)
+        a[pos] = val
+        assert ir(*a) == code, (pos, val)
+    a = list(args)
+    a[0] = 0
+    assert ir(*a) == 0
