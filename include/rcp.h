@@ -166,6 +166,63 @@ int rcp_solve_ir(int64_t n, const double* A, int64_t lda, const float* L, const 
                  int64_t ldb, double* X, int64_t ldx, double tol, int32_t max_outer,
                  int32_t restart, rcp_ir_result* res);
 
+/* ---- Batched systems ---------------------------------------------------
+ * Many independent small systems (1 <= n <= 512) factored and solved in one
+ * launch, one workgroup per system, each by the method of rcp_factor (the
+ * same Algorithm 1 with q = b, the same Omega for the same seed) followed by
+ * the solve; in the FP32 form the working matrix and L are FP32 and an FP64
+ * refinement loop (r = b - A x, x += M^{-1} r, at most 10 steps, stop at
+ * backward error 1e-13) follows the first solve.
+ *
+ * Pools: system i has order n[i]; with N2(i) = sum_{j<i} n[j]^2 and
+ * N1(i) = sum_{j<i} n[j], its matrix is Apool + N2(i) (column-major, ld
+ * n[i], lower triangle read), its right-hand sides Bpool + N1(i) nrhs and
+ * solutions Xpool + N1(i) nrhs (column-major n[i] x nrhs, ld n[i]), and the
+ * optional factor outputs perm + N1(i) (int64), L + N2(i) (double, or float
+ * in the FP32 form), D + 2 N1(i) (double[2 n]), ipiv + N1(i) (int8), laid
+ * out as in rcp_factor.  System i uses seed seed0 + i and block size
+ * b = the autotuned table entry of its size class (n <= 64, 128, 256, 512);
+ * l = b + p. */
+typedef struct rcp_batch rcp_batch;   /* opaque plan */
+
+typedef struct rcp_batch_info {
+  int32_t b;          /* block size the system was factored with            */
+  int32_t info;       /* 0, or +k: exactly zero 1x1 pivot at k (X unwritten) */
+  int32_t ir_iters;   /* refinement steps taken (FP32 form)                  */
+  int32_t n2x2;       /* number of 2x2 pivots                                */
+  double  berr;       /* ||b - A x||_inf / (||A||_inf ||x||_inf), max over RHS */
+} rcp_batch_info;
+
+/* Build a plan: upload descriptors, allocate the workspace and capture the
+ * launch in a hipGraph on a stream of the plan's own.  autotune = 1 first
+ * times b in {8, 16, 24, 32} on up to 64 of the batch's systems of each size
+ * class (the kernel only reads Apool/Bpool and writes Xpool) and keeps the
+ * fastest in the table used from then on.
+ *   count >= 0 systems, n: HOST int32[count]; p >= 0 with 32 + p <= 64;
+ *   precision 0 (FP64) or RCP_PREC_FP32; nrhs 1..4; Apool, Bpool, Xpool
+ *   device pools; perm, L, D, ipiv device pools or NULL; *out receives the
+ *   plan.  The pools must stay valid while the plan is used.
+ * Returns 0, -i for a bad argument i, RCP_EDEVICE or RCP_ENOMEM. */
+int rcp_batch_create(int64_t count, const int32_t* n, int32_t p, uint64_t seed0,
+                     int32_t precision, int32_t nrhs, const double* Apool,
+                     const double* Bpool, double* Xpool, int64_t* perm, void* L,
+                     double* D, int8_t* ipiv, int32_t autotune, rcp_batch** out);
+
+/* Replay the plan's graph once and wait for it; *ms (may be NULL) receives
+ * its duration from events around the graph launch.  Returns 0 or an error. */
+int rcp_batch_run(rcp_batch* plan, float* ms);
+
+/* Per-system results of the last run, in system order (HOST array of
+ * count entries).  Returns 0, -1 (NULL plan) or -2 (NULL info). */
+int rcp_batch_get_info(const rcp_batch* plan, rcp_batch_info* info);
+
+/* Free the plan.  Returns 0. */
+int rcp_batch_destroy(rcp_batch* plan);
+
+/* Current block size per size class (n <= 64, 128, 256, 512) for
+ * precision 0 or RCP_PREC_FP32 (HOST int32[4]).  Returns 0, -1 or -2. */
+int rcp_batch_get_table(int32_t precision, int32_t* b_by_class);
+
 #ifdef __cplusplus
 }
 #endif

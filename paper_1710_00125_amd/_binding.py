@@ -38,6 +38,11 @@ class _IrResult(ctypes.Structure):
                 ("ms", ctypes.c_double)]
 
 
+class _BatchInfo(ctypes.Structure):
+    _fields_ = [("b", ctypes.c_int32), ("info", ctypes.c_int32), ("ir_iters", ctypes.c_int32),
+                ("n2x2", ctypes.c_int32), ("berr", ctypes.c_double)]
+
+
 _SIGS = {
     "rcp_set_stream": (ctypes.c_int, [ctypes.c_void_p]),
     "rcp_set_profiling": (ctypes.c_int, [ctypes.c_int32]),
@@ -65,6 +70,16 @@ _SIGS = {
                                     ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
                                     ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.POINTER(_IrResult)]),
+    "rcp_batch_create": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32,
+                                        ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "rcp_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]),
+    "rcp_batch_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_BatchInfo)]),
+    "rcp_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "rcp_batch_get_table": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
 }
 
 
@@ -256,3 +271,87 @@ def rcp_solve_ir(A, f, B, tol=1e-13, max_outer=10, restart=30, raise_on_noconv=T
         _check("rcp_solve_ir", code)
     X = Xcm.t()
     return (X[:, 0] if vec else X), info
+
+
+# ---------------------------------------------------------------------------
+# batched systems
+
+
+def pack_batch(systems, nrhs, device="cuda"):
+    """Pools for rcp_batch_create from a list of (A (n x n), B (n x nrhs))
+    host arrays: column-major blocks laid end to end (see include/rcp.h)."""
+    import numpy as np
+    torch = _torch()
+    ns = np.array([A.shape[0] for A, _ in systems], dtype=np.int32)
+    a = np.concatenate([np.asarray(A, dtype=np.float64).T.ravel() for A, _ in systems])
+    b = np.concatenate([np.asarray(B, dtype=np.float64).reshape(A.shape[0], nrhs).T.ravel()
+                        for A, B in systems])
+    return (ns, torch.from_numpy(a).to(device), torch.from_numpy(b).to(device))
+
+
+class Batch:
+    """A captured batch plan (rcp_batch_create); run() replays its graph."""
+
+    def __init__(self, ns, Apool, Bpool, p, seed0, precision=0, nrhs=1, factors=False,
+                 autotune=True):
+        import numpy as np
+        torch = _torch()
+        self.ns = np.ascontiguousarray(ns, dtype=np.int32)
+        self.count = len(self.ns)
+        self.nrhs = nrhs
+        self.precision = int(precision)
+        dev = Apool.device
+        n1 = int(self.ns.sum())
+        self.Apool, self.Bpool = Apool, Bpool
+        self.Xpool = torch.zeros(n1 * nrhs, dtype=torch.float64, device=dev)
+        self.perm = self.L = self.D = self.ipiv = None
+        if factors:
+            n2 = int((self.ns.astype(np.int64) ** 2).sum())
+            self.perm = torch.empty(n1, dtype=torch.int64, device=dev)
+            self.L = torch.empty(n2, dtype=torch.float32 if precision else torch.float64,
+                                 device=dev)
+            self.D = torch.empty(2 * n1, dtype=torch.float64, device=dev)
+            self.ipiv = torch.empty(n1, dtype=torch.int8, device=dev)
+        torch.cuda.synchronize()
+        h = ctypes.c_void_p()
+        code = load().rcp_batch_create(
+            self.count, self.ns.ctypes.data_as(ctypes.c_void_p), int(p),
+            ctypes.c_uint64(int(seed0) & (2**64 - 1)), int(precision), int(nrhs),
+            _ptr(Apool), _ptr(Bpool), _ptr(self.Xpool), _ptr(self.perm), _ptr(self.L),
+            _ptr(self.D), _ptr(self.ipiv), 1 if autotune else 0, ctypes.byref(h))
+        _check("rcp_batch_create", code)
+        self._h = h
+
+    def run(self):
+        """Replay the captured launch once; returns its duration in ms."""
+        ms = ctypes.c_float()
+        _check("rcp_batch_run", load().rcp_batch_run(self._h, ctypes.byref(ms)))
+        return ms.value
+
+    def info(self):
+        arr = (_BatchInfo * max(1, self.count))()
+        _check("rcp_batch_get_info", load().rcp_batch_get_info(self._h, arr))
+        return [{"b": r.b, "info": r.info, "ir_iters": r.ir_iters, "n2x2": r.n2x2,
+                 "berr": r.berr} for r in arr[:self.count]]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().rcp_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def rcp_batch_create(ns, Apool, Bpool, p, seed0, precision=0, nrhs=1, factors=False,
+                     autotune=True):
+    return Batch(ns, Apool, Bpool, p, seed0, precision, nrhs, factors, autotune)
+
+
+def rcp_batch_get_table(precision=0):
+    arr = (ctypes.c_int32 * 4)()
+    _check("rcp_batch_get_table", load().rcp_batch_get_table(int(precision), arr))
+    return list(arr)

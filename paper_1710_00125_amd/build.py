@@ -14,7 +14,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librcp.so")
 
 SOURCES = ["omega.hip", "sketch.hip", "select.hip", "panel.hip", "blockops.hip", "update.hip",
-           "solve.hip", "refine.hip", "rcp_api.cpp"]
+           "solve.hip", "refine.hip", "batched.hip", "rcp_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -1,0 +1,744 @@
+// Batched RCP: many independent small systems (n <= 512) factored and solved
+// in one launch, one workgroup per system, every step of Algorithm 1
+// (q = b) inside the workgroup:
+//   sketch B = Omega A; per block: partial QRCP of the sketch (b steps),
+//   SBKP eliminations (Figure 2) with the trailing update delayed to the
+//   block end, the sketch update (eq. (3.3) in block form), the rank-m
+//   trailing update; then X = P^T L^{-T} D^{-1} L^{-1} P B.
+// In the FP32 form the working matrix and L are FP32 (pivot tests, D and
+// the 2x2 inverses stay FP64) and a classic FP64 refinement loop
+// (r = b - A x in FP64, x += solve(r)) follows the first solve.
+//
+// Unlike the single-system path, interchanges are applied physically: the
+// workgroup owns all of a system's data, and a swap of two positions costs
+// O(n) element moves inside the workgroup.  All arrays of a system live in
+// its slice of a workspace pool (L2 / MALL resident at these sizes); small
+// per-step vectors live in LDS.
+#include <climits>
+
+#include "common.h"
+#include "kernels.h"
+#include "omega_dev.h"
+
+namespace rcp {
+namespace {
+
+constexpr int kBT = 256;            // threads per system
+constexpr int kBMaxN = kBatchMaxN;  // largest system
+constexpr int kBMaxL = kBatchMaxL;  // largest l = b + p
+constexpr int kBMaxB = kBatchMaxB;  // largest block size
+constexpr int kBldp = kBMaxB + 2;   // row stride of the block L rows (b + 1 used)
+
+struct KernelArgs {
+  const BatchSys* sys;
+  const int* order;
+  const double* Apool;
+  const double* Bpool;
+  double* Xpool;
+  int nrhs;
+  char* work;
+  int64_t* perm_out;
+  void* L_out;
+  double* D_out;
+  int8_t* ipiv_out;
+  BatchStatus* status;
+  int ir_max;
+  double ir_tol;
+};
+
+// ---------------------------------------------------------------------------
+// workgroup-wide helpers
+// ---------------------------------------------------------------------------
+struct Shared {
+  double wrow[kBldp];        // W row of the pivot
+  double wrow2[kBldp];       // W row of the second pivot / of r
+  double v[kBMaxL];          // Householder vector
+  double red_v[4];
+  int red_p[4];
+  double sc[8];
+  int info;                  // first exactly zero 1x1 pivot (1-based), INT_MAX if none
+  int n2x2;
+  union {                    // phase-specific buffers
+    struct {
+      double colv[kBMaxN];   // current column (position s - k)
+      double colv2[kBMaxN];  // second column of a 2x2 pivot
+    } p;
+    double T[kBMaxL][kBldp];   // sketch update factor B~_1 L11^{-T}
+    struct {
+      double ta[64][kBMaxB + 1];   // trailing-update tiles: L21 rows
+      double tb[64][kBMaxB + 1];   //                        W21 rows
+    } u;
+    struct {
+      double yb[4][64];          // one block of the right-hand sides
+      double part[4][4][64];     // partial column sums
+    } s;
+  };
+};
+
+__device__ __forceinline__ bool key_gt(double av, int ap, double bv, int bp) {
+  return av > bv || (av == bv && ap < bp);
+}
+
+// largest value, ties to the smaller position; result in every thread
+__device__ void wg_argmax(double& val, int& pos, Shared& sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(val, off, 64);
+    const int op = __shfl_xor(pos, off, 64);
+    if (key_gt(ov, op, val, pos)) {
+      val = ov;
+      pos = op;
+    }
+  }
+  if (lane == 0) {
+    sh.red_v[w] = val;
+    sh.red_p[w] = pos;
+  }
+  __syncthreads();
+  val = sh.red_v[0];
+  pos = sh.red_p[0];
+  for (int i = 1; i < 4; ++i)
+    if (key_gt(sh.red_v[i], sh.red_p[i], val, pos)) {
+      val = sh.red_v[i];
+      pos = sh.red_p[i];
+    }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ void swp(T& a, T& b) {
+  const T t = a;
+  a = b;
+  b = t;
+}
+
+template <typename TA>
+__device__ __forceinline__ double symw(const TA* W, int n, int i, int j) {
+  return (double)((i >= j) ? W[i + (int64_t)j * n] : W[j + (int64_t)i * n]);
+}
+
+template <typename TA>
+struct Sys {
+  int n, b, l, K0;
+  bool r_live;
+  TA* W;          // working matrix (lower; the upper triangle holds A until the sketch)
+  TA* Lw;         // final L, column-major
+  double* B;      // sketch, column j at B + j l
+  double* R;      // QRCP residual (columns >= K0)
+  double* Lp;     // L rows of the current block, row s at Lp + s kBldp
+  double* Wp;     // W = L D rows of the current block
+  double* Om;     // Omega, row-major l x n
+  double* y;      // solve vectors (n x nrhs)
+  double* r;      // refinement residual
+  double* x;      // refinement iterate
+  int64_t* perm;
+  double* D;
+  int8_t* ipiv;
+};
+
+// interchange positions p < q (both >= kc, the first live position) in the
+// trailing working matrix, the sketch (and residual while the QRCP runs),
+// the rows of the block's L columns so far (kk of them), the rows of the
+// finished L columns, and the permutation
+template <typename TA>
+__device__ void swap_positions(Sys<TA>& S, int p, int q, int kc, int kk) {
+  if (p == q) return;
+  if (p > q) swp(p, q);
+  const int n = S.n, tid = threadIdx.x;
+  TA* W = S.W;
+  for (int t = kc + tid; t < n; t += kBT) {
+    if (t < p) swp(W[p + (int64_t)t * n], W[q + (int64_t)t * n]);
+    else if (t == p) swp(W[p + (int64_t)p * n], W[q + (int64_t)q * n]);
+    else if (t < q) swp(W[t + (int64_t)p * n], W[q + (int64_t)t * n]);
+    else if (t > q) swp(W[t + (int64_t)p * n], W[t + (int64_t)q * n]);
+  }
+  for (int e = tid; e < S.l; e += kBT) {
+    swp(S.B[(int64_t)p * S.l + e], S.B[(int64_t)q * S.l + e]);
+    if (S.r_live) swp(S.R[(int64_t)p * S.l + e], S.R[(int64_t)q * S.l + e]);
+  }
+  for (int t = tid; t < kk; t += kBT) swp(S.Lp[p * kBldp + t], S.Lp[q * kBldp + t]);
+  for (int t = tid; t < S.K0; t += kBT) swp(S.Lw[p + (int64_t)t * n], S.Lw[q + (int64_t)t * n]);
+  if (tid == 0) swp(S.perm[p], S.perm[q]);
+  __syncthreads();
+}
+
+// W row (L D) of position c over the block's first kk columns, into dst
+template <typename TA>
+__device__ void w_row(const Sys<TA>& S, int c, int kk, double* dst) {
+  const int K0 = S.K0, n = S.n;
+  const double* x = S.Lp + c * kBldp;
+  for (int t = threadIdx.x; t < kk; t += kBT) {
+    const int kd = S.ipiv[K0 + t];
+    double w;
+    if (kd == 1) w = x[t] * S.D[K0 + t];
+    else if (kd == 2) w = fma(x[t], S.D[K0 + t], x[t + 1] * S.D[n + K0 + t]);
+    else w = fma(x[t - 1], S.D[n + K0 + t - 1], x[t] * S.D[K0 + t]);
+    dst[t] = w;
+  }
+}
+
+// current column of position c on positions [k, n): A(s, c) - L(s, :) W(c, :)
+template <typename TA>
+__device__ void cur_column(const Sys<TA>& S, int c, int k, int kk, const double* wr, double* out) {
+  const int n = S.n;
+  for (int s = k + threadIdx.x; s < n; s += kBT) {
+    double a = symw(S.W, n, s, c);
+    const double* x = S.Lp + s * kBldp;
+    for (int t = 0; t < kk; ++t) a = fma(-x[t], wr[t], a);
+    out[s - k] = a;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// the kernel
+// ---------------------------------------------------------------------------
+template <typename TA>
+__device__ void blocked_solve(Sys<TA>& S, int nrhs, double* yv, Shared& sh);
+
+template <typename TA>
+__global__ void __launch_bounds__(kBT) batched_kernel(KernelArgs a) {
+  __shared__ Shared sh;
+  const int sid = a.order[blockIdx.x];
+  const BatchSys d = a.sys[sid];
+  const int n = d.n, b = d.b, l = d.l, tid = threadIdx.x;
+  char* base = a.work + d.w_off;
+  Sys<TA> S;
+  S.n = n;
+  S.b = b;
+  S.l = l;
+  S.K0 = 0;
+  S.r_live = false;
+  {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+      char* p = base + off;
+      off += (bytes + 255) & ~(size_t)255;
+      return p;
+    };
+    S.W = (TA*)take((size_t)n * n * sizeof(TA));
+    S.Lw = (TA*)take((size_t)n * n * sizeof(TA));
+    S.B = (double*)take((size_t)l * n * 8);
+    S.R = (double*)take((size_t)l * n * 8);
+    S.Lp = (double*)take((size_t)n * kBldp * 8);
+    S.Wp = (double*)take((size_t)n * kBldp * 8);
+    S.Om = (double*)take((size_t)l * n * 8);
+    S.y = (double*)take((size_t)n * a.nrhs * 8);
+    S.r = (double*)take((size_t)n * a.nrhs * 8);
+    S.x = (double*)take((size_t)n * a.nrhs * 8);
+    S.perm = (int64_t*)take((size_t)n * 8);
+    S.D = (double*)take((size_t)2 * n * 8);
+    S.ipiv = (int8_t*)take((size_t)n);
+  }
+  const double* A = a.Apool + d.a_off;
+  if (tid == 0) {
+    sh.info = INT_MAX;
+    sh.n2x2 = 0;
+  }
+
+  // ---- set-up: W = sym(A) (both triangles, the upper one only for the
+  // sketch), Lw = 0, perm = identity, Omega
+  for (int64_t e = tid; e < (int64_t)n * n; e += kBT) {
+    const int j = (int)(e / n), i = (int)(e - (int64_t)j * n);
+    S.W[e] = (TA)((i >= j) ? A[e] : A[j + (int64_t)i * n]);
+    S.Lw[e] = (TA)0;
+  }
+  for (int i = tid; i < n; i += kBT) {
+    S.perm[i] = i;
+    S.D[i] = 0.0;
+    S.D[n + i] = 0.0;
+    S.ipiv[i] = 1;
+  }
+  {
+    const int64_t total = (int64_t)l * n;
+    for (int64_t c = tid; 4 * c < total; c += kBT) {
+      double z[4];
+      omega_dev::omega_quad(d.seed, c, z);
+      for (int t = 0; t < 4; ++t)
+        if (4 * c + t < total) S.Om[4 * c + t] = z[t];
+    }
+  }
+  __syncthreads();
+  // ---- sketch B(r, j) = sum_i Omega(r, i) A(i, j): a thread per column j,
+  // 16 rows r at a time; W(j, i) = A(i, j) is contiguous across the lanes
+  for (int j = tid; j < n; j += kBT) {
+    for (int r0 = 0; r0 < l; r0 += 16) {
+      double acc[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+      for (int i = 0; i < n; ++i) {
+        const double av = (double)S.W[j + (int64_t)i * n];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (r0 + u < l) acc[u] = fma(S.Om[(int64_t)(r0 + u) * n + i], av, acc[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (r0 + u < l) S.B[(int64_t)j * l + r0 + u] = acc[u];
+    }
+  }
+  __syncthreads();
+
+  // ---- blocks
+  int K0 = 0;
+  while (K0 < n) {
+    S.K0 = K0;
+    const int N = n - K0;
+    const int bb = min(b, N);
+    // ---- partial QRCP on the sketch of the trailing matrix
+    for (int64_t e = tid; e < (int64_t)l * N; e += kBT) S.R[(int64_t)K0 * l + e] = S.B[(int64_t)K0 * l + e];
+    S.r_live = true;
+    __syncthreads();
+    const int qsteps = min(bb, l);
+    for (int j = 0; j < qsteps; ++j) {
+      const int pj = K0 + j;
+      double best = -1.0;
+      int bpos = INT_MAX;
+      for (int c = pj + tid; c < n; c += kBT) {
+        const double* rc = S.R + (int64_t)c * l;
+        double ss = 0.0;
+        for (int r = j; r < l; ++r) ss = fma(rc[r], rc[r], ss);
+        if (key_gt(ss, c, best, bpos)) {
+          best = ss;
+          bpos = c;
+        }
+      }
+      wg_argmax(best, bpos, sh);
+      if (!(best > 0.0)) break;
+      swap_positions(S, pj, bpos, K0, 0);
+      // Householder vector of x = R(j:l, pj): v = x + sign(x_j) ||x|| e_j,
+      // beta = 2 / v.v = 1 / (||x|| (||x|| + |x_j|))
+      const double nx = sqrt(best);
+      const double* xr = S.R + (int64_t)pj * l;
+      const double xj = xr[j];
+      const double beta = 1.0 / (nx * (nx + fabs(xj)));
+      for (int r = j + tid; r < l; r += kBT) sh.v[r] = (r == j) ? xj + copysign(nx, xj) : xr[r];
+      __syncthreads();
+      for (int c = pj + 1 + tid; c < n; c += kBT) {
+        double* rc = S.R + (int64_t)c * l;
+        double g = 0.0;
+        for (int r = j; r < l; ++r) g = fma(sh.v[r], rc[r], g);
+        g *= beta;
+        for (int r = j; r < l; ++r) rc[r] = fma(-g, sh.v[r], rc[r]);
+      }
+      __syncthreads();
+    }
+    S.r_live = false;
+
+    // ---- SBKP eliminations of the block (left-looking within the block)
+    int kk = 0;
+    while (kk < bb && K0 + kk < n) {
+      const int k = K0 + kk;
+      w_row(S, k, kk, sh.wrow);
+      __syncthreads();
+      cur_column(S, k, k, kk, sh.wrow, sh.p.colv);
+      __syncthreads();
+      if (k == n - 1) {   // last pivot: D(n, n) = a_nn
+        if (tid == 0) {
+          S.D[k] = sh.p.colv[0];
+          S.ipiv[k] = 1;
+          if (sh.p.colv[0] == 0.0) sh.info = min(sh.info, k + 1);
+        }
+        kk += 1;
+        __syncthreads();
+        break;
+      }
+      double lam = -1.0;
+      int r = INT_MAX;
+      for (int s = k + 1 + tid; s < n; s += kBT) {
+        const double v = fabs(sh.p.colv[s - k]);
+        if (key_gt(v, s, lam, r)) {
+          lam = v;
+          r = s;
+        }
+      }
+      wg_argmax(lam, r, sh);
+      const double akk = sh.p.colv[0];
+      const double alam = RCP_ALPHA * lam;
+      int step = 1;
+      if (lam == 0.0 || fabs(akk) >= alam) {
+        // cases (0) and (1): 1x1 pivot a_kk
+      } else {
+        // a_rr from the W row of r
+        w_row(S, r, kk, sh.wrow2);
+        __syncthreads();
+        if (tid < 64) {
+          double acc = 0.0;
+          const double* x = S.Lp + r * kBldp;
+          for (int t = tid; t < kk; t += 64) acc = fma(x[t], sh.wrow2[t], acc);
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+          if (tid == 0) sh.sc[0] = symw(S.W, n, r, r) - acc;
+        }
+        __syncthreads();
+        const double arr = sh.sc[0];
+        if (fabs(arr) >= alam) {
+          // case (2): interchange k and r, 1x1 pivot
+          swap_positions(S, k, r, k, kk);
+          w_row(S, k, kk, sh.wrow);
+          __syncthreads();
+          cur_column(S, k, k, kk, sh.wrow, sh.p.colv);
+          __syncthreads();
+        } else {
+          // case (3): interchange k+1 and r, 2x2 pivot
+          step = 2;
+          if (r != k + 1) {
+            swap_positions(S, k + 1, r, k, kk);
+            if (tid == 0) swp(sh.p.colv[1], sh.p.colv[r - k]);
+            __syncthreads();
+          }
+          w_row(S, k + 1, kk, sh.wrow2);
+          __syncthreads();
+          cur_column(S, k + 1, k, kk, sh.wrow2, sh.p.colv2);
+          __syncthreads();
+        }
+      }
+      // multipliers, D, ipiv
+      if (step == 1) {
+        const double dk = sh.p.colv[0];
+        for (int s = k + 1 + tid; s < n; s += kBT)
+          S.Lp[s * kBldp + kk] = dk != 0.0 ? sh.p.colv[s - k] / dk : 0.0;
+        if (tid == 0) {
+          S.D[k] = dk;
+          S.D[n + k] = 0.0;
+          S.ipiv[k] = 1;
+          if (dk == 0.0) sh.info = min(sh.info, k + 1);
+        }
+      } else {
+        const double e00 = sh.p.colv[0], e10 = sh.p.colv[1], e11 = sh.p.colv2[1];
+        const double det = fma(e00, e11, -(e10 * e10));
+        for (int s = k + 2 + tid; s < n; s += kBT) {
+          const double vv = sh.p.colv[s - k], ww = sh.p.colv2[s - k];
+          S.Lp[s * kBldp + kk] = fma(vv, e11, -(e10 * ww)) / det;
+          S.Lp[s * kBldp + kk + 1] = fma(e00, ww, -(e10 * vv)) / det;
+        }
+        if (tid == 0) {
+          S.Lp[(k + 1) * kBldp + kk] = 0.0;
+          S.D[k] = e00;
+          S.D[k + 1] = e11;
+          S.D[n + k] = e10;
+          S.D[n + k + 1] = 0.0;
+          S.ipiv[k] = 2;
+          S.ipiv[k + 1] = 0;
+          sh.n2x2 += 1;
+        }
+      }
+      kk += step;
+      __syncthreads();
+    }
+    const int m = kk;
+    const int K1 = K0 + m;
+    const int N2 = n - K1;
+    // ---- store the block's L columns (strictly lower part)
+    for (int64_t e = tid; e < (int64_t)m * N; e += kBT) {
+      const int t = (int)(e / N), s = K0 + (int)(e - (int64_t)t * N);
+      if (s > K0 + t) S.Lw[s + (int64_t)(K0 + t) * n] = (TA)S.Lp[s * kBldp + t];
+    }
+    __syncthreads();
+    if (N2 > 0) {
+      // ---- sketch update: T = B~_1 L11^{-T} (a thread per sketch row),
+      // then B(:, K1:n) -= T L21^T
+      if (tid < l) {
+        for (int t = 0; t < m; ++t) {
+          double v = S.B[(int64_t)(K0 + t) * l + tid];
+          for (int u = 0; u < t; ++u) v = fma(-sh.T[tid][u], S.Lp[(K0 + t) * kBldp + u], v);
+          sh.T[tid][t] = v;
+        }
+      }
+      // W rows of the trailing positions for the update
+      for (int e = tid; e < N2 * m; e += kBT) {
+        const int s = K1 + e / m, t = e % m;
+        const double* x = S.Lp + s * kBldp;
+        const int kd = S.ipiv[K0 + t];
+        double w;
+        if (kd == 1) w = x[t] * S.D[K0 + t];
+        else if (kd == 2) w = fma(x[t], S.D[K0 + t], x[t + 1] * S.D[n + K0 + t]);
+        else w = fma(x[t - 1], S.D[n + K0 + t - 1], x[t] * S.D[K0 + t]);
+        S.Wp[s * kBldp + t] = w;
+      }
+      __syncthreads();
+      for (int e = tid; e < N2 * l; e += kBT) {
+        const int j = K1 + e / l, rr = e % l;
+        double v = S.B[(int64_t)j * l + rr];
+        const double* x = S.Lp + j * kBldp;
+        for (int t = 0; t < m; ++t) v = fma(-sh.T[rr][t], x[t], v);
+        S.B[(int64_t)j * l + rr] = v;
+      }
+      __syncthreads();   // T and the update tiles share LDS
+      // ---- trailing update W(i, j) -= sum_t L(i, t) W(j, t), K1 <= j <= i,
+      // in 64 x 64 tiles through LDS, 4 x 4 outputs per thread
+      const int nt = (N2 + 63) / 64;
+      for (int tile = 0; tile < nt * (nt + 1) / 2; ++tile) {
+        int ti = 0;
+        while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
+        const int tj = tile - ti * (ti + 1) / 2;
+        const int i0 = K1 + 64 * ti, j0 = K1 + 64 * tj;
+        __syncthreads();
+        for (int e = tid; e < 64 * m; e += kBT) {
+          const int rr = e / m, t = e % m;
+          sh.u.ta[rr][t] = (i0 + rr < n) ? S.Lp[(i0 + rr) * kBldp + t] : 0.0;
+          sh.u.tb[rr][t] = (j0 + rr < n) ? S.Wp[(j0 + rr) * kBldp + t] : 0.0;
+        }
+        __syncthreads();
+        const int ri = (tid & 15) * 4, rj = (tid >> 4) * 4;
+        double acc[4][4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+        for (int t = 0; t < m; ++t) {
+          double av[4], bv[4];
+#pragma unroll
+          for (int x = 0; x < 4; ++x) {
+            av[x] = sh.u.ta[ri + x][t];
+            bv[x] = sh.u.tb[rj + x][t];
+          }
+#pragma unroll
+          for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) acc[x][y] = fma(av[x], bv[y], acc[x][y]);
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) {
+            const int i = i0 + ri + x, j = j0 + rj + y;
+            if (i < n && j < n && i >= j) {
+              TA* wp = &S.W[i + (int64_t)j * n];
+              *wp = (TA)((double)*wp - acc[x][y]);
+            }
+          }
+      }
+      __syncthreads();
+    }
+    K0 = K1;
+  }
+  // ---- unit diagonal of L
+  for (int i = tid; i < n; i += kBT) S.Lw[i + (int64_t)i * n] = (TA)1;
+  __syncthreads();
+
+  // ---- solve (and, in the FP32 form, refine in FP64)
+  const int nrhs = a.nrhs;
+  const double* Bv = a.Bpool + d.x_off;
+  double* Xv = a.Xpool + d.x_off;
+  int iters = 0;
+  double berr = 0.0;
+  const bool refine = sizeof(TA) == 4;
+  const int info = sh.info;   // uniform: written before the last barrier
+  if (info == INT_MAX) {
+    for (int64_t e = tid; e < (int64_t)n * nrhs; e += kBT) S.y[e] = Bv[e];
+    __syncthreads();
+    blocked_solve(S, nrhs, S.y, sh);
+    for (int64_t e = tid; e < (int64_t)n * nrhs; e += kBT) S.x[e] = S.y[e];
+    __syncthreads();
+    // ||A||_inf (row sums of |sym(A)| from the lower triangle of the input)
+    double rs_max = 0.0;
+    for (int i = tid; i < n; i += kBT) {
+      double s = 0.0;
+      for (int j = 0; j <= i; ++j) s += fabs(A[i + (int64_t)j * n]);
+      for (int j = i + 1; j < n; ++j) s += fabs(A[j + (int64_t)i * n]);
+      rs_max = fmax(rs_max, s);
+    }
+    int dummy = 0;
+    wg_argmax(rs_max, dummy, sh);
+    const double anorm = rs_max;
+    for (;;) {
+      // r = b - A x, in FP64 from the input matrix
+      for (int i = tid; i < n; i += kBT) {
+        for (int c = 0; c < nrhs; ++c) {
+          const double* xc = S.x + (int64_t)c * n;
+          double s = 0.0;
+          for (int j = 0; j <= i; ++j) s = fma(A[i + (int64_t)j * n], xc[j], s);
+          for (int j = i + 1; j < n; ++j) s = fma(A[j + (int64_t)i * n], xc[j], s);
+          S.r[i + (int64_t)c * n] = Bv[i + (int64_t)c * n] - s;
+        }
+      }
+      __syncthreads();
+      berr = 0.0;
+      for (int c = 0; c < nrhs; ++c) {
+        double rm = 0.0, xm = 0.0;
+        for (int i = tid; i < n; i += kBT) {
+          rm = fmax(rm, fabs(S.r[i + (int64_t)c * n]));
+          xm = fmax(xm, fabs(S.x[i + (int64_t)c * n]));
+        }
+        int p0 = 0, p1 = 0;
+        wg_argmax(rm, p0, sh);
+        wg_argmax(xm, p1, sh);
+        const double den = anorm * xm;
+        berr = fmax(berr, den > 0.0 ? rm / den : (rm > 0.0 ? INFINITY : 0.0));
+      }
+      if (!refine || berr <= a.ir_tol || iters >= a.ir_max) break;
+      ++iters;
+      for (int64_t e = tid; e < (int64_t)n * nrhs; e += kBT) S.y[e] = S.r[e];
+      __syncthreads();
+      blocked_solve(S, nrhs, S.y, sh);
+      for (int64_t e = tid; e < (int64_t)n * nrhs; e += kBT) S.x[e] += S.y[e];
+      __syncthreads();
+    }
+    for (int64_t e = tid; e < (int64_t)n * nrhs; e += kBT) Xv[e] = S.x[e];
+  }
+  // ---- optional factor outputs and the status record
+  if (a.perm_out)
+    for (int i = tid; i < n; i += kBT) a.perm_out[d.v_off + i] = S.perm[i];
+  if (a.D_out)
+    for (int i = tid; i < n; i += kBT) {
+      a.D_out[2 * d.v_off + i] = S.D[i];
+      a.D_out[2 * d.v_off + n + i] = S.D[n + i];
+    }
+  if (a.ipiv_out)
+    for (int i = tid; i < n; i += kBT) a.ipiv_out[d.v_off + i] = S.ipiv[i];
+  if (a.L_out) {
+    TA* Lo = (TA*)a.L_out + d.a_off;
+    for (int64_t e = tid; e < (int64_t)n * n; e += kBT) Lo[e] = S.Lw[e];
+  }
+  if (tid == 0) {
+    BatchStatus st;
+    st.b = b;
+    st.info = info == INT_MAX ? 0 : info;
+    st.ir_iters = iters;
+    st.n2x2 = sh.n2x2;
+    st.berr = berr;
+    a.status[sid] = st;
+  }
+}
+
+// X <- A^{-1} X for the factored system: gather by perm, L y = y (64-row
+// blocks: a wave solves the diagonal block with lane broadcasts, the whole
+// workgroup updates the rows below), D, L^T y = y, scatter by perm
+template <typename TA>
+__device__ void blocked_solve(Sys<TA>& S, int nrhs, double* yv, Shared& sh) {
+  const int n = S.n, tid = threadIdx.x, lane = tid & 63;
+  // gather: yv(i) = B(perm(i)); yv holds B on entry; use S.r... the caller's
+  // buffer is permuted in place through the Wp scratch
+  double* tmp = S.Wp;   // n * kBldp >= n * nrhs doubles
+  for (int64_t e = tid; e < (int64_t)n * nrhs; e += kBT) {
+    const int c = (int)(e / n), i = (int)(e - (int64_t)c * n);
+    tmp[e] = yv[S.perm[i] + (int64_t)c * n];
+  }
+  __syncthreads();
+  const int nb = (n + 63) / 64;
+  // forward
+  for (int J = 0; J < nb; ++J) {
+    const int j0 = 64 * J, jn = min(64, n - j0);
+    if (tid < 64) {
+      double yc[4];
+      for (int c = 0; c < nrhs; ++c) yc[c] = (lane < jn) ? tmp[j0 + lane + (int64_t)c * n] : 0.0;
+      for (int t = 0; t < jn; ++t) {
+        const double lv = (lane > t && lane < jn) ? (double)S.Lw[(j0 + lane) + (int64_t)(j0 + t) * n] : 0.0;
+        for (int c = 0; c < nrhs; ++c) {
+          const double yt = __shfl(yc[c], t, 64);
+          yc[c] = fma(-lv, yt, yc[c]);
+        }
+      }
+      for (int c = 0; c < nrhs; ++c) {
+        if (lane < jn) tmp[j0 + lane + (int64_t)c * n] = yc[c];
+        sh.s.yb[c][lane] = yc[c];
+      }
+    }
+    __syncthreads();
+    for (int i = j0 + jn + tid; i < n; i += kBT) {
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int t = 0; t < jn; ++t) {
+        const double lv = (double)S.Lw[i + (int64_t)(j0 + t) * n];
+        for (int c = 0; c < nrhs; ++c) acc[c] = fma(lv, sh.s.yb[c][t], acc[c]);
+      }
+      for (int c = 0; c < nrhs; ++c) tmp[i + (int64_t)c * n] -= acc[c];
+    }
+    __syncthreads();
+  }
+  // D
+  for (int i = tid; i < n; i += kBT) {
+    const int kd = S.ipiv[i];
+    for (int c = 0; c < nrhs; ++c) {
+      double* y = tmp + (int64_t)c * n;
+      if (kd == 1) {
+        y[i] = y[i] / S.D[i];
+      } else if (kd == 2) {
+        const double e00 = S.D[i], e11 = S.D[i + 1], e10 = S.D[n + i];
+        const double det = fma(e00, e11, -(e10 * e10));
+        const double y0 = y[i], y1 = y[i + 1];
+        y[i] = fma(e11, y0, -(e10 * y1)) / det;
+        y[i + 1] = fma(e00, y1, -(e10 * y0)) / det;
+      }
+    }
+  }
+  __syncthreads();
+  // backward
+  for (int J = nb - 1; J >= 0; --J) {
+    const int j0 = 64 * J, jn = min(64, n - j0);
+    // y(j0 + t) -= sum_{i >= j0 + jn} L(i, j0 + t) y(i): four quarters of
+    // the rows per column t
+    {
+      const int t = tid & 63, qtr = tid >> 6;
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      if (t < jn)
+        for (int i = j0 + jn + qtr; i < n; i += 4) {
+          const double lv = (double)S.Lw[i + (int64_t)(j0 + t) * n];
+          for (int c = 0; c < nrhs; ++c) acc[c] = fma(lv, tmp[i + (int64_t)c * n], acc[c]);
+        }
+      for (int c = 0; c < nrhs; ++c) sh.s.part[qtr][c][t] = acc[c];
+    }
+    __syncthreads();
+    if (tid < 64) {
+      double yc[4];
+      for (int c = 0; c < nrhs; ++c)
+        yc[c] = (lane < jn) ? tmp[j0 + lane + (int64_t)c * n] -
+                                  ((sh.s.part[0][c][lane] + sh.s.part[1][c][lane]) +
+                                   (sh.s.part[2][c][lane] + sh.s.part[3][c][lane]))
+                            : 0.0;
+      for (int t = jn - 1; t >= 0; --t) {
+        const double lv = (lane < t) ? (double)S.Lw[(j0 + t) + (int64_t)(j0 + lane) * n] : 0.0;
+        for (int c = 0; c < nrhs; ++c) {
+          const double yt = __shfl(yc[c], t, 64);
+          yc[c] = fma(-lv, yt, yc[c]);
+        }
+      }
+      for (int c = 0; c < nrhs; ++c)
+        if (lane < jn) tmp[j0 + lane + (int64_t)c * n] = yc[c];
+    }
+    __syncthreads();
+  }
+  // scatter
+  for (int64_t e = tid; e < (int64_t)n * nrhs; e += kBT) {
+    const int c = (int)(e / n), i = (int)(e - (int64_t)c * n);
+    yv[S.perm[i] + (int64_t)c * n] = tmp[e];
+  }
+  __syncthreads();
+}
+
+}  // namespace
+
+size_t batch_work_bytes(int n, int l, int nrhs, int prec) {
+  const size_t es = prec == kPrecF64 ? 8 : 4;
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  return 2 * al((size_t)n * n * es) + 3 * al((size_t)l * n * 8) + 2 * al((size_t)n * kBldp * 8) +
+         3 * al((size_t)n * nrhs * 8) + 2 * al((size_t)n * 8) + al((size_t)2 * n * 8) + al(n);
+}
+
+void launch_batched(int count, const BatchSys* sys, const int* order, const double* Apool,
+                    const double* Bpool, double* Xpool, int nrhs, char* work, int64_t* perm,
+                    void* L, double* D, int8_t* ipiv, BatchStatus* status, int prec, int ir_max,
+                    double ir_tol, hipStream_t s) {
+  if (count <= 0) return;
+  KernelArgs a;
+  a.sys = sys;
+  a.order = order;
+  a.Apool = Apool;
+  a.Bpool = Bpool;
+  a.Xpool = Xpool;
+  a.nrhs = nrhs;
+  a.work = work;
+  a.perm_out = perm;
+  a.L_out = L;
+  a.D_out = D;
+  a.ipiv_out = ipiv;
+  a.status = status;
+  a.ir_max = ir_max;
+  a.ir_tol = ir_tol;
+  if (prec == kPrecF64)
+    hipLaunchKernelGGL(batched_kernel<double>, dim3(count), dim3(kBT), 0, s, a);
+  else
+    hipLaunchKernelGGL(batched_kernel<float>, dim3(count), dim3(kBT), 0, s, a);
+}
+
+}  // namespace rcp

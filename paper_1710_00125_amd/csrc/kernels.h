@@ -131,6 +131,28 @@ void launch_solve(int64_t n, const void* L, int l_f32, const double* D, const in
                   unsigned int* sync, hipStream_t s);
 size_t solve_sync_words(int64_t n);
 
+// ---- batched.hip  (many small systems, one workgroup each)
+constexpr int kBatchMaxN = 512;
+constexpr int kBatchMaxL = 64;
+constexpr int kBatchMaxB = 32;
+struct BatchSys {
+  int n, b, l, pad;
+  uint64_t seed;
+  int64_t a_off;    // offset of A (and of the optional L output) in the n^2 pools
+  int64_t x_off;    // offset of B / X in the n * nrhs pools
+  int64_t v_off;    // offset in the n pools (perm, ipiv; D uses 2 v_off)
+  int64_t w_off;    // byte offset of the system's workspace
+};
+struct BatchStatus {
+  int b, info, ir_iters, n2x2;
+  double berr;
+};
+size_t batch_work_bytes(int n, int l, int nrhs, int prec);
+void launch_batched(int count, const BatchSys* sys, const int* order, const double* Apool,
+                    const double* Bpool, double* Xpool, int nrhs, char* work, int64_t* perm,
+                    void* L, double* D, int8_t* ipiv, BatchStatus* status, int prec, int ir_max,
+                    double ir_tol, hipStream_t s);
+
 // ---- refine.hip  (FP64 pieces of GMRES-based iterative refinement)
 // out(:, c) = A X(:, c) (mode 0) or B(:, c) - A X(:, c) (mode 1), A symmetric
 // from its lower triangle (lda), nr <= 4; abs_mode: row sums of |A| (nr = 1,

@@ -666,3 +666,247 @@ int rcp_solve_ir(int64_t n, const double* A, int64_t lda, const float* L, const 
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched systems: a plan holds the per-system descriptors on the device,
+// the workspace, and the launch captured in a hipGraph on the plan's own
+// stream; running the plan replays the graph.
+// ---------------------------------------------------------------------------
+struct rcp_batch {
+  int64_t count = 0;
+  int prec = 0;
+  int nrhs = 1;
+  hipStream_t stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  BatchSys* d_sys = nullptr;
+  int* d_order = nullptr;
+  char* d_work = nullptr;
+  BatchStatus* d_status = nullptr;
+  std::vector<BatchStatus> h_status;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+};
+
+namespace {
+
+// block size per size class (n <= 64, 128, 256, 512), per precision; the
+// autotuner overwrites these
+int g_batch_b[2][4] = {{8, 16, 16, 16}, {8, 16, 16, 16}};
+constexpr int kIrMax = 10;
+constexpr double kIrTol = 1e-13;
+
+int size_class(int n) { return n <= 64 ? 0 : n <= 128 ? 1 : n <= 256 ? 2 : 3; }
+
+struct BatchPlanHost {
+  std::vector<BatchSys> sys;
+  std::vector<int> order;
+  size_t work = 0;
+};
+
+void plan_layout(const int32_t* n, int64_t count, int p, uint64_t seed0, int prec, int nrhs,
+                 const int* b_of_class, const std::vector<int64_t>* subset, BatchPlanHost& P) {
+  P.sys.clear();
+  P.order.clear();
+  P.work = 0;
+  int64_t a_off = 0, x_off = 0, v_off = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    const int ni = n[i];
+    if (!subset || std::binary_search(subset->begin(), subset->end(), i)) {
+      BatchSys d;
+      d.n = ni;
+      d.b = std::min(b_of_class[size_class(ni)], std::max(1, ni));
+      d.l = d.b + p;
+      d.pad = 0;
+      d.seed = seed0 + (uint64_t)i;
+      d.a_off = a_off;
+      d.x_off = x_off;
+      d.v_off = v_off;
+      d.w_off = (int64_t)P.work;
+      P.work += batch_work_bytes(ni, d.l, nrhs, prec);
+      P.sys.push_back(d);
+    }
+    a_off += (int64_t)ni * ni;
+    x_off += (int64_t)ni * nrhs;
+    v_off += ni;
+  }
+  P.order.resize(P.sys.size());
+  for (size_t i = 0; i < P.order.size(); ++i) P.order[i] = (int)i;
+  // largest systems first: the long workgroups start early
+  std::stable_sort(P.order.begin(), P.order.end(),
+                   [&](int x, int y) { return P.sys[x].n > P.sys[y].n; });
+}
+
+void batch_free(rcp_batch* h) {
+  if (!h) return;
+  if (h->exec) hipGraphExecDestroy(h->exec);
+  if (h->graph) hipGraphDestroy(h->graph);
+  if (h->d_sys) hipFree(h->d_sys);
+  if (h->d_order) hipFree(h->d_order);
+  if (h->d_work) hipFree(h->d_work);
+  if (h->d_status) hipFree(h->d_status);
+  if (h->e0) hipEventDestroy(h->e0);
+  if (h->e1) hipEventDestroy(h->e1);
+  if (h->stream) hipStreamDestroy(h->stream);
+  delete h;
+}
+
+int upload_plan(rcp_batch* h, const BatchPlanHost& P) {
+  const size_t cnt = P.sys.size();
+  if (hipMalloc((void**)&h->d_sys, cnt * sizeof(BatchSys)) != hipSuccess) return RCP_ENOMEM;
+  if (hipMalloc((void**)&h->d_order, cnt * sizeof(int)) != hipSuccess) return RCP_ENOMEM;
+  if (hipMalloc((void**)&h->d_work, std::max<size_t>(P.work, 256)) != hipSuccess) return RCP_ENOMEM;
+  if (hipMalloc((void**)&h->d_status, cnt * sizeof(BatchStatus)) != hipSuccess) return RCP_ENOMEM;
+  RCP_CHECK(hipMemcpy(h->d_sys, P.sys.data(), cnt * sizeof(BatchSys), hipMemcpyHostToDevice));
+  RCP_CHECK(hipMemcpy(h->d_order, P.order.data(), cnt * sizeof(int), hipMemcpyHostToDevice));
+  h->count = (int64_t)cnt;
+  h->h_status.assign(cnt, BatchStatus{});
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rcp_batch_get_table(int32_t precision, int32_t* b_by_class) {
+  if (precision != 0 && precision != RCP_PREC_FP32) return -1;
+  if (!b_by_class) return -2;
+  for (int c = 0; c < 4; ++c) b_by_class[c] = g_batch_b[precision ? 1 : 0][c];
+  return 0;
+}
+
+int rcp_batch_create(int64_t count, const int32_t* n, int32_t p, uint64_t seed0,
+                     int32_t precision, int32_t nrhs, const double* Apool, const double* Bpool,
+                     double* Xpool, int64_t* perm, void* L, double* D, int8_t* ipiv,
+                     int32_t autotune, rcp_batch** out) {
+  if (count < 0) return -1;
+  if (count > 0 && !n) return -2;
+  if (p < 0 || p + kBatchMaxB > kBatchMaxL) return -3;
+  if (precision != 0 && precision != RCP_PREC_FP32) return -5;
+  if (nrhs < 1 || nrhs > 4) return -6;
+  if (count > 0 && (!Apool || !Bpool || !Xpool)) return -7;
+  if (!out) return -15;
+  for (int64_t i = 0; i < count; ++i)
+    if (n[i] < 1 || n[i] > kBatchMaxN) return -2;
+  *out = nullptr;
+  const int prec = precision ? kPrecF32 : kPrecF64;
+  const int pi = precision ? 1 : 0;
+  rcp_batch* h = new rcp_batch();
+  h->prec = prec;
+  h->nrhs = nrhs;
+  int rc = 0;
+  if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreate(&h->e0) != hipSuccess || hipEventCreate(&h->e1) != hipSuccess) {
+    batch_free(h);
+    return RCP_EDEVICE;
+  }
+  if (autotune && count > 0) {
+    // per size class: time each candidate block size on up to 64 of the
+    // batch's systems of that class and keep the fastest
+    const int cand[4] = {8, 16, 24, 32};
+    for (int c = 0; c < 4; ++c) {
+      std::vector<int64_t> sub;
+      for (int64_t i = 0; i < count && sub.size() < 64; ++i)
+        if (size_class(n[i]) == c) sub.push_back(i);
+      if (sub.empty()) continue;
+      float best_ms = 1e30f;
+      int best_b = g_batch_b[pi][c];
+      for (int b : cand) {
+        int table[4];
+        for (int t = 0; t < 4; ++t) table[t] = b;
+        BatchPlanHost P;
+        plan_layout(n, count, p, seed0, prec, nrhs, table, &sub, P);
+        rcp_batch* t = new rcp_batch();
+        t->stream = h->stream;
+        rc = upload_plan(t, P);
+        float ms = 1e30f;
+        if (rc == 0) {
+          for (int rep = 0; rep < 2; ++rep) {
+            hipEventRecord(h->e0, h->stream);
+            launch_batched((int)t->count, t->d_sys, t->d_order, Apool, Bpool, Xpool, nrhs,
+                           t->d_work, nullptr, nullptr, nullptr, nullptr, t->d_status, prec,
+                           kIrMax, kIrTol, h->stream);
+            hipEventRecord(h->e1, h->stream);
+            if (hipStreamSynchronize(h->stream) != hipSuccess) rc = RCP_EDEVICE;
+            float e = 0.f;
+            hipEventElapsedTime(&e, h->e0, h->e1);
+            if (rep == 1) ms = e;
+          }
+        }
+        t->stream = nullptr;   // owned by h
+        batch_free(t);
+        if (rc != 0) {
+          batch_free(h);
+          return rc;
+        }
+        if (ms < best_ms) {
+          best_ms = ms;
+          best_b = b;
+        }
+      }
+      g_batch_b[pi][c] = best_b;
+    }
+  }
+  BatchPlanHost P;
+  plan_layout(n, count, p, seed0, prec, nrhs, g_batch_b[pi], nullptr, P);
+  rc = upload_plan(h, P);
+  if (rc != 0) {
+    batch_free(h);
+    return rc;
+  }
+  // capture the launch (one kernel: every system writes its own status, no
+  // memset nodes)
+  if (count > 0) {
+    if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      batch_free(h);
+      return RCP_EDEVICE;
+    }
+    launch_batched((int)h->count, h->d_sys, h->d_order, Apool, Bpool, Xpool, nrhs, h->d_work,
+                   perm, L, D, ipiv, h->d_status, prec, kIrMax, kIrTol, h->stream);
+    if (hipStreamEndCapture(h->stream, &h->graph) != hipSuccess ||
+        hipGraphInstantiate(&h->exec, h->graph, nullptr, nullptr, 0) != hipSuccess) {
+      batch_free(h);
+      return RCP_EDEVICE;
+    }
+  }
+  *out = h;
+  return 0;
+}
+
+int rcp_batch_run(rcp_batch* h, float* ms) {
+  if (!h) return -1;
+  if (h->count == 0) return 0;
+  RCP_CHECK(hipEventRecord(h->e0, h->stream));
+  RCP_CHECK(hipGraphLaunch(h->exec, h->stream));
+  RCP_CHECK(hipEventRecord(h->e1, h->stream));
+  RCP_CHECK(hipMemcpyAsync(h->h_status.data(), h->d_status, h->count * sizeof(BatchStatus),
+                           hipMemcpyDeviceToHost, h->stream));
+  RCP_CHECK(hipStreamSynchronize(h->stream));
+  if (ms) {
+    float e = 0.f;
+    hipEventElapsedTime(&e, h->e0, h->e1);
+    *ms = e;
+  }
+  return 0;
+}
+
+int rcp_batch_get_info(const rcp_batch* h, rcp_batch_info* info) {
+  if (!h) return -1;
+  if (!info && h->count > 0) return -2;
+  // h_status is in plan order = system order (only the launch order is sorted)
+  for (int64_t i = 0; i < h->count; ++i) {
+    const BatchStatus& s = h->h_status[i];
+    info[i].b = s.b;
+    info[i].info = s.info;
+    info[i].ir_iters = s.ir_iters;
+    info[i].n2x2 = s.n2x2;
+    info[i].berr = s.berr;
+  }
+  return 0;
+}
+
+int rcp_batch_destroy(rcp_batch* h) {
+  batch_free(h);
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,175 @@
+"""GPU: batched systems (one workgroup per system, one captured launch).
+
+Each system is checked against the CPU oracle run with the block size the
+plan recorded for it and the same Omega seed:
+  * FP64 form: permutation and block pattern bit-exact where the oracle's
+    decision log has no near-tie (relative margin > 1e-9), L and D within
+    1e3 n u max(1, |oracle|), the solution within 1e-9 max(1, |x_oracle|) and
+    backward error <= 1e-13;
+  * FP32 form (FP64 refinement): backward error <= 1e-13 and forward error
+    against the oracle's solution <= kappa_inf 1e-12;
+  * the captured graph replays to identical results with eager work on the
+    GPU between the replays.
+Every case prints its name before running.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import rcp as orcp, textbook as tb
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+U = np.finfo(np.float64).eps / 2
+SEED0 = 7 * 2**32
+P = 8
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rcp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1710_00125_amd as pkg
+    pkg.load()
+    return pkg
+
+
+NS = [1, 2, 3, 5, 16, 17, 31, 64, 65, 100, 127, 128, 129, 200, 255, 256, 257, 300, 400, 512]
+
+
+def _systems(ns, nrhs):
+    out = []
+    for i, n in enumerate(ns):
+        s = SEED0 + i
+        if i % 2 == 0 or n < 4:
+            A = gen.gaussian_sym(n, s)
+        else:
+            n1 = (3 * n) // 4
+            A = gen.kkt(n, n1, s, nrefl=min(16, n1))
+        out.append((A, gen.rhs(n, nrhs, s)))
+    return out
+
+
+def _offsets(ns):
+    n1 = np.concatenate([[0], np.cumsum(ns)])
+    n2 = np.concatenate([[0], np.cumsum(np.asarray(ns, dtype=np.int64) ** 2)])
+    return n1, n2
+
+
+def _dmat(D, ipiv):
+    n = len(ipiv)
+    Dm = np.diag(D[:n])
+    for i in range(n - 1):
+        if ipiv[i] == 2:
+            Dm[i + 1, i] = Dm[i, i + 1] = D[n + i]
+    return Dm
+
+
+@pytest.mark.parametrize("autotune", [False, True])
+def test_batched_fp64_matches_oracle(rcp, autotune):
+    nrhs = 4
+    _say(f"batched fp64 autotune={autotune} count={len(NS)}")
+    systems = _systems(NS, nrhs)
+    ns, Ap, Bp = rcp.pack_batch(systems, nrhs)
+    batch = rcp.rcp_batch_create(ns, Ap, Bp, P, SEED0, 0, nrhs, factors=True, autotune=autotune)
+    batch.run()
+    info = batch.info()
+    table = rcp.rcp_batch_get_table(0)
+    _say(f"  table {table}")
+    X = batch.Xpool.cpu().numpy()
+    perm = batch.perm.cpu().numpy()
+    Lp = batch.L.cpu().numpy()
+    Dp = batch.D.cpu().numpy()
+    ip = batch.ipiv.cpu().numpy()
+    n1, n2 = _offsets(ns)
+    for i, (A, B) in enumerate(systems):
+        n = A.shape[0]
+        cls = 0 if n <= 64 else 1 if n <= 128 else 2 if n <= 256 else 3
+        assert info[i]["b"] == min(table[cls], n)
+        assert info[i]["info"] == 0
+        b = info[i]["b"]
+        ref = orcp.factor(A, b, P, seed=SEED0 + i)
+        margin, _ = orcp.min_margin(ref, scale=np.max(np.abs(A)))
+        pi = perm[n1[i]:n1[i + 1]]
+        ii = ip[n1[i]:n1[i + 1]]
+        L = Lp[n2[i]:n2[i + 1]].reshape(n, n).T
+        D = Dp[2 * n1[i]:2 * n1[i + 1]]
+        x = X[n1[i] * nrhs:n1[i + 1] * nrhs].reshape(nrhs, n).T
+        xr = orcp.solve(ref, B)
+        be = np.max(tb.backward_error(A, x, B))
+        _say(f"  system {i}: n={n} b={b} margin={margin:.1e} berr={be:.2e} "
+             f"reported={info[i]['berr']:.2e} n2x2={info[i]['n2x2']}")
+        assert be <= 1e-13
+        assert abs(info[i]["berr"] - be) <= 1e-3 * be + 10 * n * U
+        assert tb.reconstruction_error(A, pi, L, _dmat(D, ii)) <= 50 * n * U
+        if margin > 1e-9:
+            assert np.array_equal(pi, ref.perm)
+            assert np.array_equal(ii, ref.ipiv)
+            tol = 1e3 * n * U
+            assert np.all(np.abs(L - ref.L) <= tol * np.maximum(1.0, np.abs(ref.L)))
+            assert np.all(np.abs(D - ref.D) <= tol * np.maximum(1.0, np.abs(ref.D)))
+            assert np.max(np.abs(x - xr)) <= 1e-9 * max(1.0, np.max(np.abs(xr)))
+    batch.close()
+
+
+def test_batched_fp32_refined(rcp):
+    nrhs = 4
+    _say(f"batched fp32+refinement count={len(NS)}")
+    systems = _systems(NS, nrhs)
+    ns, Ap, Bp = rcp.pack_batch(systems, nrhs)
+    batch = rcp.rcp_batch_create(ns, Ap, Bp, P, SEED0, rcp.RCP_PREC_FP32, nrhs, factors=True,
+                                 autotune=False)
+    batch.run()
+    info = batch.info()
+    X = batch.Xpool.cpu().numpy()
+    n1, _ = _offsets(ns)
+    for i, (A, B) in enumerate(systems):
+        n = A.shape[0]
+        x = X[n1[i] * nrhs:n1[i + 1] * nrhs].reshape(nrhs, n).T
+        be = np.max(tb.backward_error(A, x, B))
+        ref = orcp.factor(A, info[i]["b"], P, seed=SEED0 + i)
+        xr = orcp.solve(ref, B)
+        kappa = np.linalg.cond(tb.sym(A), p=np.inf)
+        ferr = np.max(np.abs(x - xr)) / np.max(np.abs(xr))
+        _say(f"  system {i}: n={n} refinement steps {info[i]['ir_iters']} berr={be:.2e} "
+             f"ferr={ferr:.2e} kappa={kappa:.1e}")
+        assert info[i]["info"] == 0
+        assert be <= 1e-13
+        assert ferr <= kappa * 1e-12
+    batch.close()
+
+
+def test_batched_graph_replays_identical(rcp):
+    import torch
+    nrhs = 2
+    ns_list = [40, 300, 7, 129, 64]
+    _say(f"batched graph replays {ns_list}")
+    systems = _systems(ns_list, nrhs)
+    ns, Ap, Bp = rcp.pack_batch(systems, nrhs)
+    batch = rcp.rcp_batch_create(ns, Ap, Bp, P, SEED0, 0, nrhs, autotune=False)
+    outs = []
+    for rep in range(3):
+        batch.Xpool.zero_()
+        # eager work on the device between the replays
+        junk = torch.randn(512, 512, dtype=torch.float64, device="cuda")
+        (junk @ junk).sum().item()
+        ms = batch.run()
+        outs.append(batch.Xpool.cpu().numpy().copy())
+        _say(f"  replay {rep}: {ms:.3f} ms")
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    n1, _ = _offsets(ns)
+    for i, (A, B) in enumerate(systems):
+        n = A.shape[0]
+        x = outs[0][n1[i] * nrhs:n1[i + 1] * nrhs].reshape(nrhs, n).T
+        assert np.max(tb.backward_error(A, x, B)) <= 1e-13
+    batch.close()
