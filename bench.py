@@ -141,6 +141,45 @@ def mixed_run(rcp, A, b, cfg, name, args, fp64_ms):
     }
 
 
+def batched_run(rcp, count, replays):
+    """The batched workload: `count` systems, n uniform in [16, 512], even
+    indices Gaussian-symmetric, odd ones saddle-point; 4 right-hand sides;
+    one captured launch per batch, replayed `replays` times per form."""
+    import torch
+    from workloads.configs import batched_systems
+    nrhs, p, seed = 4, 8, 5
+    _log(f"bench: generating {count} batched systems on the host")
+    systems = batched_systems(count=count, seed=seed, nrhs=nrhs)
+    ns, Ap, Bp = rcp.pack_batch([(A, B) for _, A, B, _ in systems], nrhs)
+    flops = float(np.sum(ns.astype(np.float64) ** 3) / 3.0)
+    res = {"systems": count, "n_min": int(ns.min()), "n_max": int(ns.max()), "nrhs": nrhs,
+           "p": p, "seed0": seed * 2**32, "gflop_per_batch": round(flops / 1e9, 3)}
+    for name, prec in (("fp64", 0), ("fp32_ir", rcp.RCP_PREC_FP32)):
+        _log(f"bench: batched {name}: plan + autotune")
+        batch = rcp.rcp_batch_create(ns, Ap, Bp, p, seed * 2**32, prec, nrhs, autotune=True)
+        batch.run()
+        times = []
+        for r in range(replays):
+            times.append(batch.run())
+        info = batch.info()
+        t = np.array(times)
+        berr = max(i["berr"] for i in info)
+        res[name] = {
+            "ms_p50": round(float(np.percentile(t, 50)), 3),
+            "ms_p99": round(float(np.percentile(t, 99)), 3),
+            "systems_per_s": round(count / (np.median(t) * 1e-3), 1),
+            "tflops": round(flops / (np.median(t) * 1e-3) / 1e12, 4),
+            "max_backward_error": berr,
+            "zero_pivots": sum(1 for i in info if i["info"] != 0),
+            "table_b_by_class": rcp.rcp_batch_get_table(prec),
+            "max_refinement_steps": max(i["ir_iters"] for i in info),
+        }
+        _log(f"bench: batched {name}: p50 {res[name]['ms_p50']} ms, "
+             f"{res[name]['systems_per_s']} systems/s, max berr {berr:.2e}")
+        batch.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +191,10 @@ def main():
     ap.add_argument("--mixed", default="fp32,bf16x3",
                     help="reduced-precision forms to time after the FP64 one "
                          "(comma list of fp32, bf16x3; empty skips them)")
+    ap.add_argument("--batched", type=int, default=4096, metavar="COUNT",
+                    help="also time the batched form on COUNT systems (0 skips it)")
+    ap.add_argument("--replays", type=int, default=50,
+                    help="graph replays of the batched plan for the latency percentiles")
     ap.add_argument("--cond-sweep", action="store_true",
                     help="also time the reduced-precision forms on the cond 1e2/1e6/1e10 "
                          "matrices of the same generator")
@@ -279,6 +322,8 @@ def main():
                 fp = fp64_time(rcp, Ac, bc, ccfg)
                 out["cond_sweep"][ccfg.name]["fp64_ms"] = fp
                 del Ac, bc
+    if args.batched > 0:
+        out["batched"] = batched_run(rcp, args.batched, args.replays)
     if args.cpu_sample > 0:
         _log(f"bench: timing the CPU oracle on n={args.cpu_sample}")
         out["cpu_baseline"] = cpu_baseline(args.config, args.cpu_sample)

@@ -82,14 +82,11 @@ __device__ __forceinline__ bool key_gt(double av, int ap, double bv, int bp) {
 // largest value, ties to the smaller position; result in every thread
 __device__ void wg_argmax(double& val, int& pos, Shared& sh) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const double ov = __shfl_xor(val, off, 64);
-    const int op = __shfl_xor(pos, off, 64);
-    if (key_gt(ov, op, val, pos)) {
-      val = ov;
-      pos = op;
-    }
+  {
+    ArgKey k{val, pos, 0};
+    k = wave_argmax(k);
+    val = k.val;
+    pos = k.pos;
   }
   if (lane == 0) {
     sh.red_v[w] = val;
@@ -366,8 +363,7 @@ __global__ void __launch_bounds__(kBT) batched_kernel(KernelArgs a) {
           double acc = 0.0;
           const double* x = S.Lp + r * kBldp;
           for (int t = tid; t < kk; t += 64) acc = fma(x[t], sh.wrow2[t], acc);
-#pragma unroll
-          for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+          acc = wave_sum64(acc);
           if (tid == 0) sh.sc[0] = symw(S.W, n, r, r) - acc;
         }
         __syncthreads();
@@ -626,7 +622,7 @@ __device__ void blocked_solve(Sys<TA>& S, int nrhs, double* yv, Shared& sh) {
       for (int t = 0; t < jn; ++t) {
         const double lv = (lane > t && lane < jn) ? (double)S.Lw[(j0 + lane) + (int64_t)(j0 + t) * n] : 0.0;
         for (int c = 0; c < nrhs; ++c) {
-          const double yt = __shfl(yc[c], t, 64);
+          const double yt = bcast_lane(yc[c], t);
           yc[c] = fma(-lv, yt, yc[c]);
         }
       }
@@ -689,7 +685,7 @@ __device__ void blocked_solve(Sys<TA>& S, int nrhs, double* yv, Shared& sh) {
       for (int t = jn - 1; t >= 0; --t) {
         const double lv = (lane < t) ? (double)S.Lw[(j0 + t) + (int64_t)(j0 + lane) * n] : 0.0;
         for (int c = 0; c < nrhs; ++c) {
-          const double yt = __shfl(yc[c], t, 64);
+          const double yt = bcast_lane(yc[c], t);
           yc[c] = fma(-lv, yt, yc[c]);
         }
       }

@@ -20,61 +20,71 @@ namespace {
 
 // ---------------------------------------------------------------------------
 // Bnext(:, i - m) = B(:, srcat[i]) - T L(srcat[i], 0:m)^T for i in [m, N).
-// Matrix-core product: A operand T (lpad x m), B operand L^T of 64 gathered
-// sources.  Wave w of a workgroup owns 16 output columns and all rows.
+// A workgroup owns 64 output columns i and every sketch row; the product is
+// formed transposed, C(i, r) = sum_t L(i, t) T(r, t), so that the 16 lanes
+// of an accumulator column hold 16 consecutive sketch rows and the stores
+// are contiguous.  Both operands go through LDS in chunks of 32 k values:
+// L rows (64 x 32) and T columns (lpad x 32).  Wave w owns columns
+// 16 w .. 16 w + 15 and all row fragments.
 // ---------------------------------------------------------------------------
 constexpr int kSuCols = 64;
-constexpr int kSuRowFrags = 12;   // rows per pass: 192
+constexpr int kSuK = 32;
+constexpr int kSuMaxRowFrags = (kMaxL + 15) / 16;   // 32
 
+template <int NRF>
 __global__ void __launch_bounds__(256) sketch_update_kernel(
     const double* __restrict__ B, int lpad, int l, const int* __restrict__ srcat, int m, int N,
     const double* __restrict__ Lp, int ldp, const double* __restrict__ T,
     double* __restrict__ Bnext) {
   extern __shared__ double smem[];
-  const int mq = (m + 3) & ~3;
-  const int lds_ld = mq + 1;
-  double* Ls = smem;   // [64][mq+1]  L rows of my columns, zero padded in t
+  double* Ls = smem;                          // [64][kSuK + 1]   L(i, t)
+  double* Ts = Ls + kSuCols * (kSuK + 1);     // [kSuK][lpad + 1] T(r, t) by t
+  const int ldt = lpad + 1;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int i0 = m + blockIdx.x * kSuCols;
-  for (int e = tid; e < kSuCols * mq; e += 256) {
-    const int cc = e / mq, t = e - cc * mq;
-    const int i = i0 + cc;
-    double v = 0.0;
-    if (i < N && t < m) v = Lp[(size_t)srcat[i] * ldp + t];
-    Ls[cc * lds_ld + t] = v;
-  }
-  __syncthreads();
   const int nrf = lpad / 16;
-  for (int rf0 = 0; rf0 < nrf; rf0 += kSuRowFrags) {
-    rcp_d4 acc[kSuRowFrags];
+  rcp_d4 acc[NRF];
 #pragma unroll
-    for (int f = 0; f < kSuRowFrags; ++f) acc[f] = rcp_d4{0.0, 0.0, 0.0, 0.0};
-    for (int q = 0; q < mq / 4; ++q) {
+  for (int f = 0; f < NRF; ++f) acc[f] = rcp_d4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < m; k0 += kSuK) {
+    const int kn = min(kSuK, m - k0);
+    __syncthreads();
+    for (int e = tid; e < kSuCols * kSuK; e += 256) {
+      const int cc = e / kSuK, t = e - cc * kSuK;
+      const int i = i0 + cc;
+      Ls[cc * (kSuK + 1) + t] =
+          (i < N && t < kn) ? Lp[(size_t)srcat[i] * ldp + k0 + t] : 0.0;
+    }
+    for (int e = tid; e < kSuK * lpad; e += 256) {
+      const int t = e / lpad, r = e - t * lpad;
+      Ts[t * ldt + r] = (t < kn) ? T[(size_t)(k0 + t) * lpad + r] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kSuK / 4; ++q) {
       const int t = 4 * q + frag_k(lane);
-      // A operand: L(column 16 w + l%16 of this workgroup, t)
-      const double av = Ls[(16 * w + frag_row(lane)) * lds_ld + t];
+      // A operand: L(column 16 w + l%16, t); B operand: T(row 16 f + l%16, t)
+      const double av = Ls[(16 * w + frag_row(lane)) * (kSuK + 1) + t];
 #pragma unroll
-      for (int f = 0; f < kSuRowFrags; ++f) {
-        if (rf0 + f < nrf) {
-          // B operand: T(r, t) for r = 16 (rf0 + f) + l%16
-          const double bv = (t < m) ? T[(size_t)t * lpad + 16 * (rf0 + f) + frag_col(lane)] : 0.0;
+      for (int f = 0; f < NRF; ++f) {
+        if (f < nrf) {
+          const double bv = Ts[t * ldt + 16 * f + frag_col(lane)];
           acc[f] = mfma16x16x4(av, bv, acc[f]);
         }
       }
     }
-    // acc[f]: lane l, element v = (column 16 w + l/16 + 4 v, row 16 (rf0 + f) + l%16)
+  }
+  // acc[f]: lane l, element v = (column 16 w + l/16 + 4 v, row 16 f + l%16)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int ocol = 16 * w + acc_row(lane, v);
-      const int i = i0 + ocol;
-      if (i >= N) continue;
-      const int s = srcat[i];
+  for (int v = 0; v < 4; ++v) {
+    const int i = i0 + 16 * w + acc_row(lane, v);
+    if (i >= N) continue;
+    const int s = srcat[i];
 #pragma unroll
-      for (int f = 0; f < kSuRowFrags; ++f) {
-        if (rf0 + f < nrf) {
-          const int r = 16 * (rf0 + f) + acc_col(lane);
-          Bnext[(size_t)(i - m) * lpad + r] = (r < l) ? B[(size_t)s * lpad + r] - acc[f][v] : 0.0;
-        }
+    for (int f = 0; f < NRF; ++f) {
+      if (f < nrf) {
+        const int r = 16 * f + acc_col(lane);
+        Bnext[(size_t)(i - m) * lpad + r] = (r < l) ? B[(size_t)s * lpad + r] - acc[f][v] : 0.0;
       }
     }
   }
@@ -205,12 +215,20 @@ void launch_sketch_update(const double* B, int lpad, int l, const int* srcat, in
                           hipStream_t s) {
   const int N2 = N - m;
   if (N2 <= 0) return;
-  const int mq = (m + 3) & ~3;
-  const size_t lds = (size_t)kSuCols * (mq + 1) * 8;
-  hipFuncSetAttribute((const void*)sketch_update_kernel,
-                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(sketch_update_kernel, dim3((N2 + kSuCols - 1) / kSuCols), dim3(256), lds, s,
-                     B, lpad, l, srcat, m, N, Lpanel, ldp, T, Bnext);
+  const size_t lds = ((size_t)kSuCols * (kSuK + 1) + (size_t)kSuK * (lpad + 1)) * 8;
+  const dim3 grid((N2 + kSuCols - 1) / kSuCols);
+  auto go = [&](auto kern) {
+    hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, B, lpad, l, srcat, m, N, Lpanel, ldp, T,
+                       Bnext);
+  };
+  // accumulators sized for the sketch height (lpad / 16 fragments)
+  const int nrf = lpad / 16;
+  if (nrf <= 4) go(sketch_update_kernel<4>);
+  else if (nrf <= 8) go(sketch_update_kernel<8>);
+  else if (nrf <= 12) go(sketch_update_kernel<12>);
+  else if (nrf <= 16) go(sketch_update_kernel<16>);
+  else go(sketch_update_kernel<kSuMaxRowFrags>);
 }
 
 int update_k_frags(int prec, int m) { return prec == kPrecBF16x3 ? (m + 31) / 32 : (m + 3) / 4; }

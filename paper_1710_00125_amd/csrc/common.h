@@ -76,6 +76,57 @@ __device__ __forceinline__ void grid_barrier(unsigned int* flags, unsigned int& 
 }
 
 // ---------------------------------------------------------------------------
+// Lane exchanges on the VALU, without LDS traffic: the partner value of a
+// butterfly stage of width K.  K = 1, 2: xor through DPP quad permutes;
+// K = 4, 8: DPP half-row / row mirrors (lane i <-> 7 - i within 8, 15 - i
+// within 16), which equal the xor partner whenever the values are uniform
+// in groups of K -- as they are at that stage of a butterfly; K = 16, 32:
+// xor through the gfx950 permlane swaps.  (The lane maps were checked on
+// the hardware.)
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int K>
+__device__ __forceinline__ int xchg_i(int v);
+template <>
+__device__ __forceinline__ int xchg_i<1>(int v) { return dpp_i<0xB1>(v); }
+template <>
+__device__ __forceinline__ int xchg_i<2>(int v) { return dpp_i<0x4E>(v); }
+template <>
+__device__ __forceinline__ int xchg_i<4>(int v) { return dpp_i<0x141>(v); }
+template <>
+__device__ __forceinline__ int xchg_i<8>(int v) { return dpp_i<0x140>(v); }
+template <>
+__device__ __forceinline__ int xchg_i<16>(int v) {
+  const auto r = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+  return (int)((threadIdx.x & 16) ? r[0] : r[1]);
+}
+template <>
+__device__ __forceinline__ int xchg_i<32>(int v) {
+  const auto r = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+  return (int)((threadIdx.x & 32) ? r[0] : r[1]);
+}
+template <int K>
+__device__ __forceinline__ double xchg(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const int lo = xchg_i<K>((int)(unsigned)u);
+  const int hi = xchg_i<K>((int)(unsigned)(u >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                          (unsigned long long)(unsigned)lo));
+}
+
+// value of lane `lane` (uniform across the wave) broadcast through scalar
+// registers
+__device__ __forceinline__ double bcast_lane(double v, int lane) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, lane);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// ---------------------------------------------------------------------------
 // Argmax keys.  A candidate is (value, position); larger value wins, equal
 // values go to the smaller position (the paper's smallest-index rule).
 // value < 0 marks "no candidate".
@@ -91,12 +142,24 @@ __device__ __forceinline__ bool key_better(const ArgKey& a, const ArgKey& b) {
   return a.pos < b.pos;
 }
 
-__device__ __forceinline__ ArgKey shfl_key(const ArgKey& k, int src_lane) {
+template <int K>
+__device__ __forceinline__ void argmax_stage(ArgKey& k) {
   ArgKey o;
-  o.val = __shfl(k.val, src_lane, RCP_WAVE);
-  o.pos = __shfl(k.pos, src_lane, RCP_WAVE);
-  o.idx = __shfl(k.idx, src_lane, RCP_WAVE);
-  return o;
+  o.val = xchg<K>(k.val);
+  o.pos = xchg_i<K>(k.pos);
+  o.idx = xchg_i<K>(k.idx);
+  if (key_better(o, k)) k = o;
+}
+
+// argmax over the 64 lanes of a wave; the result is in every lane
+__device__ __forceinline__ ArgKey wave_argmax(ArgKey k) {
+  argmax_stage<1>(k);
+  argmax_stage<2>(k);
+  argmax_stage<4>(k);
+  argmax_stage<8>(k);
+  argmax_stage<16>(k);
+  argmax_stage<32>(k);
+  return k;
 }
 
 // Workgroup-wide argmax; the result is returned to every thread.
@@ -104,11 +167,7 @@ __device__ __forceinline__ ArgKey shfl_key(const ArgKey& k, int src_lane) {
 __device__ __forceinline__ ArgKey block_argmax(ArgKey k, ArgKey* sh) {
   const int lane = threadIdx.x & (RCP_WAVE - 1);
   const int wid = threadIdx.x / RCP_WAVE;
-#pragma unroll
-  for (int off = RCP_WAVE / 2; off > 0; off >>= 1) {
-    ArgKey o = shfl_key(k, lane ^ off);
-    if (key_better(o, k)) k = o;
-  }
+  k = wave_argmax(k);
   if (lane == 0) sh[wid] = k;
   __syncthreads();
   ArgKey best = sh[0];
@@ -119,11 +178,21 @@ __device__ __forceinline__ ArgKey block_argmax(ArgKey k, ArgKey* sh) {
   return best;
 }
 
+// sum over the 64 lanes of a wave (butterfly); the result is in every lane
+__device__ __forceinline__ double wave_sum64(double v) {
+  v += xchg<1>(v);
+  v += xchg<2>(v);
+  v += xchg<4>(v);
+  v += xchg<8>(v);
+  v += xchg<16>(v);
+  v += xchg<32>(v);
+  return v;
+}
+
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   const int lane = threadIdx.x & (RCP_WAVE - 1);
   const int wid = threadIdx.x / RCP_WAVE;
-#pragma unroll
-  for (int off = RCP_WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, RCP_WAVE);
+  v = wave_sum64(v);
   if (lane == 0) sh[wid] = v;
   __syncthreads();
   double s = 0.0;
@@ -173,8 +242,8 @@ __device__ __forceinline__ T dot16_quad(const T* __restrict__ x, const T* __rest
   const T a = dot_chunk16(x, y, i, 4 * q), b = dot_chunk16(x, y, i, 4 * q + 1);
   const T c = dot_chunk16(x, y, i, 4 * q + 2), d = dot_chunk16(x, y, i, 4 * q + 3);
   T v = (a + b) + (c + d);
-  v += __shfl_xor(v, 1, 4);
-  v += __shfl_xor(v, 2, 4);
+  v += xchg<1>(v);
+  v += xchg<2>(v);
   return v;
 }
 
@@ -183,10 +252,10 @@ template <typename T>
 __device__ __forceinline__ T dot16_lanes(const T* __restrict__ x, const T* __restrict__ y, int i,
                                          int j) {
   T v = dot_chunk16(x, y, i, j);
-  v += __shfl_xor(v, 1, 16);
-  v += __shfl_xor(v, 2, 16);
-  v += __shfl_xor(v, 4, 16);
-  v += __shfl_xor(v, 8, 16);
+  v += xchg<1>(v);
+  v += xchg<2>(v);
+  v += xchg<4>(v);
+  v += xchg<8>(v);
   return v;
 }
 

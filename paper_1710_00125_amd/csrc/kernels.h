@@ -115,7 +115,8 @@ void launch_commit(const int* srcat, int m, int N, int K0, int64_t n, const doub
 // ---- update.hip  (trailing Schur complement on the matrix cores)
 // Anext(i, j) = Acur(rowsrc[i], rowsrc[j]) - sum_t L21(i,t) W21(j,t), 0 <= j <= i < N2
 void launch_update(const void* Acur, void* Anext, int64_t ld, const int* rowsrc, int N2,
-                   const void* L21p, const void* W21p, int Qk, int prec, hipStream_t s);
+                   const void* L21p, const void* W21p, int Qk, int prec, int num_cu,
+                   hipStream_t s);
 
 // ---- solve.hip
 // L (n x n col-major) from Lwork rows by original index, final perm P

@@ -45,6 +45,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kRowsPerPass = kThreads / 4;
+constexpr int kMaxG = 256;   // workgroups of one launch (one per CU at most)
 
 struct PanelParams {
   PanelArgs a;
@@ -89,33 +90,6 @@ __device__ __forceinline__ bool rec_better(const Rec& a, const Rec& b) {
   return a.pos < b.pos;
 }
 
-__device__ __forceinline__ Rec shfl_rec(const Rec& r, int lane) {
-  Rec o;
-  o.val = __shfl(r.val, lane, 64);
-  o.pos = __shfl(r.pos, lane, 64);
-  o.src = __shfl(r.src, lane, 64);
-  o.ark = __shfl(r.ark, lane, 64);
-  o.arr = __shfl(r.arr, lane, 64);
-  o.g = __shfl(r.g, lane, 64);
-  return o;
-}
-
-__device__ __forceinline__ Rec block_best_rec(Rec r, Rec* sh) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    Rec o = shfl_rec(r, lane ^ off);
-    if (rec_better(o, r)) r = o;
-  }
-  if (lane == 0) sh[wid] = r;
-  __syncthreads();
-  Rec best = sh[0];
-  for (int w = 1; w < kThreads / 64; ++w)
-    if (rec_better(sh[w], best)) best = sh[w];
-  __syncthreads();
-  return best;
-}
-
 // TA: element type of the stored trailing matrix (double, or float in the
 // reduced-precision modes; values are widened to FP64 on load)
 template <typename TA>
@@ -143,8 +117,9 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
   int* kind = (int*)(Tl + (size_t)ntr * ldt);   // [ldp]
   int* posl = kind + ldp;                   // [R]
   int* win = posl + R;                      // [bb + 2]
-  __shared__ Rec shr[kThreads / 64];
   __shared__ ArgKey shk[kThreads / 64];
+  __shared__ int sh_rsrc[2][kMaxG];
+  __shared__ double sh_rark[2][kMaxG], sh_rarr[2][kMaxG];
   __shared__ double sh_akk, sh_Acc, sh_A1c, sh_A2c, sh_A11, sh_A22, sh_Anr;
   __shared__ double sh_vn, sh_vrn;
   __shared__ int sh_pend_n, sh_pend_t, sh_pend_s1, sh_pend_s2;
@@ -279,16 +254,15 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
     grid_wait(P.ex.bar, epoch, P.G, P.ex.abort_flag);
 
     // ---- phase B: every record in one round trip, the same decision everywhere
-    Rec rc{-1.0, INT_MAX, -1, 0.0, 0.0, -1};
+    // keys (value, position, workgroup) are reduced on the VALU; the rest
+    // of the winning record is looked up by workgroup afterwards
+    ArgKey rk{-1.0, INT_MAX, -1};
     for (int w = tid; w < P.G; w += kThreads) {
-      Rec o;
-      o.val = ld_agent(&P.ex.val[par * P.G + w]);
-      o.pos = ld_agent(&P.ex.pos[par * P.G + w]);
-      o.src = ld_agent(&P.ex.src[par * P.G + w]);
-      o.ark = ld_agent(&P.ex.aux0[par * P.G + w]);
-      o.arr = ld_agent(&P.ex.aux1[par * P.G + w]);
-      o.g = w;
-      if (rec_better(o, rc)) rc = o;
+      ArgKey o{ld_agent(&P.ex.val[par * P.G + w]), ld_agent(&P.ex.pos[par * P.G + w]), w};
+      sh_rsrc[par][w] = ld_agent(&P.ex.src[par * P.G + w]);
+      sh_rark[par][w] = ld_agent(&P.ex.aux0[par * P.G + w]);
+      sh_rarr[par][w] = ld_agent(&P.ex.aux1[par * P.G + w]);
+      if (key_better(o, rk)) rk = o;
     }
     // L rows of the two window candidates for the next pivot (entries < k
     // were stored by their owners before this step's barrier)
@@ -296,7 +270,13 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
       if (c1 >= 0) Ln1[t] = ld_agent(&a.Lpanel[(size_t)c1 * ldp + t]);
       if (c2 >= 0) Ln2[t] = ld_agent(&a.Lpanel[(size_t)c2 * ldp + t]);
     }
-    rc = block_best_rec(rc, shr);
+    rk = block_argmax(rk, shk);
+    Rec rc{rk.val, rk.pos, -1, 0.0, 0.0, rk.idx};
+    if (rk.idx >= 0) {
+      rc.src = sh_rsrc[par][rk.idx];
+      rc.ark = sh_rark[par][rk.idx];
+      rc.arr = sh_rarr[par][rk.idx];
+    }
     const double akk = sh_akk;
     const double lam = rc.val >= 0.0 ? rc.val : 0.0;
     const int rpos = rc.pos, rsrc = rc.src;
@@ -506,7 +486,7 @@ int panel_grid(int N, int ldp, int lpad, int num_cu, size_t* lds_bytes, int* ntr
     const int ntr = (lpad + gg - 1) / gg;
     return panel_lds((N + gg - 1) / gg, ldp, ldp, ntr, ldp);
   };
-  while (G < num_cu && lds_of(G) > 150 * 1024) ++G;
+  while (G < num_cu && lds_of(G) > 140 * 1024) ++G;
   *lds_bytes = lds_of(G);
   *ntr_out = (lpad + G - 1) / G;
   return G;

@@ -86,20 +86,46 @@ Prof g_profiler;
 struct Scope {
   int cls;
   int e0 = -1;
-  Scope(int c) : cls(c) {
+  hipStream_t st;
+  explicit Scope(int c, hipStream_t stream = nullptr) : cls(c), st(stream ? stream : g_stream) {
     if (g_prof) {
       e0 = (int)g_profiler.used;
-      hipEventRecord(g_profiler.get(), g_stream);
+      hipEventRecord(g_profiler.get(), st);
     }
   }
   ~Scope() {
     if (g_prof) {
       const int e1 = (int)g_profiler.used;
-      hipEventRecord(g_profiler.get(), g_stream);
+      hipEventRecord(g_profiler.get(), st);
       g_profiler.marks.push_back({cls, {e0, e1}});
     }
   }
 };
+
+// Second stream of the factorization: the trailing update of block j runs
+// there while the main stream already runs the QRCP selection of block j+1
+// (which needs only the updated sketch).  One per device, created once.
+struct SideStream {
+  int device = -1;
+  hipStream_t s = nullptr;
+  hipEvent_t committed = nullptr, updated = nullptr;
+};
+SideStream g_side;
+
+bool side_stream_ready(int dev) {
+  if (g_side.s && g_side.device == dev) return true;
+  if (g_side.s) {
+    hipStreamDestroy(g_side.s);
+    hipEventDestroy(g_side.committed);
+    hipEventDestroy(g_side.updated);
+    g_side = SideStream();
+  }
+  if (hipStreamCreateWithFlags(&g_side.s, hipStreamNonBlocking) != hipSuccess) return false;
+  if (hipEventCreateWithFlags(&g_side.committed, hipEventDisableTiming) != hipSuccess) return false;
+  if (hipEventCreateWithFlags(&g_side.updated, hipEventDisableTiming) != hipSuccess) return false;
+  g_side.device = dev;
+  return true;
+}
 
 void collect_profile() {
   double* dst[KNum] = {&g_stats.ms_omega, &g_stats.ms_sketch, &g_stats.ms_select,
@@ -188,11 +214,12 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
   {
     const int Gs = select_grid((int)n, lpad, ncu);
     const int Rs = (int)((n + Gs - 1) / Gs);
-    if ((size_t)Rs * (l | 1) * 8 + (size_t)lpad * 8 + 4096 > 150 * 1024) return RCP_EUNSUPPORTED;
+    if ((size_t)Rs * (l | 1) * 8 + (size_t)lpad * 8 + (size_t)Rs * 12 + 4096 > 140 * 1024)
+      return RCP_EUNSUPPORTED;
     size_t lds = 0;
     int ngr = 0;
-    panel_grid((int)n, ldp, lpad, ncu, &lds, &ngr);
-    if (lds > 150 * 1024) return RCP_EUNSUPPORTED;
+    const int Gp = panel_grid((int)n, ldp, lpad, ncu, &lds, &ngr);
+    if (lds > 140 * 1024 || Gp > 256) return RCP_EUNSUPPORTED;
   }
   const int Gmax = ncu;
   const int vec_stride = std::max(lpad, ldp);
@@ -272,15 +299,24 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
   int64_t K0 = 0;
   int nblocks = 0;
   int status = 0;
+  if (!side_stream_ready(dev)) return RCP_EDEVICE;
+  hipStream_t s2 = g_side.s;
+  bool update_in_flight = false;
+  bool selected = false;   // the selection of the current block is enqueued
+  auto enqueue_select = [&](int Nb) {
+    Scope sc(KSelect);
+    const int Gs = select_grid(Nb, lpad, ncu);
+    hipMemsetAsync(ex.bar, 0, (size_t)Gmax * 128, s);
+    launch_select(Bc, lpad, l, Nb, std::min<int>(b, Nb), posof, win, ex, Gs, s);
+  };
   while (K0 < n) {
     const int N = (int)(n - K0);
     const int bb = std::min<int>(b, N);
-    {
-      Scope sc(KSelect);
-      const int Gs = select_grid(N, lpad, ncu);
-      hipMemsetAsync(ex.bar, 0, (size_t)Gmax * 128, s);
-      launch_select(Bc, lpad, l, N, bb, posof, win, ex, Gs, s);
-    }
+    if (!selected) enqueue_select(N);
+    selected = false;
+    // the panel reads the trailing matrix: the previous block's update first
+    if (update_in_flight) RCP_CHECK(hipStreamWaitEvent(s, g_side.updated, 0));
+    update_in_flight = false;
     {
       Scope sc(KPanel);
       size_t lds = 0;
@@ -339,9 +375,15 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
                     W21p, Qk, rows_pad, rowsrc, s);
     }
     if (N2 > 0) {
-      Scope sc(KUpdate);
-      launch_update(Ac + (size_t)(K0 + K0 * n) * esz, An + (size_t)(K1 + K1 * n) * esz, n, rowsrc,
-                    N2, L21p, W21p, Qk, prec, s);
+      RCP_CHECK(hipEventRecord(g_side.committed, s));
+      RCP_CHECK(hipStreamWaitEvent(s2, g_side.committed, 0));
+      {
+        Scope sc(KUpdate, s2);
+        launch_update(Ac + (size_t)(K0 + K0 * n) * esz, An + (size_t)(K1 + K1 * n) * esz, n,
+                      rowsrc, N2, L21p, W21p, Qk, prec, ncu, s2);
+      }
+      RCP_CHECK(hipEventRecord(g_side.updated, s2));
+      update_in_flight = true;
       g_stats.launches_update += 1;
       g_stats.flops_update += (double)N2 * (N2 + 1) * m;           // lower triangle, 2m per entry
       g_stats.bytes_update += (double)N2 * (N2 + 1) / 2 * 2.0 * esz;   // read + write of each entry
@@ -352,7 +394,14 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
     std::swap(Bc, Bn);
     K0 = K1;
     ++nblocks;
+    // the next block's selection needs only the updated sketch: it runs
+    // while the trailing update proceeds on the second stream
+    if (N2 > 0) {
+      enqueue_select(N2);
+      selected = true;
+    }
   }
+  if (update_in_flight) RCP_CHECK(hipStreamWaitEvent(s, g_side.updated, 0));
   if (status == 0) {
     Scope sc(KFinal);
     launch_finalize_L(n, Lwork, Pc, ipiv, L, prec != kPrecF64, s);
@@ -362,6 +411,7 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
   hipEventRecord(t1, s);
   RCP_CHECK(hipGetLastError());
   RCP_CHECK(hipStreamSynchronize(s));
+  RCP_CHECK(hipStreamSynchronize(s2));
   float ms = 0.f;
   hipEventElapsedTime(&ms, t0, t1);
   hipEventDestroy(t0);

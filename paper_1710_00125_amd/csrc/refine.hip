@@ -22,11 +22,7 @@ namespace {
 constexpr int kT = 64;             // tile edge
 constexpr int kChunkTiles = 16;    // tiles per workgroup along a strip
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum64(v); }
 
 // ABS = true: |A| and x = 1 (row sums of |A|); NR = right-hand sides.
 // Per tile every thread loads 16 entries of one row (a wave reads 16 column

@@ -4,9 +4,12 @@
 //
 // Step j takes the column whose residual B(j:l, c) -- after the j
 // Householder reflections so far -- has the largest 2-norm (squared norms
-// compared, recomputed each step; ties to the smallest position), moves it
-// to position j by one transposition, and reflects the remaining columns
-// with the Householder vector of the taken one.
+// compared, recomputed each step from the reflected entries; ties to the
+// smallest position), moves it to position j by one transposition, and
+// reflects the remaining columns with the Householder vector of the taken
+// one.  The squared norm of each reflected column is formed in the same
+// pass over its entries, and the reflector's scalars come from the winner's
+// squared norm, so a step makes one sweep over the slab.
 //
 // One persistent launch of G workgroups.  Workgroup g owns the sources
 // (columns at block start) [g R, g R + R) and keeps their l x R slab of B in
@@ -26,39 +29,6 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kColsPerPass = 64;   // a quad of lanes per column
 
-// one workgroup's candidate as read back after the barrier
-struct SelRec {
-  double val;   // squared residual norm, -1 if none
-  int pos;      // position of the column
-  int g;        // publishing workgroup
-  int src;      // source of the column
-};
-
-__device__ __forceinline__ bool sel_better(const SelRec& a, const SelRec& b) {
-  if (a.val != b.val) return a.val > b.val;
-  return a.pos < b.pos;
-}
-
-__device__ __forceinline__ SelRec block_best_sel(SelRec r, SelRec* sh) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    SelRec o;
-    o.val = __shfl(r.val, lane ^ off, 64);
-    o.pos = __shfl(r.pos, lane ^ off, 64);
-    o.g = __shfl(r.g, lane ^ off, 64);
-    o.src = __shfl(r.src, lane ^ off, 64);
-    if (sel_better(o, r)) r = o;
-  }
-  if (lane == 0) sh[wid] = r;
-  __syncthreads();
-  SelRec best = sh[0];
-  for (int w = 1; w < (int)(blockDim.x / 64); ++w)
-    if (sel_better(sh[w], best)) best = sh[w];
-  __syncthreads();
-  return best;
-}
-
 struct SelectParams {
   const double* B;
   int lpad, l, N, bb, G, R;
@@ -67,6 +37,13 @@ struct SelectParams {
   Exchange ex;
 };
 
+// quad of lanes, rows [r0, r1) of one column each: sum of squares / dot
+__device__ __forceinline__ double quad_sum(double v) {
+  v += xchg<1>(v);
+  v += xchg<2>(v);
+  return v;
+}
+
 __global__ void __launch_bounds__(kThreads) select_kernel(SelectParams a) {
   extern __shared__ double smem[];
   const int R = a.R;
@@ -74,11 +51,13 @@ __global__ void __launch_bounds__(kThreads) select_kernel(SelectParams a) {
   const int lp = l | 1;                        // odd column stride in LDS
   double* Rs = smem;                           // [R][lp]  residual slab, by column
   double* x = Rs + (size_t)R * lp;             // [lpad] winner residual / Householder v
-  int* posl = (int*)(x + a.lpad);              // [R]
+  double* nrm = x + a.lpad;                    // [R] squared residual norms of my columns
+  int* posl = (int*)(nrm + R);                 // [R]
   int* win = posl + R;                         // [bb+2]
   __shared__ ArgKey shk[kThreads / 64];
-  __shared__ SelRec shs[kThreads / 64];
-  __shared__ double sh_beta;
+  __shared__ ArgKey shr[kThreads / 64];
+  __shared__ int sh_src[2][1024];
+  __shared__ int sh_sw;
 
   const int tid = threadIdx.x;
   const int g = blockIdx.x;
@@ -95,30 +74,29 @@ __global__ void __launch_bounds__(kThreads) select_kernel(SelectParams a) {
   for (int c = tid; c < R; c += kThreads) posl[c] = s0 + c;
   for (int t = tid; t <= a.bb; t += kThreads) win[t] = t;
   __syncthreads();
-
-  const int nsteps = min(min(a.bb, l), a.N);
-  for (int j = 0; j < nsteps; ++j) {
-    const int par = j & 1;
-    const int rows = l - j;
-    const int cs = (rows + 3) >> 2;
-    const int r0 = j + q * cs, r1 = min(l, r0 + cs);
-    // ---- residual norms of my untaken columns (rows j..l-1), a quad per column
-    ArgKey best{-1.0, 0x7fffffff, -1};
+  // squared norms of the full columns (step 0)
+  {
+    const int cs = (l + 3) >> 2;
+    const int r0 = q * cs, r1 = min(l, r0 + cs);
     for (int cb = 0; cb < nown; cb += kColsPerPass) {
       const int c = cb + cq;
       double part = 0.0;
       if (c < nown)
-        for (int b = r0; b < r1; b += 8) {
-          double vs[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) vs[u] = (b + u < r1) ? Rs[c * lp + b + u] : 0.0;
-#pragma unroll
-          for (int u = 0; u < 8; ++u) part = fma(vs[u], vs[u], part);
-        }
-      part += __shfl_xor(part, 1, 4);
-      part += __shfl_xor(part, 2, 4);
-      if (q == 0 && c < nown && posl[c] >= j) {
-        ArgKey k{part, posl[c], s0 + c};
+        for (int i = r0; i < r1; ++i) part = fma(Rs[c * lp + i], Rs[c * lp + i], part);
+      part = quad_sum(part);
+      if (q == 0 && c < nown) nrm[c] = part;
+    }
+  }
+  __syncthreads();
+
+  const int nsteps = min(min(a.bb, l), a.N);
+  for (int j = 0; j < nsteps; ++j) {
+    const int par = j & 1;
+    // ---- my best untaken column (position >= j) by squared residual norm
+    ArgKey best{-1.0, 0x7fffffff, -1};
+    for (int c = tid; c < nown; c += kThreads) {
+      if (posl[c] >= j) {
+        ArgKey k{nrm[c], posl[c], s0 + c};
         if (key_better(k, best)) best = k;
       }
     }
@@ -135,19 +113,19 @@ __global__ void __launch_bounds__(kThreads) select_kernel(SelectParams a) {
       for (int i = j + tid; i < l; i += kThreads) st_agent(&dst[i], Rs[c * lp + i]);
     }
     grid_barrier(a.ex.bar, epoch, a.G, a.ex.abort_flag);
-    // ---- global winner (identical in every workgroup); the record's
-    // source travels with it, so one round trip reads all but the residual
-    SelRec cand{-1.0, 0x7fffffff, -1, -1};
+    // ---- global winner (identical in every workgroup): keys reduced on the
+    // VALU, the winner's source looked up by workgroup afterwards
+    ArgKey cand{-1.0, 0x7fffffff, -1};
     for (int w = tid; w < a.G; w += kThreads) {
-      SelRec o{ld_agent(&a.ex.val[par * a.G + w]), ld_agent(&a.ex.pos[par * a.G + w]), w,
-               ld_agent(&a.ex.src[par * a.G + w])};
-      if (sel_better(o, cand)) cand = o;
+      ArgKey o{ld_agent(&a.ex.val[par * a.G + w]), ld_agent(&a.ex.pos[par * a.G + w]), w};
+      sh_src[par][w] = ld_agent(&a.ex.src[par * a.G + w]);
+      if (key_better(o, cand)) cand = o;
     }
-    cand = block_best_sel(cand, shs);
+    cand = block_argmax(cand, shr);
     if (cand.val <= 0.0) break;   // all residuals zero: no further pivots
-    const int gw = cand.g;
+    const int gw = cand.idx;
     const int pw = cand.pos;
-    const int sw = cand.src;
+    const int sw = sh_src[par][gw];
     const double* xv = a.ex.vec + ((size_t)par * a.G + gw) * a.ex.vec_stride;
     for (int i = j + tid; i < l; i += kThreads) x[i] = ld_agent(&xv[i]);
     // ---- transposition: the winner goes to position j
@@ -158,62 +136,63 @@ __global__ void __launch_bounds__(kThreads) select_kernel(SelectParams a) {
         else if (s0 + c == sj) posl[c] = pw;
       }
     __syncthreads();
-    // ---- Householder vector v = x + sign(x_j) ||x|| e_j and beta = 2 / v.v
-    // (one wave; every workgroup forms the same bits)
-    if (tid < 64) {
-      double ss = 0.0;
-      for (int i = j + tid; i < l; i += 64) ss = fma(x[i], x[i], ss);
-      for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
-      const double xj = x[j];
-      const double vj = xj + copysign(sqrt(ss), xj);
-      double vv = 0.0;
-      for (int i = j + tid; i < l; i += 64) {
-        const double vi = (i == j) ? vj : x[i];
-        vv = fma(vi, vi, vv);
-      }
-      for (int off = 32; off > 0; off >>= 1) vv += __shfl_xor(vv, off, 64);
-      if (tid == 0) {
-        x[j] = vj;
-        sh_beta = 2.0 / vv;
-        if (pw != j) {
-          win[j] = sw;
-          if (pw <= a.bb) win[pw] = sj;
-        }
-      }
+    if (tid == 0 && pw != j) {
+      win[j] = sw;
+      if (pw <= a.bb) win[pw] = sj;
     }
-    __syncthreads();
-    const double beta = sh_beta;
-    // ---- reflect my untaken columns, a quad per column
-    for (int cb = 0; cb < nown; cb += kColsPerPass) {
-      const int c = cb + cq;
-      const bool live = c < nown && posl[c] > j;
-      double part = 0.0;
-      if (live)
-        for (int b = r0; b < r1; b += 8) {
-          double xs[8], vs[8];
+    // ---- Householder v = x + sign(x_j) ||x|| e_j, beta = 2 / v.v =
+    // 1 / (||x|| (||x|| + |x_j|)), from the winner's published squared norm
+    const double nx = sqrt(cand.val);
+    const double xj = x[j];
+    const double vj = xj + copysign(nx, xj);
+    const double beta = 1.0 / (nx * (nx + fabs(xj)));
+    // ---- reflect my untaken columns and form their next squared norms
+    // (rows j+1 .. l-1) in the same pass, a quad per column; the LDS loads
+    // of eight rows are issued before their arithmetic
+    const int cs = (l - j + 3) >> 2;
+    const int r0 = j + q * cs, r1 = min(l, r0 + cs);
+    {
+      for (int cb = 0; cb < nown; cb += kColsPerPass) {
+        const int c = cb + cq;
+        const bool live = c < nown && posl[c] > j;
+        double dot = 0.0;
+        if (live)
+          for (int b = r0; b < r1; b += 8) {
+            double xs[8], rs[8];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            xs[u] = (b + u < r1) ? x[b + u] : 0.0;
-            vs[u] = (b + u < r1) ? Rs[c * lp + b + u] : 0.0;
+            for (int u = 0; u < 8; ++u) {
+              const int i = b + u;
+              xs[u] = (i < r1) ? (i == j ? vj : x[i]) : 0.0;
+              rs[u] = (i < r1) ? Rs[c * lp + i] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) dot = fma(xs[u], rs[u], dot);
           }
+        dot = quad_sum(dot);
+        double part = 0.0;
+        if (live) {
+          const double gmm = beta * dot;
+          for (int b = r0; b < r1; b += 8) {
+            double xs[8], rs[8];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) part = fma(xs[u], vs[u], part);
-        }
-      part += __shfl_xor(part, 1, 4);
-      part += __shfl_xor(part, 2, 4);
-      if (live) {
-        const double gmm = beta * part;
-        for (int b = r0; b < r1; b += 8) {
-          double xs[8], vs[8];
+            for (int u = 0; u < 8; ++u) {
+              const int i = b + u;
+              xs[u] = (i < r1) ? (i == j ? vj : x[i]) : 0.0;
+              rs[u] = (i < r1) ? Rs[c * lp + i] : 0.0;
+            }
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            xs[u] = (b + u < r1) ? x[b + u] : 0.0;
-            vs[u] = (b + u < r1) ? Rs[c * lp + b + u] : 0.0;
+            for (int u = 0; u < 8; ++u) {
+              const int i = b + u;
+              if (i < r1) {
+                const double nv = fma(-gmm, xs[u], rs[u]);
+                Rs[c * lp + i] = nv;
+                if (i > j) part = fma(nv, nv, part);
+              }
+            }
           }
-#pragma unroll
-          for (int u = 0; u < 8; ++u)
-            if (b + u < r1) Rs[c * lp + b + u] = fma(-gmm, xs[u], vs[u]);
         }
+        part = quad_sum(part);
+        if (q == 0 && live) nrm[c] = part;
       }
     }
     __syncthreads();
@@ -232,7 +211,7 @@ int select_grid(int N, int lpad, int num_cu) {
   int G = std::max(1, std::min(num_cu, (N + 31) / 32));
   while (G < num_cu) {
     const int R = (N + G - 1) / G;
-    if ((size_t)lpad * R * 8 + (size_t)R * 8 <= 140 * 1024) break;
+    if ((size_t)lpad * R * 8 + (size_t)R * 16 <= 130 * 1024) break;
     ++G;
   }
   return G;
@@ -251,8 +230,8 @@ void launch_select(const double* B, int lpad, int l, int N, int bb, int* posof, 
   p.posof = posof;
   p.win = win;
   p.ex = ex;
-  const size_t lds = (size_t)p.R * (l | 1) * 8 + (size_t)lpad * 8 + (size_t)p.R * 4 +
-                     (size_t)(bb + 2) * 4 + 64;
+  const size_t lds = (size_t)p.R * (l | 1) * 8 + (size_t)lpad * 8 + (size_t)p.R * 8 +
+                     (size_t)p.R * 4 + (size_t)(bb + 2) * 4 + 64;
   hipFuncSetAttribute((const void*)select_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)lds);
   void* args[] = {&p};

@@ -126,13 +126,6 @@ __device__ __forceinline__ void wait_flag(const unsigned int* f, unsigned int* a
   __syncthreads();
 }
 
-__device__ __forceinline__ double bcast_lane(double v, int lane) {
-  const unsigned long long u = __double_as_longlong(v);
-  const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, lane);
-  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), lane);
-  return __longlong_as_double(((unsigned long long)hi << 32) | lo);
-}
-
 // Forward (lower = 1): L y = y.  Backward (lower = 0): L^T y = y.
 // sync[0] = ticket counter, sync[1 + k] = done flag of block k, sync[1 + nb]
 // = abort word (raised by a wait that timed out).  A block's finished values

@@ -11,13 +11,15 @@
 // hazards.  For positions the block did not move rowsrc is the identity and
 // the reads are plain coalesced column runs.
 //
-// Tiling: a workgroup owns a 128 x 128 tile (I, J), I >= J, of the lower
-// triangle; its four waves each own 64 x 64 (4 x 4 fragments of 16 x 16).
+// Tiling: a workgroup takes 128 x 128 tiles (I, J), I >= J, of the lower
+// triangle in turn; its four waves each own 64 x 64 (4 x 4 fragments of
+// 16 x 16).
 // L21 and W21 arrive packed in fragment order, so each operand fragment is
 // one coalesced 512-byte load per wave, straight from L2 into registers,
-// double-buffered across the k loop.  Workgroups are numbered so that each
-// XCD (which receives every 8th workgroup) walks a contiguous stretch of the
-// tile order and reuses the same rows of L21 in its own L2.
+// double-buffered across the k loop.  The launch is persistent (two
+// workgroups per CU) and each XCD (which receives every 8th workgroup) walks
+// a contiguous stretch of the tile order, reusing the same rows of L21 in
+// its own L2.
 #include "common.h"
 #include "kernels.h"
 #include "mfma.h"
@@ -93,20 +95,24 @@ __global__ void __launch_bounds__(256, 2) update_kernel(const typename P::TA* __
   typedef typename P::TA TA;
   typedef typename P::Frag Frag;
   typedef typename P::Acc Acc;
-  // XCD-aware numbering: hardware block b runs on XCD b % 8
+  // Persistent: the grid (a multiple of 8) loops over the tiles.  Hardware
+  // block b runs on XCD b % 8; XCD x walks the contiguous tile range
+  // [x per, (x + 1) per), so the rows of L21 a range touches stay in one L2.
   const int64_t b = blockIdx.x;
   const int64_t per = (ntiles + kXcd - 1) / kXcd;
-  const int64_t id = (b % kXcd) * per + b / kXcd;
-  if (id >= ntiles) return;
-  int I, J;
-  tile_of(id, I, J);
+  const int64_t xcd = b % kXcd, nx = gridDim.x / kXcd;
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int wy = w >> 1, wx = w & 1;
-  if (I == J && wx > wy) return;   // strictly upper quarter of a diagonal tile
+  for (int64_t t = b / kXcd; t < per; t += nx) {
+  const int64_t id = xcd * per + t;
+  if (id >= ntiles) break;
+  int I, J;
+  tile_of(id, I, J);
+  if (I == J && wx > wy) continue;   // strictly upper quarter of a diagonal tile
   const int r0 = I * kTile + wy * 64;   // first row of my 64 x 64
   const int c0 = J * kTile + wx * 64;   // first column
-  if (r0 >= N2 || c0 >= N2) return;
+  if (r0 >= N2 || c0 >= N2) continue;
 
   const int g0 = r0 / 16, h0 = c0 / 16;
   constexpr int FE = P::kFragElems;
@@ -167,17 +173,22 @@ __global__ void __launch_bounds__(256, 2) update_kernel(const typename P::TA* __
       }
     }
   }
+  }
 }
 
 }  // namespace
 
 void launch_update(const void* Acur, void* Anext, int64_t ld, const int* rowsrc, int N2,
-                   const void* L21p, const void* W21p, int Qk, int prec, hipStream_t s) {
+                   const void* L21p, const void* W21p, int Qk, int prec, int num_cu,
+                   hipStream_t s) {
   if (N2 <= 0) return;
   const int64_t T = (N2 + kTile - 1) / kTile;
   const int64_t ntiles = T * (T + 1) / 2;
   const int64_t per = (ntiles + kXcd - 1) / kXcd;
-  const dim3 grid((unsigned)(per * kXcd));
+  // two workgroups per CU (leaves registers for a concurrent selection
+  // kernel), never more than the tiles need
+  const int64_t nwg = std::min<int64_t>((int64_t)2 * num_cu / kXcd, per) * kXcd;
+  const dim3 grid((unsigned)std::max<int64_t>(kXcd, nwg));
   if (prec == kPrecF64)
     hipLaunchKernelGGL(update_kernel<PackF64>, grid, dim3(256), 0, s, (const double*)Acur,
                        (double*)Anext, ld, rowsrc, N2, (const double*)L21p, (const double*)W21p,
