@@ -271,6 +271,13 @@ def main():
     upd_bytes = stats[-1]["bytes_update"]
     launches = stats[-1]["launches_update"]
     achieved = upd_flops / (upd_ms * 1e-3) / 1e12 if upd_ms > 0 else 0.0
+    # the same kernel without the concurrent selection beside it (one extra,
+    # untimed factorization with the overlap switched off)
+    rcp.rcp_set_overlap(False)
+    rcp.rcp_factor(A, cfg.b, cfg.p, cfg.seed)
+    iso_ms = rcp.rcp_get_stats()["ms_update"]
+    rcp.rcp_set_overlap(True)
+    traffic = measured_traffic() if args.config == "householder16384" else None
     breakdown = {k: round(sum(s[k] for s in stats) / len(stats), 3)
                  for k in ("ms_total", "ms_omega", "ms_sketch", "ms_select", "ms_panel",
                            "ms_sketch_update", "ms_commit", "ms_update", "ms_finalize",
@@ -293,11 +300,20 @@ def main():
         "roofline": {"kernel": "rcp_update", "bound": "mfma", "achieved": round(achieved, 3),
                      "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP64_MFMA, 4),
-                     "traffic": measured_traffic() if args.config == "householder16384" else None,
+                     "traffic": traffic,
+                     "traffic_over_algorithmic": round(traffic / (upd_bytes / launches), 3)
+                     if traffic else None,
                      "launches": launches, "ms_total": round(upd_ms, 3),
+                     "us_per_launch": round(1e3 * upd_ms / launches, 1),
                      "algorithmic_flops": upd_flops, "algorithmic_bytes": upd_bytes,
                      "achieved_GBps": round(upd_bytes / (upd_ms * 1e-3) / 1e9, 1)
-                     if upd_ms > 0 else 0.0},
+                     if upd_ms > 0 else 0.0,
+                     "note": "timed while overlapped with the next block's selection",
+                     "isolated_ms_total": round(iso_ms, 3),
+                     "isolated_achieved": round(upd_flops / (iso_ms * 1e-3) / 1e12, 3)
+                     if iso_ms > 0 else None,
+                     "isolated_frac": round(upd_flops / (iso_ms * 1e-3) / 1e12 / PEAK_FP64_MFMA, 4)
+                     if iso_ms > 0 else None},
         "backward_error": berr,
         "n2x2": stats[-1]["n2x2"],
         "sbkp_cases": stats[-1]["ncase"],

@@ -71,6 +71,12 @@ int rcp_set_stream(void* hip_stream);
  * in rcp_stats (on = 1) or not (on = 0, the default).  Returns 0. */
 int rcp_set_profiling(int32_t on);
 
+/* Run the trailing update of block j on a second stream, concurrently with
+ * the pivot selection of block j+1 (on = 1, the default), or strictly after
+ * it (on = 0; every kernel then runs alone, which is how per-kernel times
+ * are measured in isolation).  Results are identical either way.  Returns 0. */
+int rcp_set_overlap(int32_t on);
+
 /* Copy the statistics of the last call into *st.  Returns 0, -1 if st is NULL. */
 int rcp_get_stats(rcp_stats* st);
 

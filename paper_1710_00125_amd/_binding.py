@@ -46,6 +46,7 @@ class _BatchInfo(ctypes.Structure):
 _SIGS = {
     "rcp_set_stream": (ctypes.c_int, [ctypes.c_void_p]),
     "rcp_set_profiling": (ctypes.c_int, [ctypes.c_int32]),
+    "rcp_set_overlap": (ctypes.c_int, [ctypes.c_int32]),
     "rcp_get_stats": (ctypes.c_int, [ctypes.POINTER(_Stats)]),
     "rcp_release": (ctypes.c_int, []),
     "rcp_omega": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64,
@@ -138,6 +139,10 @@ def rcp_set_stream(stream=None):
 
 def rcp_set_profiling(on):
     return load().rcp_set_profiling(1 if on else 0)
+
+
+def rcp_set_overlap(on):
+    return load().rcp_set_overlap(1 if on else 0)
 
 
 def rcp_release():

@@ -24,6 +24,7 @@ namespace {
 
 hipStream_t g_stream = nullptr;
 bool g_prof = false;
+bool g_overlap = true;
 rcp_stats g_stats;
 
 struct Arena {
@@ -162,6 +163,11 @@ int rcp_set_stream(void* hip_stream) {
 
 int rcp_set_profiling(int32_t on) {
   g_prof = on != 0;
+  return 0;
+}
+
+int rcp_set_overlap(int32_t on) {
+  g_overlap = on != 0;
   return 0;
 }
 
@@ -384,6 +390,10 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
       }
       RCP_CHECK(hipEventRecord(g_side.updated, s2));
       update_in_flight = true;
+      if (!g_overlap) {
+        RCP_CHECK(hipStreamWaitEvent(s, g_side.updated, 0));
+        update_in_flight = false;
+      }
       g_stats.launches_update += 1;
       g_stats.flops_update += (double)N2 * (N2 + 1) * m;           // lower triangle, 2m per entry
       g_stats.bytes_update += (double)N2 * (N2 + 1) / 2 * 2.0 * esz;   // read + write of each entry
@@ -396,7 +406,7 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
     ++nblocks;
     // the next block's selection needs only the updated sketch: it runs
     // while the trailing update proceeds on the second stream
-    if (N2 > 0) {
+    if (N2 > 0 && g_overlap) {
       enqueue_select(N2);
       selected = true;
     }
