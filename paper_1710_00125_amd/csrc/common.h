@@ -76,6 +76,46 @@ __device__ __forceinline__ void grid_barrier(unsigned int* flags, unsigned int& 
 }
 
 // ---------------------------------------------------------------------------
+// Step-tagged records of the persistent kernels.  A workgroup publishes its
+// candidate for a step as 64-bit words on its own 128-byte line, each word
+// carrying the step, so that polling the records is the barrier and the
+// read at once.  Value words: a double with its two lowest mantissa bits
+// replaced by step & 3 (a change below 2^-50 relative, far inside the
+// rounding of the value itself); the index word: (step + 1) in the top 16
+// bits, then 24 bits of position and 24 bits of source (all-ones: none).
+// A record is current when every word carries the step; zeroed memory never
+// is.  Everything a workgroup stored before its record is visible to a
+// reader that has seen the record.
+// ---------------------------------------------------------------------------
+#define RCP_REC_STRIDE 16   // 64-bit words per record line
+__device__ __forceinline__ unsigned long long rec_tag(double val, int step) {
+  return ((unsigned long long)__double_as_longlong(val) & ~3ull) | (unsigned long long)(step & 3);
+}
+__device__ __forceinline__ unsigned long long rec_word1(int pos, int src, int step) {
+  const unsigned long long p = pos < 0 || pos >= 0xFFFFFF ? 0xFFFFFFull : (unsigned long long)pos;
+  const unsigned long long s = src < 0 || src >= 0xFFFFFF ? 0xFFFFFFull : (unsigned long long)src;
+  return ((unsigned long long)((step + 1) & 0xFFFF) << 48) | (p << 24) | s;
+}
+__device__ __forceinline__ bool rec_tag_current(unsigned long long w, int step) {
+  return (w & 3ull) == (unsigned long long)(step & 3);
+}
+__device__ __forceinline__ bool rec_index_current(unsigned long long w1, int step) {
+  return (w1 >> 48) == (unsigned long long)((step + 1) & 0xFFFF);
+}
+__device__ __forceinline__ double rec_untag(unsigned long long w0) {
+  return __longlong_as_double((long long)w0);
+}
+__device__ __forceinline__ int rec_pos(unsigned long long w1) {
+  const int p = (int)((w1 >> 24) & 0xFFFFFF);
+  return p == 0xFFFFFF ? 0x7fffffff : p;
+}
+__device__ __forceinline__ int rec_src(unsigned long long w1) {
+  const int s = (int)(w1 & 0xFFFFFF);
+  return s == 0xFFFFFF ? -1 : s;
+}
+
+
+// ---------------------------------------------------------------------------
 // Lane exchanges on the VALU, without LDS traffic: the partner value of a
 // butterfly stage of width K.  K = 1, 2: xor through DPP quad permutes;
 // K = 4, 8: DPP half-row / row mirrors (lane i <-> 7 - i within 8, 15 - i

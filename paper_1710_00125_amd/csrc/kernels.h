@@ -39,6 +39,8 @@ struct Exchange {
   int* src;         // [2][G]
   double* vec;      // [2][G][vec_stride]
   int vec_stride;
+  unsigned long long* rec;   // [2][G][16] step-tagged records, one per 128-byte line
+                             // (zeroed before each launch)
   unsigned int* bar;  // grid barrier flags, [G * RCP_FLAG_STRIDE] (zeroed before each launch)
   int* abort_flag;    // raised by a barrier wait that timed out
 };

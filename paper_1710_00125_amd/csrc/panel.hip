@@ -122,6 +122,7 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
   __shared__ double sh_rark[2][kMaxG], sh_rarr[2][kMaxG];
   __shared__ double sh_akk, sh_Acc, sh_A1c, sh_A2c, sh_A11, sh_A22, sh_Anr;
   __shared__ double sh_vn, sh_vrn;
+  __shared__ unsigned long long sh_rec[4];
   __shared__ int sh_pend_n, sh_pend_t, sh_pend_s1, sh_pend_s2;
 
   const int tid = threadIdx.x;
@@ -137,7 +138,7 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
   const int64_t ld = a.ld;
   const int lpad = a.lpad;
   const int tr0 = P.G - 1 - g;    // my rows of T: tr0, tr0 + G, ... (< lpad)
-  unsigned int epoch = 0;
+  int it = 0;   // iteration (decision) count: parity of the exchange slots and record tag
   long long ncase[4] = {0, 0, 0, 0};
   double bp1 = 0.0, bp2 = 0.0;    // prefetched B(r, pivot) for my first pass of T rows
 
@@ -189,7 +190,8 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
 
   int k = 0;
   while (k < bb) {
-    const int par = k & 1;
+    // a 2x2 step advances k by two, so the slots alternate by iteration
+    const int par = it & 1;
     const int c = win[k];
     const int c1 = (k + 1 < bb) ? win[k + 1] : -1;
     const int c2 = (k + 2 < bb) ? win[k + 2] : -1;
@@ -227,15 +229,20 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
       if (tid < 16) {
         const double dsum = dot16_lanes(xr, Wr, have ? k : 0, tid);
         if (tid == 0) {
-          st_agent(&P.ex.val[par * P.G + g], best.val);
-          st_agent(&P.ex.pos[par * P.G + g], best.pos);
-          st_agent(&P.ex.src[par * P.G + g], best.idx);
-          st_agent(&P.ex.aux0[par * P.G + g], have ? vcol[rl] : 0.0);
-          st_agent(&P.ex.aux1[par * P.G + g], have ? Adiag[rl] - dsum : 0.0);
+          sh_rec[0] = rec_tag(best.val, it);
+          sh_rec[1] = rec_word1(best.pos, best.idx, it);
+          sh_rec[2] = rec_tag(have ? vcol[rl] : 0.0, it);
+          sh_rec[3] = rec_tag(have ? Adiag[rl] - dsum : 0.0, it);
         }
       }
     }
-    grid_arrive(P.ex.bar, epoch);
+    // publish the record after every store of this workgroup so far (its L
+    // row above, its multipliers of the last step) has completed
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    unsigned long long* recs = P.ex.rec + (size_t)par * P.G * RCP_REC_STRIDE;
+    if (tid < 4) st_agent(&recs[RCP_REC_STRIDE * g + tid], sh_rec[tid]);
     // ---- gap: prefetch the columns of the two window candidates for the
     // next step, and extend T by the previous step's pivots
     for (int r = tid; r < nown; r += kThreads) {
@@ -251,26 +258,47 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
       sh_A22 = A[(int64_t)c2 * (ld + 1)];
     }
     flush_T();
-    grid_wait(P.ex.bar, epoch, P.G, P.ex.abort_flag);
 
-    // ---- phase B: every record in one round trip, the same decision everywhere
-    // keys (value, position, workgroup) are reduced on the VALU; the rest
-    // of the winning record is looked up by workgroup afterwards
+    // ---- phase B: every workgroup's record (one poll is the barrier and the
+    // read), the same decision everywhere; keys (value, position,
+    // workgroup) are reduced on the VALU, the rest of the winning record is
+    // looked up by workgroup afterwards
     ArgKey rk{-1.0, INT_MAX, -1};
     for (int w = tid; w < P.G; w += kThreads) {
-      ArgKey o{ld_agent(&P.ex.val[par * P.G + w]), ld_agent(&P.ex.pos[par * P.G + w]), w};
-      sh_rsrc[par][w] = ld_agent(&P.ex.src[par * P.G + w]);
-      sh_rark[par][w] = ld_agent(&P.ex.aux0[par * P.G + w]);
-      sh_rarr[par][w] = ld_agent(&P.ex.aux1[par * P.G + w]);
+      const unsigned long long* rw = recs + (size_t)RCP_REC_STRIDE * w;
+      unsigned long long w0, w1, w2, w3;
+      unsigned int spins = 0;
+      for (;;) {
+        w1 = ld_agent(&rw[1]);
+        w0 = ld_agent(&rw[0]);
+        w2 = ld_agent(&rw[2]);
+        w3 = ld_agent(&rw[3]);
+        if (rec_index_current(w1, it) && rec_tag_current(w0, it) && rec_tag_current(w2, it) &&
+            rec_tag_current(w3, it))
+          break;
+        if ((++spins & 1023u) == 0) {
+          if (ld_agent(P.ex.abort_flag)) break;
+          if (spins > (1u << 22)) {
+            st_agent(P.ex.abort_flag, 1);
+            break;
+          }
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      ArgKey o{rec_untag(w0), rec_pos(w1), w};
+      sh_rsrc[par][w] = rec_src(w1);
+      sh_rark[par][w] = rec_untag(w2);
+      sh_rarr[par][w] = rec_untag(w3);
       if (key_better(o, rk)) rk = o;
     }
+    __syncthreads();   // every record seen: all earlier stores of all workgroups visible
     // L rows of the two window candidates for the next pivot (entries < k
-    // were stored by their owners before this step's barrier)
+    // were stored by their owners before their records)
     for (int t = tid; t < k; t += kThreads) {
       if (c1 >= 0) Ln1[t] = ld_agent(&a.Lpanel[(size_t)c1 * ldp + t]);
       if (c2 >= 0) Ln2[t] = ld_agent(&a.Lpanel[(size_t)c2 * ldp + t]);
     }
-    rk = block_argmax(rk, shk);
+    rk = block_argmax(rk, shk);   // (its barriers also order the LDS lookups below)
     Rec rc{rk.val, rk.pos, -1, 0.0, 0.0, rk.idx};
     if (rk.idx >= 0) {
       rc.src = sh_rsrc[par][rk.idx];
@@ -423,6 +451,7 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
     __syncthreads();
     const int kold = k;
     k += sstep;
+    it += 1;
     if (k >= bb) break;
     // ---- the next pivot's new L entries, W entries and a_kk (wave 0; the
     // same in every workgroup)

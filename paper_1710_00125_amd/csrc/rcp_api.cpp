@@ -237,7 +237,7 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
                  al((size_t)n * ldp * 8) + 2 * al(pack_bytes) +
                  al((size_t)lpad * (b + 2) * 8) + 2 * al((size_t)n * 8) + 3 * al((size_t)n * 4) +
                  al((size_t)(b + 2) * 4) + al(sizeof(Ctrl)) + 3 * al((size_t)2 * Gmax * 8) +
-                 2 * al((size_t)2 * Gmax * 4) + al((size_t)2 * Gmax * vec_stride * 8) + al((size_t)Gmax * 128) +
+                 2 * al((size_t)2 * Gmax * 4) + al((size_t)2 * Gmax * vec_stride * 8) + al((size_t)Gmax * 128) + al((size_t)32 * Gmax * 8) +
                  4096;
   int dev = 0;
   hipGetDevice(&dev);
@@ -267,6 +267,7 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
   ex.pos = g_fact.take<int>(2 * Gmax);
   ex.src = g_fact.take<int>(2 * Gmax);
   ex.vec = g_fact.take<double>((size_t)2 * Gmax * vec_stride);
+  ex.rec = g_fact.take<unsigned long long>((size_t)32 * Gmax);
   ex.vec_stride = vec_stride;
   ex.bar = g_fact.take<unsigned int>((size_t)Gmax * 32);
   ex.abort_flag = &ctrl->abort_flag;
@@ -312,7 +313,7 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
   auto enqueue_select = [&](int Nb) {
     Scope sc(KSelect);
     const int Gs = select_grid(Nb, lpad, ncu);
-    hipMemsetAsync(ex.bar, 0, (size_t)Gmax * 128, s);
+    hipMemsetAsync(ex.rec, 0, (size_t)32 * Gmax * sizeof(unsigned long long), s);
     launch_select(Bc, lpad, l, Nb, std::min<int>(b, Nb), posof, win, ex, Gs, s);
   };
   while (K0 < n) {
@@ -348,7 +349,7 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
       pa.l = l;
       pa.lpad = lpad;
       pa.T = Tm;
-      hipMemsetAsync(ex.bar, 0, (size_t)Gmax * 128, s);
+      hipMemsetAsync(ex.rec, 0, (size_t)32 * Gmax * sizeof(unsigned long long), s);
       launch_panel(pa, ex, Gp, ngr, lds, s);
     }
     RCP_CHECK(hipGetLastError());

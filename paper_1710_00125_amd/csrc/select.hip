@@ -28,6 +28,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kColsPerPass = 64;   // a quad of lanes per column
+constexpr int kRecStride = RCP_REC_STRIDE;
 
 struct SelectParams {
   const double* B;
@@ -65,7 +66,6 @@ __global__ void __launch_bounds__(kThreads) select_kernel(SelectParams a) {
   const int nown = max(0, min(R, a.N - s0));
   const int q = tid & 3;            // chunk of rows handled by this lane
   const int cq = tid >> 2;          // column within a pass (a quad per column)
-  unsigned int epoch = 0;
 
   for (int e = tid; e < l * R; e += kThreads) {
     const int c = e / l, i = e - c * l;
@@ -101,24 +101,43 @@ __global__ void __launch_bounds__(kThreads) select_kernel(SelectParams a) {
       }
     }
     best = block_argmax(best, shk);
-    // ---- publish my candidate and its residual
-    if (tid == 0) {
-      st_agent(&a.ex.val[par * a.G + g], best.val);
-      st_agent(&a.ex.pos[par * a.G + g], best.pos);
-      st_agent(&a.ex.src[par * a.G + g], best.idx);
-    }
+    // ---- publish my candidate's residual, then its record: two 64-bit words
+    // that both carry the step, so that one poll of them is the barrier and
+    // the read at once (a workgroup's record appears only after its vector)
     if (best.idx >= 0) {
       const int c = best.idx - s0;
       double* dst = a.ex.vec + ((size_t)par * a.G + g) * a.ex.vec_stride;
       for (int i = j + tid; i < l; i += kThreads) st_agent(&dst[i], Rs[c * lp + i]);
     }
-    grid_barrier(a.ex.bar, epoch, a.G, a.ex.abort_flag);
-    // ---- global winner (identical in every workgroup): keys reduced on the
-    // VALU, the winner's source looked up by workgroup afterwards
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    unsigned long long* rec = a.ex.rec + (size_t)par * a.G * kRecStride;
+    if (tid == 0) {
+      st_agent(&rec[kRecStride * g], rec_tag(best.val, j));
+      st_agent(&rec[kRecStride * g + 1], rec_word1(best.pos, best.idx, j));
+    }
+    // ---- global winner (identical in every workgroup): one thread polls one
+    // workgroup's record; keys reduced on the VALU, the source looked up after
     ArgKey cand{-1.0, 0x7fffffff, -1};
     for (int w = tid; w < a.G; w += kThreads) {
-      ArgKey o{ld_agent(&a.ex.val[par * a.G + w]), ld_agent(&a.ex.pos[par * a.G + w]), w};
-      sh_src[par][w] = ld_agent(&a.ex.src[par * a.G + w]);
+      unsigned long long w0, w1;
+      unsigned int spins = 0;
+      for (;;) {
+        w1 = ld_agent(&rec[kRecStride * w + 1]);
+        w0 = ld_agent(&rec[kRecStride * w]);
+        if (rec_index_current(w1, j) && rec_tag_current(w0, j)) break;
+        if ((++spins & 1023u) == 0) {
+          if (ld_agent(a.ex.abort_flag)) break;
+          if (spins > (1u << 22)) {
+            st_agent(a.ex.abort_flag, 1);
+            break;
+          }
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      ArgKey o{rec_untag(w0), rec_pos(w1), w};
+      sh_src[par][w] = rec_src(w1);
       if (key_better(o, cand)) cand = o;
     }
     cand = block_argmax(cand, shr);
@@ -142,6 +161,7 @@ __global__ void __launch_bounds__(kThreads) select_kernel(SelectParams a) {
     }
     // ---- Householder v = x + sign(x_j) ||x|| e_j, beta = 2 / v.v =
     // 1 / (||x|| (||x|| + |x_j|)), from the winner's published squared norm
+    // (the same bits in every workgroup)
     const double nx = sqrt(cand.val);
     const double xj = x[j];
     const double vj = xj + copysign(nx, xj);
