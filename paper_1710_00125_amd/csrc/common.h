@@ -202,18 +202,22 @@ __device__ __forceinline__ ArgKey wave_argmax(ArgKey k) {
   return k;
 }
 
-// Workgroup-wide argmax; the result is returned to every thread.
-// `sh` must hold (blockDim.x / 64) ArgKeys.
+// Workgroup-wide argmax over NW waves (the workgroup size / 64); the result
+// is returned to every thread.  `sh` must hold NW ArgKeys.
+template <int NW = 4>
 __device__ __forceinline__ ArgKey block_argmax(ArgKey k, ArgKey* sh) {
   const int lane = threadIdx.x & (RCP_WAVE - 1);
   const int wid = threadIdx.x / RCP_WAVE;
   k = wave_argmax(k);
   if (lane == 0) sh[wid] = k;
   __syncthreads();
-  ArgKey best = sh[0];
-  const int nw = blockDim.x / RCP_WAVE;
-  for (int w = 1; w < nw; ++w)
-    if (key_better(sh[w], best)) best = sh[w];
+  ArgKey v[NW];
+#pragma unroll
+  for (int w = 0; w < NW; ++w) v[w] = sh[w];
+  ArgKey best = v[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w)
+    if (key_better(v[w], best)) best = v[w];
   __syncthreads();
   return best;
 }
@@ -229,6 +233,7 @@ __device__ __forceinline__ double wave_sum64(double v) {
   return v;
 }
 
+template <int NW = 4>
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   const int lane = threadIdx.x & (RCP_WAVE - 1);
   const int wid = threadIdx.x / RCP_WAVE;
@@ -236,8 +241,8 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   if (lane == 0) sh[wid] = v;
   __syncthreads();
   double s = 0.0;
-  const int nw = blockDim.x / RCP_WAVE;
-  for (int w = 0; w < nw; ++w) s += sh[w];
+#pragma unroll
+  for (int w = 0; w < NW; ++w) s += sh[w];
   __syncthreads();
   return s;
 }
@@ -253,6 +258,10 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 // (IEEE addition is commutative).  So a value that one workgroup forms for
 // its own row and another workgroup forms redundantly agree exactly.
 // ---------------------------------------------------------------------------
+// x and y must point into LDS: the loads of a batch of eight are issued
+// unconditionally (an LDS read past the end of the allocation returns 0)
+// and the accumulator is selected for the terms inside the chunk, so the
+// batch compiles to straight-line code.
 template <typename T>
 __device__ __forceinline__ T dot_chunk16(const T* __restrict__ x, const T* __restrict__ y,
                                          int i, int j) {
@@ -265,12 +274,16 @@ __device__ __forceinline__ T dot_chunk16(const T* __restrict__ x, const T* __res
     T xs[8], ys[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      xs[u] = (b + u < t1) ? x[b + u] : T(0);
-      ys[u] = (b + u < t1) ? y[b + u] : T(0);
+      xs[u] = x[b + u];
+      ys[u] = y[b + u];
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (b + u < t1) s = fma(xs[u], ys[u], s);
+    for (int u = 0; u < 8; ++u) {
+      // the loaded words past the chunk may hold anything (even NaN):
+      // select the accumulator, never multiply by a masked zero
+      const T f = fma(xs[u], ys[u], s);
+      s = (b + u < t1) ? f : s;
+    }
   }
   return s;
 }

@@ -167,53 +167,55 @@ __global__ void __launch_bounds__(kThreads) select_kernel(SelectParams a) {
     const double vj = xj + copysign(nx, xj);
     const double beta = 1.0 / (nx * (nx + fabs(xj)));
     // ---- reflect my untaken columns and form their next squared norms
-    // (rows j+1 .. l-1) in the same pass, a quad per column; the LDS loads
-    // of eight rows are issued before their arithmetic
+    // (rows j+1 .. l-1) in the same pass, a quad per column; each batch of
+    // eight rows is loaded unconditionally (LDS: the slab is followed by x
+    // and nrm, and reads past the allocation return 0) and the sums are
+    // selected for the rows in range, so the batch is straight-line code
     const int cs = (l - j + 3) >> 2;
     const int r0 = j + q * cs, r1 = min(l, r0 + cs);
-    {
-      for (int cb = 0; cb < nown; cb += kColsPerPass) {
-        const int c = cb + cq;
-        const bool live = c < nown && posl[c] > j;
-        double dot = 0.0;
-        if (live)
-          for (int b = r0; b < r1; b += 8) {
-            double xs[8], rs[8];
+    for (int cb = 0; cb < nown; cb += kColsPerPass) {
+      const int c = cb + cq;
+      const bool live = c < nown && posl[c] > j;
+      const int e1 = live ? r1 : r0;   // empty range for dead columns
+      double* rc = Rs + (size_t)min(c, R - 1) * lp;
+      double dot = 0.0;
+      for (int b = r0; b < e1; b += 8) {
+        double xs[8], rs[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-              const int i = b + u;
-              xs[u] = (i < r1) ? (i == j ? vj : x[i]) : 0.0;
-              rs[u] = (i < r1) ? Rs[c * lp + i] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) dot = fma(xs[u], rs[u], dot);
-          }
-        dot = quad_sum(dot);
-        double part = 0.0;
-        if (live) {
-          const double gmm = beta * dot;
-          for (int b = r0; b < r1; b += 8) {
-            double xs[8], rs[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-              const int i = b + u;
-              xs[u] = (i < r1) ? (i == j ? vj : x[i]) : 0.0;
-              rs[u] = (i < r1) ? Rs[c * lp + i] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-              const int i = b + u;
-              if (i < r1) {
-                const double nv = fma(-gmm, xs[u], rs[u]);
-                Rs[c * lp + i] = nv;
-                if (i > j) part = fma(nv, nv, part);
-              }
-            }
-          }
+        for (int u = 0; u < 8; ++u) {
+          xs[u] = x[b + u];
+          rs[u] = rc[b + u];
         }
-        part = quad_sum(part);
-        if (q == 0 && live) nrm[c] = part;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = b + u;
+          const double v = (i == j) ? vj : xs[u];
+          const double f = fma(v, rs[u], dot);   // words past the range may be NaN:
+          dot = (i < e1) ? f : dot;              // select, never multiply by zero
+        }
       }
+      dot = quad_sum(dot);
+      const double gmm = beta * dot;
+      double part = 0.0;
+      for (int b = r0; b < e1; b += 8) {
+        double xs[8], rs[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          xs[u] = x[b + u];
+          rs[u] = rc[b + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = b + u;
+          const double v = (i == j) ? vj : xs[u];
+          const double nv = fma(-gmm, v, rs[u]);
+          if (i < e1) rc[i] = nv;
+          const double f = fma(nv, nv, part);
+          part = (i < e1 && i > j) ? f : part;
+        }
+      }
+      part = quad_sum(part);
+      if (q == 0 && live) nrm[c] = part;
     }
     __syncthreads();
   }
