@@ -231,7 +231,12 @@ void launch_sketch_update(const double* B, int lpad, int l, const int* srcat, in
   else go(sketch_update_kernel<kSuMaxRowFrags>);
 }
 
-int update_k_frags(int prec, int m) { return prec == kPrecBF16x3 ? (m + 31) / 32 : (m + 3) / 4; }
+// k steps of the trailing update, rounded up to an even count (the update
+// walks them in pairs; the packing writes zeros past m)
+int update_k_frags(int prec, int m) {
+  const int q = prec == kPrecBF16x3 ? (m + 31) / 32 : (m + 3) / 4;
+  return (q + 1) & ~1;
+}
 
 size_t update_pack_bytes(int prec, int64_t rows_pad, int Qk) {
   if (prec == kPrecBF16x3) return (size_t)(rows_pad / 16) * Qk * 2048;

@@ -106,7 +106,7 @@ void launch_sketch_update(const double* B, int lpad, int l, const int* srcat, in
 // Pack L21 and W21 = L21 D1 (rows srcat[m..N)) in MFMA fragment order,
 // write the block's rows of Lwork (row-major n x n by original index, element
 // type by prec) and Pnext, and the gather map rowsrc[i] = srcat[m + i].
-// Qk = number of k fragments (update_k_frags(prec, m)).
+// Qk = number of k fragments (update_k_frags(prec, m), always even).
 int update_k_frags(int prec, int m);
 size_t update_pack_bytes(int prec, int64_t rows_pad, int Qk);
 void launch_commit(const int* srcat, int m, int N, int K0, int64_t n, const double* Lpanel,

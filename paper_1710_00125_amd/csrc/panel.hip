@@ -24,14 +24,15 @@
 // (nothing is physically interchanged).  Per step:
 //   phase A  every workgroup forms the current column on its rows and
 //            publishes one record -- its best off-diagonal candidate (value,
-//            position, source, a_rk, a_rr) and that candidate's L row -- then
-//            arrives at the barrier;
+//            position, source, a_rk, a_rr) -- then arrives at the barrier;
 //   (gap)    between arriving and waiting, every workgroup prefetches the
 //            columns of the next window candidates, and the workgroups that
 //            own rows of T add the previous step's pivot columns to them;
 //   phase B  after the barrier every workgroup reads all records in one
 //            round trip, derives the same decision, forms column r from the
-//            winner's L row when SBKP needs it, stores its multipliers, and
+//            candidate's L row (read back from the panel's L, whose entries
+//            before k its owner stored before its record) when SBKP needs
+//            it, stores its multipliers, and
 //            forms the L row of the next pivot redundantly.  The next pivot
 //            is always one of {c, win[k+1], win[k+2]}: their rows of L and
 //            their columns of A are prefetched during the step.
@@ -94,6 +95,7 @@ __device__ __forceinline__ bool rec_better(const Rec& a, const Rec& b) {
 // reduced-precision modes; values are widened to FP64 on load)
 template <typename TA>
 __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
+  __builtin_amdgcn_s_setprio(3);
   const PanelArgs& a = P.a;
   extern __shared__ double smem[];
   const int R = P.R, ldp = a.ldp, ldt = P.ldt, ntr = P.ntr;
@@ -215,16 +217,10 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
     const bool have = best.idx >= 0;
     const int rl = have ? best.idx - s0 : 0;
     {
-      // publish the candidate's L row, and its current diagonal a_rr (formed
-      // only here) from its W row
+      // the candidate's current diagonal a_rr (formed only here) from its W row
       const double* xr = Lrow + (size_t)rl * ldp;
-      if (have) {
-        double* dst = P.ex.vec + ((size_t)par * P.G + g) * P.ex.vec_stride;
-        for (int t = tid; t < k; t += kThreads) {
-          st_agent(&dst[t], xr[t]);
-          Wr[t] = w_entry(xr, Dd, Ds, kind, t);
-        }
-      }
+      if (have)
+        for (int t = tid; t < k; t += kThreads) Wr[t] = w_entry(xr, Dd, Ds, kind, t);
       __syncthreads();
       if (tid < 16) {
         const double dsum = dot16_lanes(xr, Wr, have ? k : 0, tid);
@@ -236,8 +232,8 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
         }
       }
     }
-    // publish the record after every store of this workgroup so far (its L
-    // row above, its multipliers of the last step) has completed
+    // publish the record after every store of this workgroup so far (its
+    // multipliers of the last step) has completed
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
@@ -337,7 +333,7 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
     }
     if (kase >= 2) {
       // second round trip: the winner's L row, A(s, r) on my rows, A(cn, r)
-      const double* xv = P.ex.vec + ((size_t)par * P.G + rc.g) * P.ex.vec_stride;
+      const double* xv = a.Lpanel + (size_t)rsrc * ldp;
       for (int t = tid; t < k; t += kThreads) Lr[t] = ld_agent(&xv[t]);
       for (int r = tid; r < nown; r += kThreads)
         avec[r] = sym_at(A, ld, (int64_t)(s0 + r), (int64_t)rsrc);

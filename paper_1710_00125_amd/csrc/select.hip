@@ -46,6 +46,8 @@ __device__ __forceinline__ double quad_sum(double v) {
 }
 
 __global__ void __launch_bounds__(kThreads) select_kernel(SelectParams a) {
+  // issue priority over the trailing update's waves that share the CU
+  __builtin_amdgcn_s_setprio(3);
   extern __shared__ double smem[];
   const int R = a.R;
   const int l = a.l;

@@ -16,7 +16,8 @@
 // 16 x 16).
 // L21 and W21 arrive packed in fragment order, so each operand fragment is
 // one coalesced 512-byte load per wave, straight from L2 into registers,
-// double-buffered across the k loop.  The launch is persistent (two
+// double-buffered across the k loop.  In the epilogue each fragment row's
+// 16 reads of the old matrix are issued together.  The launch is persistent (two
 // workgroups per CU) and each XCD (which receives every 8th workgroup) walks
 // a contiguous stretch of the tile order, reusing the same rows of L21 in
 // its own L2.
@@ -84,6 +85,8 @@ struct PackElem<PackBF16x3> {
   typedef rcp_bf8 type;
 };
 
+// two workgroups per CU at no more than 216 registers leave room for a
+// concurrent selection kernel (80 registers, one wave per SIMD)
 template <typename P>
 __global__ void __launch_bounds__(256, 2) update_kernel(const typename P::TA* __restrict__ Acur,
                                                         typename P::TA* __restrict__ Anext,
@@ -102,7 +105,9 @@ __global__ void __launch_bounds__(256, 2) update_kernel(const typename P::TA* __
   const int64_t per = (ntiles + kXcd - 1) / kXcd;
   const int64_t xcd = b % kXcd, nx = gridDim.x / kXcd;
   const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
+  // wave index as a scalar: everything derived from it (tile corner,
+  // operand bases) stays in scalar registers
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wy = w >> 1, wx = w & 1;
   for (int64_t t = b / kXcd; t < per; t += nx) {
   const int64_t id = xcd * per + t;
@@ -114,6 +119,8 @@ __global__ void __launch_bounds__(256, 2) update_kernel(const typename P::TA* __
   const int c0 = J * kTile + wx * 64;   // first column
   if (r0 >= N2 || c0 >= N2) continue;
 
+  const int src_r = rowsrc[min(r0 + lane, N2 - 1)];
+  const int src_c = rowsrc[min(c0 + lane, N2 - 1)];
   const int g0 = r0 / 16, h0 = c0 / 16;
   constexpr int FE = P::kFragElems;
   const auto* pa = L21p + ((int64_t)g0 * Qk) * FE + lane;
@@ -126,50 +133,64 @@ __global__ void __launch_bounds__(256, 2) update_kernel(const typename P::TA* __
 #pragma unroll
     for (int y = 0; y < 4; ++y) acc[x][y] = Acc{0, 0, 0, 0};
 
-  Frag a_cur[4], b_cur[4], a_nxt[4], b_nxt[4];
+  Frag a0[4], b0[4], a1[4], b1[4];
 #pragma unroll
   for (int x = 0; x < 4; ++x) {
-    a_cur[x] = P::load(pa + x * gstride);
-    b_cur[x] = P::load(pb + x * gstride);
+    a0[x] = P::load(pa + x * gstride);
+    b0[x] = P::load(pb + x * gstride);
   }
-  for (int q = 0; q < Qk; ++q) {
-    if (q + 1 < Qk) {
+  // two operand buffers used in turn (Qk is even; no register copies), so
+  // that the wait before a step's products covers only that step's loads and
+  // the next step's loads stay in flight behind them
+  for (int q = 0; q < Qk; q += 2) {
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      a1[x] = P::load(pa + x * gstride + (q + 1) * FE);
+      b1[x] = P::load(pb + x * gstride + (q + 1) * FE);
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[x][y] = P::mma(b0[y], a0[x], acc[x][y]);
+    if (q + 2 < Qk) {
 #pragma unroll
       for (int x = 0; x < 4; ++x) {
-        a_nxt[x] = P::load(pa + x * gstride + (q + 1) * FE);
-        b_nxt[x] = P::load(pb + x * gstride + (q + 1) * FE);
+        a0[x] = P::load(pa + x * gstride + (q + 2) * FE);
+        b0[x] = P::load(pb + x * gstride + (q + 2) * FE);
       }
     }
 #pragma unroll
     for (int x = 0; x < 4; ++x)
 #pragma unroll
-      for (int y = 0; y < 4; ++y) acc[x][y] = P::mma(b_cur[y], a_cur[x], acc[x][y]);
-#pragma unroll
-    for (int x = 0; x < 4; ++x) {
-      a_cur[x] = a_nxt[x];
-      b_cur[x] = b_nxt[x];
-    }
+      for (int y = 0; y < 4; ++y) acc[x][y] = P::mma(b1[y], a1[x], acc[x][y]);
   }
 
   // acc[x][y] holds the 16 x 16 block (j, i) = (W L^T)(c0 + 16y.., r0 + 16x..):
   // lane l, element v is column j = c0 + 16y + MfmaAcc<TA>::row(l, v), row
   // i = r0 + 16x + l%16, so 16 consecutive lanes cover 16 consecutive rows of
-  // one column.  C = Acur(rowsrc(i), rowsrc(j)) - acc, written to Anext(i, j)
+  // one column.  C = Acur(rowsrc(i), rowsrc(j)) - acc, written to Anext(i, j).
+  // Lane l holds the sources of row r0 + l and column c0 + l (loaded before
+  // the k loop, indices clamped into the matrix; entries outside it are
+  // never stored) and hands them out by lane shuffles.  Per 16 x 16 block
+  // its 4 reads of the old matrix are issued together, then its 4 writes
+  // (a compiler fence between the blocks bounds the registers in flight).
 #pragma unroll
   for (int x = 0; x < 4; ++x) {
     const int i = r0 + 16 * x + acc_col(lane);
-    if (i >= N2) continue;
-    const int64_t si = rowsrc[i];
+    const int64_t s_i = __shfl(src_r, 16 * x + acc_col(lane));
 #pragma unroll
     for (int y = 0; y < 4; ++y) {
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      TA cv[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t s_j = __shfl(src_c, 16 * y + MfmaAcc<TA>::row(lane, v));
+        cv[v] = Acur[(s_i >= s_j) ? s_i + s_j * ld : s_j + s_i * ld];
+      }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int j = c0 + 16 * y + MfmaAcc<TA>::row(lane, v);
-        if (j < N2) {
-          const int64_t sj = rowsrc[j];
-          const TA a = (si >= sj) ? Acur[si + sj * ld] : Acur[sj + si * ld];
-          Anext[i + (int64_t)j * ld] = a - acc[x][y][v];
-        }
+        if (i < N2 && j < N2) Anext[i + (int64_t)j * ld] = cv[v] - acc[x][y][v];
       }
     }
   }
