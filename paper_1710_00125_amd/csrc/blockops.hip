@@ -105,7 +105,7 @@ __device__ __forceinline__ double w_of_row(const double* __restrict__ x, const d
 
 // FP64 / FP32 packing for the K = 4 matrix-core steps: element e of the
 // packed arrays is ((g * Qk + qk) * 64 + lane), holding row 16 g + lane % 16
-// and k = 4 qk + lane / 16.
+// and k = 4 qk + lane / 16.  W21 is stored negated.
 template <typename TF>
 __global__ void commit_pack_kernel(const int* __restrict__ srcat, int m, int N, int K0, int64_t n,
                                    const double* __restrict__ Lp, int ldp,
@@ -129,7 +129,7 @@ __global__ void commit_pack_kernel(const int* __restrict__ srcat, int m, int N, 
       wv = w_of_row(x, Dg, ipiv, n, K0, t);
     }
     L21p[e] = (TF)lv;
-    W21p[e] = (TF)wv;
+    W21p[e] = (TF)(-wv);   // negated: the update accumulates onto the old entries
   }
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N2;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -174,7 +174,7 @@ __global__ void commit_pack_bf16x3_kernel(const int* __restrict__ srcat, int m, 
       split_bf16(lv, h, lo);
       lh[u] = h;
       ll[u] = lo;
-      split_bf16(wv, h, lo);
+      split_bf16(-wv, h, lo);   // negated, as in the FP64 / FP32 packing
       wh[u] = h;
       wl[u] = lo;
     }

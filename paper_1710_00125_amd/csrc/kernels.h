@@ -103,7 +103,7 @@ void launch_panel(const PanelArgs& a, Exchange ex, int G, int ngr, size_t lds_by
 void launch_sketch_update(const double* B, int lpad, int l, const int* srcat, int m, int N,
                           const double* Lpanel, int ldp, const double* T, double* Bnext,
                           hipStream_t s);
-// Pack L21 and W21 = L21 D1 (rows srcat[m..N)) in MFMA fragment order,
+// Pack L21 and -W21 = -L21 D1 (rows srcat[m..N)) in MFMA fragment order,
 // write the block's rows of Lwork (row-major n x n by original index, element
 // type by prec) and Pnext, and the gather map rowsrc[i] = srcat[m + i].
 // Qk = number of k fragments (update_k_frags(prec, m), always even).

@@ -16,11 +16,11 @@
 // 16 x 16).
 // L21 and W21 arrive packed in fragment order, so each operand fragment is
 // one coalesced 512-byte load per wave, straight from L2 into registers,
-// double-buffered across the k loop.  In the epilogue each fragment row's
-// 16 reads of the old matrix are issued together.  The launch is persistent (two
-// workgroups per CU) and each XCD (which receives every 8th workgroup) walks
-// a contiguous stretch of the tile order, reusing the same rows of L21 in
-// its own L2.
+// double-buffered across the k loop.  The accumulators are loaded with the
+// old entries before the k loop (W21 arrives negated), so the epilogue only
+// stores.  The launch is persistent (two workgroups per CU) and each XCD
+// (which receives every 8th workgroup) walks a contiguous stretch of the
+// tile order, reusing the same rows of L21 in its own L2.
 #include "common.h"
 #include "kernels.h"
 #include "mfma.h"
@@ -127,11 +127,26 @@ __global__ void __launch_bounds__(256, 2) update_kernel(const typename P::TA* __
   const auto* pb = W21p + ((int64_t)h0 * Qk) * FE + lane;
   const int64_t gstride = (int64_t)Qk * FE;
 
+  // The accumulators start as the old entries C = Acur(rowsrc(i), rowsrc(j))
+  // and the packed W21 is negated, so the products leave C - L21 W21^T in
+  // them and the epilogue only stores.  acc[x][y] is the 16 x 16 block
+  // (j, i) = (c0 + 16y.., r0 + 16x..): lane l, element v is column
+  // j = c0 + 16y + MfmaAcc<TA>::row(l, v), row i = r0 + 16x + l%16.  Lane l
+  // holds the sources of row r0 + l and column c0 + l (indices clamped into
+  // the matrix; entries outside it are never stored) and hands them out by
+  // lane shuffles.  All 64 reads are issued before the first product.
   Acc acc[4][4];
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+  for (int x = 0; x < 4; ++x) {
+    const int64_t s_i = __shfl(src_r, 16 * x + acc_col(lane));
 #pragma unroll
-    for (int y = 0; y < 4; ++y) acc[x][y] = Acc{0, 0, 0, 0};
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t s_j = __shfl(src_c, 16 * y + MfmaAcc<TA>::row(lane, v));
+        acc[x][y][v] = Acur[(s_i >= s_j) ? s_i + s_j * ld : s_j + s_i * ld];
+      }
+  }
 
   Frag a0[4], b0[4], a1[4], b1[4];
 #pragma unroll
@@ -165,34 +180,16 @@ __global__ void __launch_bounds__(256, 2) update_kernel(const typename P::TA* __
       for (int y = 0; y < 4; ++y) acc[x][y] = P::mma(b1[y], a1[x], acc[x][y]);
   }
 
-  // acc[x][y] holds the 16 x 16 block (j, i) = (W L^T)(c0 + 16y.., r0 + 16x..):
-  // lane l, element v is column j = c0 + 16y + MfmaAcc<TA>::row(l, v), row
-  // i = r0 + 16x + l%16, so 16 consecutive lanes cover 16 consecutive rows of
-  // one column.  C = Acur(rowsrc(i), rowsrc(j)) - acc, written to Anext(i, j).
-  // Lane l holds the sources of row r0 + l and column c0 + l (loaded before
-  // the k loop, indices clamped into the matrix; entries outside it are
-  // never stored) and hands them out by lane shuffles.  Per 16 x 16 block
-  // its 4 reads of the old matrix are issued together, then its 4 writes
-  // (a compiler fence between the blocks bounds the registers in flight).
 #pragma unroll
   for (int x = 0; x < 4; ++x) {
     const int i = r0 + 16 * x + acc_col(lane);
-    const int64_t s_i = __shfl(src_r, 16 * x + acc_col(lane));
 #pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      __atomic_signal_fence(__ATOMIC_SEQ_CST);
-      TA cv[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t s_j = __shfl(src_c, 16 * y + MfmaAcc<TA>::row(lane, v));
-        cv[v] = Acur[(s_i >= s_j) ? s_i + s_j * ld : s_j + s_i * ld];
-      }
+    for (int y = 0; y < 4; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int j = c0 + 16 * y + MfmaAcc<TA>::row(lane, v);
-        if (i < N2 && j < N2) Anext[i + (int64_t)j * ld] = cv[v] - acc[x][y][v];
+        if (i < N2 && j < N2) Anext[i + (int64_t)j * ld] = acc[x][y][v];
       }
-    }
   }
   }
 }
