@@ -88,22 +88,6 @@ __device__ __forceinline__ void grid_barrier(unsigned int* flags, unsigned int& 
 // reader that has seen the record.
 // ---------------------------------------------------------------------------
 #define RCP_REC_STRIDE 16   // 64-bit words per record line
-// A double carried exactly: two words, each holding 32 bits of the value in
-// its low half and (step + 1) in its high half.
-__device__ __forceinline__ unsigned long long rec_hi(double v, int step) {
-  return ((unsigned long long)(unsigned)(step + 1) << 32) |
-         ((unsigned long long)__double_as_longlong(v) >> 32);
-}
-__device__ __forceinline__ unsigned long long rec_lo(double v, int step) {
-  return ((unsigned long long)(unsigned)(step + 1) << 32) |
-         ((unsigned long long)__double_as_longlong(v) & 0xFFFFFFFFull);
-}
-__device__ __forceinline__ bool rec_half_current(unsigned long long w, int step) {
-  return (unsigned)(w >> 32) == (unsigned)(step + 1);
-}
-__device__ __forceinline__ double rec_join(unsigned long long hi, unsigned long long lo) {
-  return __longlong_as_double((long long)((hi << 32) | (lo & 0xFFFFFFFFull)));
-}
 __device__ __forceinline__ unsigned long long rec_tag(double val, int step) {
   return ((unsigned long long)__double_as_longlong(val) & ~3ull) | (unsigned long long)(step & 3);
 }

@@ -25,11 +25,9 @@
 //   phase A  every workgroup forms the current column on its rows and
 //            publishes one record -- its best off-diagonal candidate (value,
 //            position, source, a_rk, a_rr) -- then arrives at the barrier;
-//   (gap)    between arriving and waiting, every workgroup issues the loads
-//            it needs after the poll -- the columns of the window candidates
-//            win[k+1], win[k+2] and the entries of their L rows before the
-//            last step's -- into registers, and the workgroups that own rows
-//            of T add the previous step's pivot columns to them;
+//   (gap)    between arriving and waiting, every workgroup prefetches the
+//            columns of the next window candidates, and the workgroups that
+//            own rows of T add the previous step's pivot columns to them;
 //   phase B  after the barrier every workgroup reads all records in one
 //            round trip, derives the same decision, forms column r from the
 //            candidate's L row (read back from the panel's L, whose entries
@@ -37,9 +35,7 @@
 //            it, stores its multipliers, and
 //            forms the L row of the next pivot redundantly.  The next pivot
 //            is always one of {c, win[k+1], win[k+2]}: their rows of L and
-//            their columns of A are prefetched during the step; the owner
-//            of a window candidate carries its L entries of the last step
-//            (exactly, two words each) in its record.
+//            their columns of A are prefetched during the step.
 #include <climits>
 
 #include "common.h"
@@ -51,9 +47,6 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kRowsPerPass = kThreads / 4;
 constexpr int kMaxG = 256;   // workgroups of one launch (one per CU at most)
-// record words: value, index, a_rk, a_rr, then the last step's (up to two)
-// L entries of win[k+1] and of win[k+2], two words each
-constexpr int kRecWords = 12;
 
 struct PanelParams {
   PanelArgs a;
@@ -131,7 +124,7 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
   __shared__ double sh_rark[2][kMaxG], sh_rarr[2][kMaxG];
   __shared__ double sh_akk, sh_Acc, sh_A1c, sh_A2c, sh_A11, sh_A22, sh_Anr;
   __shared__ double sh_vn, sh_vrn;
-  __shared__ unsigned long long sh_rec[kRecWords];
+  __shared__ unsigned long long sh_rec[4];
   __shared__ int sh_pend_n, sh_pend_t, sh_pend_s1, sh_pend_s2;
 
   const int tid = threadIdx.x;
@@ -148,7 +141,6 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
   const int lpad = a.lpad;
   const int tr0 = P.G - 1 - g;    // my rows of T: tr0, tr0 + G, ... (< lpad)
   int it = 0;   // iteration (decision) count: parity of the exchange slots and record tag
-  int kprev = 0;   // k of the previous iteration: L entries in [kprev, k) are the last step's
   long long ncase[4] = {0, 0, 0, 0};
   double bp1 = 0.0, bp2 = 0.0;    // prefetched B(r, pivot) for my first pass of T rows
 
@@ -239,15 +231,6 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
           sh_rec[3] = rec_tag(have ? Adiag[rl] - dsum : 0.0, it);
         }
       }
-      // the last step's L entries of the window candidates this workgroup owns
-      if (tid >= 32 && tid < 36) {
-        const int which = (tid - 32) >> 1, e = (tid - 32) & 1;
-        const int cs = which == 0 ? c1 : c2;
-        double v = 0.0;
-        if (cs >= 0 && cs / R == g && e < k - kprev) v = Lrow[(size_t)(cs - s0) * ldp + kprev + e];
-        sh_rec[4 + 4 * which + 2 * e] = rec_hi(v, it);
-        sh_rec[5 + 4 * which + 2 * e] = rec_lo(v, it);
-      }
     }
     // publish the record after every store of this workgroup so far (its
     // multipliers of the last step) has completed
@@ -255,36 +238,20 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     unsigned long long* recs = P.ex.rec + (size_t)par * P.G * RCP_REC_STRIDE;
-    if (tid < kRecWords) st_agent(&recs[RCP_REC_STRIDE * g + tid], sh_rec[tid]);
-    // ---- gap: the columns of the two window candidates for the next step
-    // and their L entries before kprev (visible since the last poll) are
-    // loaded into registers and written to LDS after the poll (rows and
-    // entries beyond the first kThreads go straight to LDS); T is extended
-    // by the previous step's pivots
-    double pf1 = 0.0, pf2 = 0.0, pl1 = 0.0, pl2 = 0.0, pax = 0.0, pdg = 0.0;
-    if (tid < nown) {
-      if (c1 >= 0) pf1 = sym_at(A, ld, (int64_t)(s0 + tid), (int64_t)c1);
-      if (c2 >= 0) pf2 = sym_at(A, ld, (int64_t)(s0 + tid), (int64_t)c2);
-    }
-    for (int r = tid + kThreads; r < nown; r += kThreads) {
+    if (tid < 4) st_agent(&recs[RCP_REC_STRIDE * g + tid], sh_rec[tid]);
+    // ---- gap: prefetch the columns of the two window candidates for the
+    // next step, and extend T by the previous step's pivots
+    for (int r = tid; r < nown; r += kThreads) {
       if (c1 >= 0) acol1[r] = sym_at(A, ld, (int64_t)(s0 + r), (int64_t)c1);
       if (c2 >= 0) acol2[r] = sym_at(A, ld, (int64_t)(s0 + r), (int64_t)c2);
     }
-    if (tid < kprev) {
-      if (c1 >= 0) pl1 = ld_agent(&a.Lpanel[(size_t)c1 * ldp + tid]);
-      if (c2 >= 0) pl2 = ld_agent(&a.Lpanel[(size_t)c2 * ldp + tid]);
-    }
-    for (int t = tid + kThreads; t < kprev; t += kThreads) {
-      if (c1 >= 0) Ln1[t] = ld_agent(&a.Lpanel[(size_t)c1 * ldp + t]);
-      if (c2 >= 0) Ln2[t] = ld_agent(&a.Lpanel[(size_t)c2 * ldp + t]);
-    }
     if (tid == 64 && c1 >= 0) {
-      pax = sym_at(A, ld, (int64_t)c1, (int64_t)c);
-      pdg = A[(int64_t)c1 * (ld + 1)];
+      sh_A1c = sym_at(A, ld, (int64_t)c1, (int64_t)c);
+      sh_A11 = A[(int64_t)c1 * (ld + 1)];
     }
     if (tid == 128 && c2 >= 0) {
-      pax = sym_at(A, ld, (int64_t)c2, (int64_t)c);
-      pdg = A[(int64_t)c2 * (ld + 1)];
+      sh_A2c = sym_at(A, ld, (int64_t)c2, (int64_t)c);
+      sh_A22 = A[(int64_t)c2 * (ld + 1)];
     }
     flush_T();
 
@@ -293,42 +260,18 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
     // workgroup) are reduced on the VALU, the rest of the winning record is
     // looked up by workgroup afterwards
     ArgKey rk{-1.0, INT_MAX, -1};
-    const int npe = k - kprev;   // L entries of the last step (0 at the first)
-    const int own1 = c1 >= 0 ? c1 / R : -1, own2 = c2 >= 0 ? c2 / R : -1;
     for (int w = tid; w < P.G; w += kThreads) {
       const unsigned long long* rw = recs + (size_t)RCP_REC_STRIDE * w;
-      const int n1 = (w == own1) ? npe : 0, n2 = (w == own2) ? npe : 0;
       unsigned long long w0, w1, w2, w3;
-      unsigned long long h10 = 0, l10 = 0, h11 = 0, l11 = 0, h20 = 0, l20 = 0, h21 = 0, l21 = 0;
       unsigned int spins = 0;
       for (;;) {
         w1 = ld_agent(&rw[1]);
         w0 = ld_agent(&rw[0]);
         w2 = ld_agent(&rw[2]);
         w3 = ld_agent(&rw[3]);
-        bool cur = rec_index_current(w1, it) && rec_tag_current(w0, it) &&
-                   rec_tag_current(w2, it) && rec_tag_current(w3, it);
-        if (n1 > 0) {
-          h10 = ld_agent(&rw[4]);
-          l10 = ld_agent(&rw[5]);
-          cur = cur && rec_half_current(h10, it) && rec_half_current(l10, it);
-        }
-        if (n1 > 1) {
-          h11 = ld_agent(&rw[6]);
-          l11 = ld_agent(&rw[7]);
-          cur = cur && rec_half_current(h11, it) && rec_half_current(l11, it);
-        }
-        if (n2 > 0) {
-          h20 = ld_agent(&rw[8]);
-          l20 = ld_agent(&rw[9]);
-          cur = cur && rec_half_current(h20, it) && rec_half_current(l20, it);
-        }
-        if (n2 > 1) {
-          h21 = ld_agent(&rw[10]);
-          l21 = ld_agent(&rw[11]);
-          cur = cur && rec_half_current(h21, it) && rec_half_current(l21, it);
-        }
-        if (cur) break;
+        if (rec_index_current(w1, it) && rec_tag_current(w0, it) && rec_tag_current(w2, it) &&
+            rec_tag_current(w3, it))
+          break;
         if ((++spins & 1023u) == 0) {
           if (ld_agent(P.ex.abort_flag)) break;
           if (spins > (1u << 22)) {
@@ -342,29 +285,14 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
       sh_rsrc[par][w] = rec_src(w1);
       sh_rark[par][w] = rec_untag(w2);
       sh_rarr[par][w] = rec_untag(w3);
-      if (n1 > 0) Ln1[kprev] = rec_join(h10, l10);
-      if (n1 > 1) Ln1[kprev + 1] = rec_join(h11, l11);
-      if (n2 > 0) Ln2[kprev] = rec_join(h20, l20);
-      if (n2 > 1) Ln2[kprev + 1] = rec_join(h21, l21);
       if (key_better(o, rk)) rk = o;
     }
     __syncthreads();   // every record seen: all earlier stores of all workgroups visible
-    // what the gap loaded into registers
-    if (tid < nown) {
-      if (c1 >= 0) acol1[tid] = pf1;
-      if (c2 >= 0) acol2[tid] = pf2;
-    }
-    if (tid < kprev) {
-      if (c1 >= 0) Ln1[tid] = pl1;
-      if (c2 >= 0) Ln2[tid] = pl2;
-    }
-    if (tid == 64 && c1 >= 0) {
-      sh_A1c = pax;
-      sh_A11 = pdg;
-    }
-    if (tid == 128 && c2 >= 0) {
-      sh_A2c = pax;
-      sh_A22 = pdg;
+    // L rows of the two window candidates for the next pivot (entries < k
+    // were stored by their owners before their records)
+    for (int t = tid; t < k; t += kThreads) {
+      if (c1 >= 0) Ln1[t] = ld_agent(&a.Lpanel[(size_t)c1 * ldp + t]);
+      if (c2 >= 0) Ln2[t] = ld_agent(&a.Lpanel[(size_t)c2 * ldp + t]);
     }
     rk = block_argmax(rk, shk);   // (its barriers also order the LDS lookups below)
     Rec rc{rk.val, rk.pos, -1, 0.0, 0.0, rk.idx};
@@ -518,7 +446,6 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
     }
     __syncthreads();
     const int kold = k;
-    kprev = kold;
     k += sstep;
     it += 1;
     if (k >= bb) break;

@@ -227,6 +227,188 @@ __global__ void __launch_bounds__(kThreads) select_kernel(SelectParams a) {
     for (int t = tid; t <= a.bb && t < a.N; t += kThreads) a.win[t] = win[t];
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident variant, for l <= 144 rows and R <= 64 columns per
+// workgroup (the sketch of the whole trailing matrix at b = 128, p = 16 and
+// N <= 16384): thread (wave w, lane) holds rows i = rq + 16 u (u < 9) of
+// columns c = 4 cg + e (e < 4), rq = lane % 16, cg = 4 w + lane / 16.  The
+// 16 row groups of a column are the 16 lanes of one DPP row, so every sum
+// over a column is four lane exchanges; the reflection is register
+// arithmetic (applied to every column, taken or not: the taken ones are
+// never read again, and an orthogonal map keeps them finite), and the
+// winner's residual is read from the exchange straight into registers.
+// ---------------------------------------------------------------------------
+constexpr int kRegRows = 9;
+constexpr int kRegCols = 4;
+
+__device__ __forceinline__ double sum16(double v) {
+  v += xchg<1>(v);
+  v += xchg<2>(v);
+  v += xchg<4>(v);
+  v += xchg<8>(v);
+  return v;
+}
+
+__global__ void __launch_bounds__(kThreads) select_reg_kernel(SelectParams a) {
+  __builtin_amdgcn_s_setprio(3);
+  extern __shared__ int win[];   // [bb + 2]
+  __shared__ ArgKey shk[kThreads / 64];
+  __shared__ ArgKey shr[kThreads / 64];
+  __shared__ int sh_src[2][256];
+  // per column (c = 4 cg + e): squared residual norm and position (-1: no
+  // column); kept in LDS to leave the registers to the slab
+  __shared__ double nrm[16 * kRegCols];
+  __shared__ int posl[16 * kRegCols];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int rq = lane & 15;
+  const int cg = 4 * (tid >> 6) + (lane >> 4);
+  const int g = blockIdx.x;
+  const int l = a.l;
+  const int s0 = g * a.R;
+  const int nown = max(0, min(a.R, a.N - s0));
+
+  // my columns' rows
+  double d[kRegRows][kRegCols];
+  if (tid < 16 * kRegCols) posl[tid] = (tid < nown) ? s0 + tid : -1;
+#pragma unroll
+  for (int e = 0; e < kRegCols; ++e) {
+    const int c = 4 * cg + e;
+    const double* col = a.B + (int64_t)min(s0 + c, a.N - 1) * a.lpad;   // clamped; unused if c >= nown
+#pragma unroll
+    for (int u = 0; u < kRegRows; ++u) {
+      const int i = rq + 16 * u;
+      const double bv = col[min(i, l - 1)];
+      d[u][e] = (c < nown && i < l) ? bv : 0.0;
+    }
+  }
+  for (int t = tid; t <= a.bb; t += kThreads) win[t] = t;
+  // squared norms of the full columns (step 0)
+#pragma unroll
+  for (int e = 0; e < kRegCols; ++e) {
+    double sq = 0.0;
+#pragma unroll
+    for (int u = 0; u < kRegRows; ++u) sq = fma(d[u][e], d[u][e], sq);
+    sq = sum16(sq);
+    if (rq == 0) nrm[4 * cg + e] = sq;
+  }
+  __syncthreads();
+
+  const int nsteps = min(min(a.bb, l), a.N);
+  for (int j = 0; j < nsteps; ++j) {
+    const int par = j & 1;
+    // ---- my best untaken column (position >= j) by squared residual norm
+    ArgKey best{-1.0, 0x7fffffff, -1};
+    if (tid < 16 * kRegCols && posl[tid] >= j) best = ArgKey{nrm[tid], posl[tid], s0 + tid};
+    best = block_argmax(best, shk);
+    // ---- publish my candidate's residual (the 16 lanes of its column
+    // group), then its record
+    if (best.idx >= 0 && (best.idx - s0) / kRegCols == cg) {
+      const int e = (best.idx - s0) % kRegCols;
+      double* dst = a.ex.vec + ((size_t)par * a.G + g) * a.ex.vec_stride;
+      // one branch per column slot keeps every register index a constant
+#pragma unroll
+      for (int ee = 0; ee < kRegCols; ++ee)
+        if (ee == e) {
+#pragma unroll
+          for (int u = 0; u < kRegRows; ++u) {
+            const int i = rq + 16 * u;
+            if (i >= j && i < l) st_agent(&dst[i], d[u][ee]);
+          }
+        }
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    unsigned long long* rec = a.ex.rec + (size_t)par * a.G * kRecStride;
+    if (tid == 0) {
+      st_agent(&rec[kRecStride * g], rec_tag(best.val, j));
+      st_agent(&rec[kRecStride * g + 1], rec_word1(best.pos, best.idx, j));
+    }
+    // ---- global winner: one thread polls one workgroup's record
+    ArgKey cand{-1.0, 0x7fffffff, -1};
+    for (int w = tid; w < a.G; w += kThreads) {
+      unsigned long long w0, w1;
+      unsigned int spins = 0;
+      for (;;) {
+        w1 = ld_agent(&rec[kRecStride * w + 1]);
+        w0 = ld_agent(&rec[kRecStride * w]);
+        if (rec_index_current(w1, j) && rec_tag_current(w0, j)) break;
+        if ((++spins & 1023u) == 0) {
+          if (ld_agent(a.ex.abort_flag)) break;
+          if (spins > (1u << 22)) {
+            st_agent(a.ex.abort_flag, 1);
+            break;
+          }
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      ArgKey o{rec_untag(w0), rec_pos(w1), w};
+      sh_src[par][w] = rec_src(w1);
+      if (key_better(o, cand)) cand = o;
+    }
+    cand = block_argmax(cand, shr);
+    if (cand.val <= 0.0) break;   // all residuals zero: no further pivots
+    const int gw = cand.idx;
+    const int pw = cand.pos;
+    const int sw = sh_src[par][gw];
+    // ---- the winner's residual, rows j .. l-1, into registers (reads
+    // clamped into that range, values outside it zero)
+    const double* xv = a.ex.vec + ((size_t)par * a.G + gw) * a.ex.vec_stride;
+    double v[kRegRows];
+#pragma unroll
+    for (int u = 0; u < kRegRows; ++u) {
+      const int i = rq + 16 * u;
+      const double xr = ld_agent(&xv[min(max(i, j), l - 1)]);
+      v[u] = (i > j && i < l) ? xr : 0.0;
+    }
+    const double xj = ld_agent(&xv[j]);
+    // ---- transposition: the winner goes to position j
+    const int sj = win[j];
+    if (pw != j && tid < 16 * kRegCols && posl[tid] >= 0) {
+      if (s0 + tid == sw) posl[tid] = j;
+      else if (s0 + tid == sj) posl[tid] = pw;
+    }
+    __syncthreads();
+    if (tid == 0 && pw != j) {
+      win[j] = sw;
+      if (pw <= a.bb) win[pw] = sj;
+    }
+    // ---- Householder v = x + sign(x_j) ||x|| e_j, beta = 1 / (||x|| (||x|| +
+    // |x_j|)), from the winner's published squared norm
+    const double nx = sqrt(cand.val);
+    const double vj = xj + copysign(nx, xj);
+    const double beta = 1.0 / (nx * (nx + fabs(xj)));
+#pragma unroll
+    for (int u = 0; u < kRegRows; ++u)
+      if (rq + 16 * u == j) v[u] = vj;
+    // ---- reflect, and the next squared norms (rows j+1 .. l-1)
+#pragma unroll
+    for (int e = 0; e < kRegCols; ++e) {
+      double dot = 0.0;
+#pragma unroll
+      for (int u = 0; u < kRegRows; ++u) dot = fma(v[u], d[u][e], dot);
+      const double gmm = beta * sum16(dot);
+      double sq = 0.0;
+#pragma unroll
+      for (int u = 0; u < kRegRows; ++u) {
+        const int i = rq + 16 * u;
+        d[u][e] = fma(-gmm, v[u], d[u][e]);
+        const double f = fma(d[u][e], d[u][e], sq);
+        sq = (i > j && i < l) ? f : sq;
+      }
+      const double t = sum16(sq);
+      if (rq == 0 && posl[4 * cg + e] > j) nrm[4 * cg + e] = t;
+    }
+    __syncthreads();
+  }
+  // ---- results
+  if (tid < 16 * kRegCols && posl[tid] >= 0) a.posof[s0 + tid] = posl[tid];
+  if (g == 0)
+    for (int t = tid; t <= a.bb && t < a.N; t += kThreads) a.win[t] = win[t];
+}
+
 }  // namespace
 
 int select_grid(int N, int lpad, int num_cu) {
@@ -242,7 +424,7 @@ int select_grid(int N, int lpad, int num_cu) {
 }
 
 void launch_select(const double* B, int lpad, int l, int N, int bb, int* posof, int* win,
-                   Exchange ex, int G, hipStream_t s) {
+                   Exchange ex, int G, bool reg_ok, hipStream_t s) {
   SelectParams p;
   p.B = B;
   p.lpad = lpad;
@@ -254,11 +436,17 @@ void launch_select(const double* B, int lpad, int l, int N, int bb, int* posof, 
   p.posof = posof;
   p.win = win;
   p.ex = ex;
+  void* args[] = {&p};
+  if (reg_ok && l <= 16 * kRegRows && p.R <= 16 * kRegCols && G <= 256) {
+    const size_t lds = (size_t)(bb + 2) * 4;
+    hipLaunchCooperativeKernel((const void*)select_reg_kernel, dim3(G), dim3(kThreads), args, lds,
+                               s);
+    return;
+  }
   const size_t lds = (size_t)p.R * (l | 1) * 8 + (size_t)lpad * 8 + (size_t)p.R * 8 +
                      (size_t)p.R * 4 + (size_t)(bb + 2) * 4 + 64;
   hipFuncSetAttribute((const void*)select_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)lds);
-  void* args[] = {&p};
   hipLaunchCooperativeKernel((const void*)select_kernel, dim3(G), dim3(kThreads), args, lds, s);
 }
 
