@@ -24,8 +24,9 @@ namespace {
 // formed transposed, C(i, r) = sum_t L(i, t) T(r, t), so that the 16 lanes
 // of an accumulator column hold 16 consecutive sketch rows and the stores
 // are contiguous.  Both operands go through LDS in chunks of 32 k values:
-// L rows (64 x 32) and T columns (lpad x 32).  Wave w owns columns
-// 16 w .. 16 w + 15 and all row fragments.
+// L rows (64 x 32, negated) and T columns (lpad x 32).  Wave w owns columns
+// 16 w .. 16 w + 15 and all row fragments; its accumulators start from the
+// old sketch columns.
 // ---------------------------------------------------------------------------
 constexpr int kSuCols = 64;
 constexpr int kSuK = 32;
@@ -43,21 +44,62 @@ __global__ void __launch_bounds__(256) sketch_update_kernel(
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int i0 = m + blockIdx.x * kSuCols;
   const int nrf = lpad / 16;
+  // the accumulators start from the old sketch columns B(:, srcat[i]) (all
+  // reads issued before the k loop) and the staged L is negated, so the
+  // epilogue only stores; acc[f]: lane l, element v = (column
+  // 16 w + acc_row(l, v), row 16 f + l%16)
   rcp_d4 acc[NRF];
+  {
+    int sv[4];
 #pragma unroll
-  for (int f = 0; f < NRF; ++f) acc[f] = rcp_d4{0.0, 0.0, 0.0, 0.0};
+    for (int v = 0; v < 4; ++v) sv[v] = srcat[min(i0 + 16 * w + acc_row(lane, v), N - 1)];
+#pragma unroll
+    for (int f = 0; f < NRF; ++f) {
+      const int r = 16 * f + acc_col(lane);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double x = B[(size_t)sv[v] * lpad + min(r, l - 1)];
+        acc[f][v] = (f < nrf && r < l) ? x : 0.0;
+      }
+    }
+  }
+  // staging: every thread issues all its loads of a chunk before its first
+  // LDS store.  L: thread tid takes column tid / 4 (its source read once)
+  // and 8 consecutive k values; T: 8 elements per thread per pass.
+  const int cc = tid >> 2, t8 = (tid & 3) * 8;
+  const int isrc = srcat[min(i0 + cc, N - 1)];
+  const bool col_ok = i0 + cc < N;
   for (int k0 = 0; k0 < m; k0 += kSuK) {
     const int kn = min(kSuK, m - k0);
-    __syncthreads();
-    for (int e = tid; e < kSuCols * kSuK; e += 256) {
-      const int cc = e / kSuK, t = e - cc * kSuK;
-      const int i = i0 + cc;
-      Ls[cc * (kSuK + 1) + t] =
-          (i < N && t < kn) ? Lp[(size_t)srcat[i] * ldp + k0 + t] : 0.0;
+    double lv[8];
+    const double* lrow = Lp + (size_t)isrc * ldp + k0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = t8 + u;
+      const double x = lrow[min(t, kn - 1)];
+      lv[u] = (col_ok && t < kn) ? -x : 0.0;
     }
-    for (int e = tid; e < kSuK * lpad; e += 256) {
-      const int t = e / lpad, r = e - t * lpad;
-      Ts[t * ldt + r] = (t < kn) ? T[(size_t)(k0 + t) * lpad + r] : 0.0;
+    __syncthreads();   // the previous chunk's products are done with Ls, Ts
+#pragma unroll
+    for (int u = 0; u < 8; ++u) Ls[cc * (kSuK + 1) + t8 + u] = lv[u];
+    const int tot = kSuK * lpad;
+    for (int e0 = 0; e0 < tot; e0 += 256 * 8) {
+      double tv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = min(e0 + tid + 256 * u, tot - 1);
+        const int t = e / lpad, r = e - t * lpad;
+        const double x = T[(size_t)(k0 + min(t, kn - 1)) * lpad + r];
+        tv[u] = (t < kn) ? x : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + tid + 256 * u;
+        if (e < tot) {
+          const int t = e / lpad, r = e - t * lpad;
+          Ts[t * ldt + r] = tv[u];
+        }
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -74,17 +116,15 @@ __global__ void __launch_bounds__(256) sketch_update_kernel(
       }
     }
   }
-  // acc[f]: lane l, element v = (column 16 w + l/16 + 4 v, row 16 f + l%16)
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int i = i0 + 16 * w + acc_row(lane, v);
     if (i >= N) continue;
-    const int s = srcat[i];
 #pragma unroll
     for (int f = 0; f < NRF; ++f) {
       if (f < nrf) {
         const int r = 16 * f + acc_col(lane);
-        Bnext[(size_t)(i - m) * lpad + r] = (r < l) ? B[(size_t)s * lpad + r] - acc[f][v] : 0.0;
+        Bnext[(size_t)(i - m) * lpad + r] = (r < l) ? acc[f][v] : 0.0;
       }
     }
   }
