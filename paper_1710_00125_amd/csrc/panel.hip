@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
   double* Lrow = smem;                      // [R][ldp] L rows of my sources
   double* vcol = Lrow + (size_t)R * ldp;    // [R] current column on my rows
   double* acolv = vcol + R;                 // [3][R] A(s, .) for c, win[k+1], win[k+2]
-  double* Adiag = acolv + 3 * R;            // [R] A(s, s)
+  double* Adiag = acolv + 3 * R;            // [R] current diagonal a_ss of my rows
   double* avec = Adiag + R;                 // [R] A(s, r)
   double* Lp = avec + R;                    // [ldp] L row of the pivot
   double* Wp = Lp + ldp;                    // [ldp] its W row
@@ -216,21 +216,11 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
     best = block_argmax(best, shk);
     const bool have = best.idx >= 0;
     const int rl = have ? best.idx - s0 : 0;
-    {
-      // the candidate's current diagonal a_rr (formed only here) from its W row
-      const double* xr = Lrow + (size_t)rl * ldp;
-      if (have)
-        for (int t = tid; t < k; t += kThreads) Wr[t] = w_entry(xr, Dd, Ds, kind, t);
-      __syncthreads();
-      if (tid < 16) {
-        const double dsum = dot16_lanes(xr, Wr, have ? k : 0, tid);
-        if (tid == 0) {
-          sh_rec[0] = rec_tag(best.val, it);
-          sh_rec[1] = rec_word1(best.pos, best.idx, it);
-          sh_rec[2] = rec_tag(have ? vcol[rl] : 0.0, it);
-          sh_rec[3] = rec_tag(have ? Adiag[rl] - dsum : 0.0, it);
-        }
-      }
+    if (tid == 0) {
+      sh_rec[0] = rec_tag(best.val, it);
+      sh_rec[1] = rec_word1(best.pos, best.idx, it);
+      sh_rec[2] = rec_tag(have ? vcol[rl] : 0.0, it);
+      sh_rec[3] = rec_tag(have ? Adiag[rl] : 0.0, it);
     }
     // publish the record after every store of this workgroup so far (its
     // multipliers of the last step) has completed
@@ -365,6 +355,8 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
         if (live) {
           double* Lrr = Lrow + (size_t)r * ldp;
           double* Lg = a.Lpanel + (size_t)(s0 + r) * ldp;
+          // the row's current diagonal loses L(r, t) W(r, t) for the new
+          // columns (W entries as w_entry forms them)
           if (kase == 3) {
             double l1, l2;
             mult_2x2(vcol[r], vr, akk, ark, arr, det, l1, l2);
@@ -372,10 +364,13 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
             Lrr[k + 1] = l2;
             st_agent(&Lg[k], l1);
             st_agent(&Lg[k + 1], l2);
+            const double w1 = fma(l1, akk, l2 * ark), w2 = fma(l1, ark, l2 * arr);
+            Adiag[r] -= fma(l1, w1, l2 * w2);
           } else {
             const double l1 = mult_1x1(kase == 2 ? vr : vcol[r], dpiv);
             Lrr[k] = l1;
             st_agent(&Lg[k], l1);
+            Adiag[r] = fma(-l1, l1 * dpiv, Adiag[r]);
           }
         } else if (kase == 3 && s0 + r == rsrc) {
           // inside a 2x2 block L(k+1, k) = 0
