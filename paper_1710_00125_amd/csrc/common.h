@@ -250,39 +250,37 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 // ---------------------------------------------------------------------------
 // The one definition of a Schur-column entry used by every kernel that forms
 // one:  a = A(s, c) - sum_{t < i} L(s, t) W(c, t).  The sum over t is split
-// into 16 contiguous chunks of ceil(i/16) terms, each an fma chain in
-// increasing t, and the 16 chunk sums are added by a balanced binary tree
-// ((c0 + c1) + (c2 + c3)) + ... .  Sixteen lanes (one chunk each, xor
-// shuffles 1, 2, 4, 8) or four lanes (four chunks each, then xor 1, 2) give
-// the same bits, because every level of the tree adds the same two values
-// (IEEE addition is commutative).  So a value that one workgroup forms for
-// its own row and another workgroup forms redundantly agree exactly.
+// into 16 interleaved chunks -- chunk j holds the terms t = j, j + 16,
+// j + 32, ... -- each an fma chain in increasing t, and the 16 chunk sums are
+// added by a balanced binary tree ((c0 + c1) + (c2 + c3)) + ... .  Sixteen
+// lanes (one chunk each, xor shuffles 1, 2, 4, 8) or four lanes (four chunks
+// each, then xor 1, 2) give the same bits, because every level of the tree
+// adds the same two values (IEEE addition is commutative).  So a value that
+// one workgroup forms for its own row and another workgroup forms
+// redundantly agree exactly.  Interleaving puts the 16 chunks' terms of one
+// step in 16 consecutive words (no LDS bank conflicts between the lanes).
 // ---------------------------------------------------------------------------
-// x and y must point into LDS: the loads of a batch of eight are issued
-// unconditionally (an LDS read past the end of the allocation returns 0)
-// and the accumulator is selected for the terms inside the chunk, so the
+// x and y must point into LDS: the loads of a batch of eight terms are
+// issued unconditionally (an LDS read past the end of the allocation
+// returns 0) and the accumulator is selected for the terms below i, so the
 // batch compiles to straight-line code.
 template <typename T>
 __device__ __forceinline__ T dot_chunk16(const T* __restrict__ x, const T* __restrict__ y,
                                          int i, int j) {
-  const int cs = (i + 15) >> 4;
-  const int t0 = j * cs;
-  const int t1 = min(i, t0 + cs);
   T s = T(0);
-  // loads of 8 terms are issued before their fma chain (same order of adds)
-  for (int b = t0; b < t1; b += 8) {
+  for (int b = j; b < i; b += 128) {
     T xs[8], ys[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      xs[u] = x[b + u];
-      ys[u] = y[b + u];
+      xs[u] = x[b + 16 * u];
+      ys[u] = y[b + 16 * u];
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      // the loaded words past the chunk may hold anything (even NaN):
+      // the loaded words past the sum may hold anything (even NaN):
       // select the accumulator, never multiply by a masked zero
       const T f = fma(xs[u], ys[u], s);
-      s = (b + u < t1) ? f : s;
+      s = (b + 16 * u < i) ? f : s;
     }
   }
   return s;

@@ -99,8 +99,9 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
   const PanelArgs& a = P.a;
   extern __shared__ double smem[];
   const int R = P.R, ldp = a.ldp, ldt = P.ldt, ntr = P.ntr;
-  double* Lrow = smem;                      // [R][ldp] L rows of my sources
-  double* vcol = Lrow + (size_t)R * ldp;    // [R] current column on my rows
+  const int ldl = ldp | 1;                  // odd LDS row stride (fewer bank conflicts)
+  double* Lrow = smem;                      // [R][ldl] L rows of my sources
+  double* vcol = Lrow + (size_t)R * ldl;    // [R] current column on my rows
   double* acolv = vcol + R;                 // [3][R] A(s, .) for c, win[k+1], win[k+2]
   double* Adiag = acolv + 3 * R;            // [R] current diagonal a_ss of my rows
   double* avec = Adiag + R;                 // [R] A(s, r)
@@ -205,7 +206,7 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
     for (int rb = 0; rb < nown; rb += kRowsPerPass) {
       const int r = rb + rho;
       const bool live = r < nown && posl[r] > k;
-      const double dsum = dot16_quad(Lrow + (size_t)(live ? r : 0) * ldp, Wp, live ? k : 0, q);
+      const double dsum = dot16_quad(Lrow + (size_t)(live ? r : 0) * ldl, Wp, live ? k : 0, q);
       if (live && q == 0) {
         const double v = acol[r] - dsum;
         vcol[r] = v;
@@ -347,13 +348,13 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
       const bool live = r < nown && pr >= k + sstep;
       double vr = 0.0;
       if (kase >= 2) {
-        const double dsum = dot16_quad(Lrow + (size_t)(live ? r : 0) * ldp, Wr, live ? k : 0, q);
+        const double dsum = dot16_quad(Lrow + (size_t)(live ? r : 0) * ldl, Wr, live ? k : 0, q);
         if (live) vr = avec[r] - dsum;
       }
       if (r < nown && q == 0) {
         posl[r] = pr;
         if (live) {
-          double* Lrr = Lrow + (size_t)r * ldp;
+          double* Lrr = Lrow + (size_t)r * ldl;
           double* Lg = a.Lpanel + (size_t)(s0 + r) * ldp;
           // the row's current diagonal loses L(r, t) W(r, t) for the new
           // columns (W entries as w_entry forms them)
@@ -374,7 +375,7 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
           }
         } else if (kase == 3 && s0 + r == rsrc) {
           // inside a 2x2 block L(k+1, k) = 0
-          Lrow[(size_t)r * ldp + k] = 0.0;
+          Lrow[(size_t)r * ldl + k] = 0.0;
           st_agent(&a.Lpanel[(size_t)rsrc * ldp + k], 0.0);
         }
       }
@@ -494,7 +495,7 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
 }
 
 size_t panel_lds(int R, int ldp, int bb, int ntr, int ldt) {
-  return (size_t)R * ldp * 8 + (size_t)7 * R * 8 + (size_t)12 * ldp * 8 +
+  return (size_t)R * (ldp | 1) * 8 + (size_t)7 * R * 8 + (size_t)12 * ldp * 8 +
          (size_t)ntr * ldt * 8 + (size_t)ldp * 4 + (size_t)R * 4 + (size_t)(bb + 2) * 4 + 64;
 }
 
