@@ -76,6 +76,36 @@ __device__ __forceinline__ double w_entry(const double* x, const double* Dd, con
   return fma(x[t - 1], Ds[t - 1], x[t] * Dd[t]);
 }
 
+// sum_{t<i} x[t] W(t) with W(t) = w_entry(x, .., t) formed on the fly: the
+// chunks, fma order and lane tree of dot16_lanes, so the same bits as
+// dot16_lanes(x, W, i, j) over a stored W row
+__device__ __forceinline__ double dot16_lanes_w(const double* x, const double* Dd,
+                                                const double* Ds, const int* kind, int i, int j) {
+  double s = 0.0;
+  for (int t = j; t < i; t += 16) s = fma(x[t], w_entry(x, Dd, Ds, kind, t), s);
+  s += xchg<1>(s);
+  s += xchg<2>(s);
+  s += xchg<4>(s);
+  s += xchg<8>(s);
+  return s;
+}
+
+// block_argmax with one barrier: the caller guarantees another barrier
+// before sh is written again
+template <int NW = 4>
+__device__ __forceinline__ ArgKey block_argmax1(ArgKey k, ArgKey* sh) {
+  const int lane = threadIdx.x & (RCP_WAVE - 1);
+  const int wid = threadIdx.x / RCP_WAVE;
+  k = wave_argmax(k);
+  if (lane == 0) sh[wid] = k;
+  __syncthreads();
+  ArgKey best = sh[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w)
+    if (key_better(sh[w], best)) best = sh[w];
+  return best;
+}
+
 // one workgroup's candidate, as read back after the barrier
 struct Rec {
   double val;   // |a(r)|, -1 if the workgroup had no candidate
@@ -124,7 +154,7 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
   __shared__ int sh_rsrc[2][kMaxG];
   __shared__ double sh_rark[2][kMaxG], sh_rarr[2][kMaxG];
   __shared__ double sh_akk, sh_Acc, sh_A1c, sh_A2c, sh_A11, sh_A22, sh_Anr;
-  __shared__ double sh_vn, sh_vrn;
+  __shared__ double sh_vn, sh_vrn, sh_sold;
   __shared__ unsigned long long sh_rec[4];
   __shared__ int sh_pend_n, sh_pend_t, sh_pend_s1, sh_pend_s2;
 
@@ -214,7 +244,7 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
         if (key_better(kk, best)) best = kk;
       }
     }
-    best = block_argmax(best, shk);
+    best = block_argmax1(best, shk);   // (the publication barrier follows)
     const bool have = best.idx >= 0;
     const int rl = have ? best.idx - s0 : 0;
     if (tid == 0) {
@@ -401,6 +431,11 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
       const double dsum = dot16_lanes(Lsrc, Wr, k, l16);
       if (l16 == 0) sh_vrn = sh_Anr - dsum;
     }
+    if (cn >= 0 && (tid >> 6) == 3 && (tid & 63) < 16) {
+      // ... and its old L row against its old W row (for a_kk)
+      const double sold = dot16_lanes_w(Lsrc, Dd, Ds, kind, k, l16);
+      if (l16 == 0) sh_sold = sold;
+    }
     if (tid == 0) {
       if (kase >= 2 && rpos != p1) {
         win[p1] = rsrc;
@@ -447,24 +482,21 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
     if (k >= bb) break;
     // ---- the next pivot's new L entries, W entries and a_kk (wave 0; the
     // same in every workgroup)
-    if (tid < 16) {
-      const double sold = dot16_lanes(Lp, Wn, kold, tid);
-      if (tid == 0) {
-        const double vn = sh_vn, vrn = (kase >= 2) ? sh_vrn : 0.0;
-        double l1 = 0.0, l2 = 0.0;
-        if (kase == 3) mult_2x2(vn, vrn, akk, ark, arr, det, l1, l2);
-        else l1 = mult_1x1(kase == 2 ? vrn : vn, dpiv);
-        Lp[kold] = l1;
-        if (kase == 3) Lp[kold + 1] = l2;
-        double tail = 0.0;
-        for (int t = kold; t < k; ++t) {
-          Wn[t] = w_entry(Lp, Dd, Ds, kind, t);
-          tail = fma(Lp[t], Wn[t], tail);
-        }
-        const double Acc = (cn == c) ? sh_Acc : (cn == c1 ? sh_A11 : sh_A22);
-        sh_Acc = Acc;
-        sh_akk = Acc - (sold + tail);
+    if (tid == 0) {
+      const double vn = sh_vn, vrn = (kase >= 2) ? sh_vrn : 0.0;
+      double l1 = 0.0, l2 = 0.0;
+      if (kase == 3) mult_2x2(vn, vrn, akk, ark, arr, det, l1, l2);
+      else l1 = mult_1x1(kase == 2 ? vrn : vn, dpiv);
+      Lp[kold] = l1;
+      if (kase == 3) Lp[kold + 1] = l2;
+      double tail = 0.0;
+      for (int t = kold; t < k; ++t) {
+        Wn[t] = w_entry(Lp, Dd, Ds, kind, t);
+        tail = fma(Lp[t], Wn[t], tail);
       }
+      const double Acc = (cn == c) ? sh_Acc : (cn == c1 ? sh_A11 : sh_A22);
+      sh_Acc = Acc;
+      sh_akk = Acc - (sh_sold + tail);
     }
     {
       double* tmp = Wp;
