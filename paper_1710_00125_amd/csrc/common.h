@@ -27,54 +27,6 @@ __device__ __forceinline__ T ld_agent(const T* p) {
   return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Stride (in 32-bit words) between the arrival flags of two workgroups: one
-// flag per 128-byte line.
-#define RCP_FLAG_STRIDE 32
-
-// Grid-wide barrier for persistent kernels whose workgroups are all resident
-// (launched cooperatively).  flags[g * RCP_FLAG_STRIDE] holds the number of
-// barriers workgroup g has reached; all flags are zeroed before the launch.
-// Each workgroup waits until its own communication stores have completed
-// (s_waitcnt), publishes its arrival (grid_arrive), and polls every other
-// workgroup's flag with one thread per flag (grid_wait); work that needs no
-// other workgroup's data may run between the two.  The waits are bounded: a barrier that
-// never completes (which a correct launch cannot produce) raises *abort_flag
-// instead of spinning forever, and then every later wait returns at once.
-__device__ __forceinline__ void grid_arrive(unsigned int* flags, unsigned int& epoch) {
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  epoch += 1;
-  if (threadIdx.x == 0) st_agent(&flags[blockIdx.x * RCP_FLAG_STRIDE], epoch);
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
-
-__device__ __forceinline__ void grid_wait(unsigned int* flags, unsigned int epoch,
-                                          unsigned int nblocks, int* abort_flag) {
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  for (unsigned int w = threadIdx.x; w < nblocks; w += blockDim.x) {
-    unsigned int spins = 0;
-    while (ld_agent(&flags[w * RCP_FLAG_STRIDE]) < epoch) {
-      if ((++spins & 1023u) == 0) {
-        if (ld_agent(abort_flag)) break;
-        if (spins > (1u << 22)) {
-          st_agent(abort_flag, 1);
-          break;
-        }
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
-  }
-  __syncthreads();
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
-
-__device__ __forceinline__ void grid_barrier(unsigned int* flags, unsigned int& epoch,
-                                             unsigned int nblocks, int* abort_flag) {
-  grid_arrive(flags, epoch);
-  grid_wait(flags, epoch, nblocks, abort_flag);
-}
-
 // ---------------------------------------------------------------------------
 // Step-tagged records of the persistent kernels.  A workgroup publishes its
 // candidate for a step as 64-bit words on its own 128-byte line, each word
@@ -231,20 +183,6 @@ __device__ __forceinline__ double wave_sum64(double v) {
   v += xchg<16>(v);
   v += xchg<32>(v);
   return v;
-}
-
-template <int NW = 4>
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-  const int lane = threadIdx.x & (RCP_WAVE - 1);
-  const int wid = threadIdx.x / RCP_WAVE;
-  v = wave_sum64(v);
-  if (lane == 0) sh[wid] = v;
-  __syncthreads();
-  double s = 0.0;
-#pragma unroll
-  for (int w = 0; w < NW; ++w) s += sh[w];
-  __syncthreads();
-  return s;
 }
 
 // ---------------------------------------------------------------------------

@@ -25,24 +25,18 @@ struct Ctrl {
   int m;            // columns eliminated by the last panel (b or b+1)
   int info;         // first exactly-zero 1x1 pivot, 1-based (INT_MAX: none)
   int nonfinite;    // set if the sketch held a NaN or Inf
-  int abort_flag;   // set if a grid barrier or flag wait timed out
+  int abort_flag;   // set if a wait for another workgroup's record timed out
   long long ncase[4];  // SBKP cases (0)..(3) of Figure 2
 };
 
 // Scratch used by the persistent kernels to exchange per-workgroup
 // candidates (two parities, see the kernels).
 struct Exchange {
-  double* val;      // [2][G]
-  double* aux0;     // [2][G]   signed value / unused
-  double* aux1;     // [2][G]   a_rr of the candidate / unused
-  int* pos;         // [2][G]
-  int* src;         // [2][G]
-  double* vec;      // [2][G][vec_stride]
+  double* vec;      // [2][G][vec_stride] candidate residuals (selection)
   int vec_stride;
   unsigned long long* rec;   // [2][G][16] step-tagged records, one per 128-byte line
                              // (zeroed before each launch)
-  unsigned int* bar;  // grid barrier flags, [G * RCP_FLAG_STRIDE] (zeroed before each launch)
-  int* abort_flag;    // raised by a barrier wait that timed out
+  int* abort_flag;    // raised by a record wait that timed out
 };
 
 // ---- omega.hip

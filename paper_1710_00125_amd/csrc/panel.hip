@@ -18,7 +18,8 @@
 // block sketch update (eq. (3.3) in block form), one column per eliminated
 // pivot: T(:, t) = B(:, piv_t) - sum_{u<t} T(:, u) L11(t, u).
 //
-// One persistent launch of G workgroups, one grid barrier per step.
+// One persistent launch of G workgroups, one exchange of step-tagged records
+// (the cross-workgroup barrier) per step.
 // Workgroup g owns the sources [g R, g R + R) of the block: their L rows and
 // their diagonal entries of A stay in LDS, and it tracks their positions
 // (nothing is physically interchanged).  Per step:

@@ -236,9 +236,8 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
   size_t bytes = 3 * al(nn * esz) + al((size_t)n * lpad * 8) * (2 + 1 + ksplit) +
                  al((size_t)n * ldp * 8) + 2 * al(pack_bytes) +
                  al((size_t)lpad * (b + 2) * 8) + 2 * al((size_t)n * 8) + 3 * al((size_t)n * 4) +
-                 al((size_t)(b + 2) * 4) + al(sizeof(Ctrl)) + 3 * al((size_t)2 * Gmax * 8) +
-                 2 * al((size_t)2 * Gmax * 4) + al((size_t)2 * Gmax * vec_stride * 8) + al((size_t)Gmax * 128) + al((size_t)32 * Gmax * 8) +
-                 4096;
+                 al((size_t)(b + 2) * 4) + al(sizeof(Ctrl)) +
+                 al((size_t)2 * Gmax * vec_stride * 8) + al((size_t)32 * Gmax * 8) + 4096;
   int dev = 0;
   hipGetDevice(&dev);
   if (!g_fact.reserve(bytes, dev)) return RCP_ENOMEM;
@@ -261,15 +260,9 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
   int* win = g_fact.take<int>(b + 2);
   Ctrl* ctrl = g_fact.take<Ctrl>(1);
   Exchange ex;
-  ex.val = g_fact.take<double>(2 * Gmax);
-  ex.aux0 = g_fact.take<double>(2 * Gmax);
-  ex.aux1 = g_fact.take<double>(2 * Gmax);
-  ex.pos = g_fact.take<int>(2 * Gmax);
-  ex.src = g_fact.take<int>(2 * Gmax);
   ex.vec = g_fact.take<double>((size_t)2 * Gmax * vec_stride);
   ex.rec = g_fact.take<unsigned long long>((size_t)32 * Gmax);
   ex.vec_stride = vec_stride;
-  ex.bar = g_fact.take<unsigned int>((size_t)Gmax * 32);
   ex.abort_flag = &ctrl->abort_flag;
 
   if (!g_ctrl_host) {

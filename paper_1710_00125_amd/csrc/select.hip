@@ -13,10 +13,10 @@
 //
 // One persistent launch of G workgroups.  Workgroup g owns the sources
 // (columns at block start) [g R, g R + R) and keeps their l x R slab of B in
-// LDS for the whole block.  Per step it proposes its best column and
-// publishes that column's residual, one grid barrier later every workgroup
-// picks the same winner and builds the same reflector from the published
-// residual.  Interchanges are not applied to any array: each workgroup only
+// LDS (or, for l <= 144 and R <= 64, in registers) for the whole block.  Per
+// step it proposes its best column and publishes that column's residual and
+// a step-tagged record; once every record is in, every workgroup picks the
+// same winner and builds the same reflector from the published residual.  Interchanges are not applied to any array: each workgroup only
 // tracks the positions of its own sources (and all workgroups a replica of
 // the b+1 window positions), so ties are decided by position exactly as in
 // an eager implementation.
