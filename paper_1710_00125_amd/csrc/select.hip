@@ -249,6 +249,27 @@ __device__ __forceinline__ double sum16(double v) {
   return v;
 }
 
+// sum16 of a thread's four column values, stage by stage (same bits)
+__device__ __forceinline__ void sum16_cols(double (&x)[kRegCols]) {
+  double y[kRegCols];
+#pragma unroll
+  for (int e = 0; e < kRegCols; ++e) y[e] = xchg<1>(x[e]);
+#pragma unroll
+  for (int e = 0; e < kRegCols; ++e) x[e] += y[e];
+#pragma unroll
+  for (int e = 0; e < kRegCols; ++e) y[e] = xchg<2>(x[e]);
+#pragma unroll
+  for (int e = 0; e < kRegCols; ++e) x[e] += y[e];
+#pragma unroll
+  for (int e = 0; e < kRegCols; ++e) y[e] = xchg<4>(x[e]);
+#pragma unroll
+  for (int e = 0; e < kRegCols; ++e) x[e] += y[e];
+#pragma unroll
+  for (int e = 0; e < kRegCols; ++e) y[e] = xchg<8>(x[e]);
+#pragma unroll
+  for (int e = 0; e < kRegCols; ++e) x[e] += y[e];
+}
+
 __global__ void __launch_bounds__(kThreads) select_reg_kernel(SelectParams a) {
   __builtin_amdgcn_s_setprio(3);
   extern __shared__ int win[];   // [bb + 2]
@@ -375,6 +396,9 @@ __global__ void __launch_bounds__(kThreads) select_reg_kernel(SelectParams a) {
       win[j] = sw;
       if (pw <= a.bb) win[pw] = sj;
     }
+    bool live[kRegCols];
+#pragma unroll
+    for (int e = 0; e < kRegCols; ++e) live[e] = posl[4 * cg + e] > j;
     // ---- Householder v = x + sign(x_j) ||x|| e_j, beta = 1 / (||x|| (||x|| +
     // |x_j|)), from the winner's published squared norm
     const double nx = sqrt(cand.val);
@@ -383,23 +407,38 @@ __global__ void __launch_bounds__(kThreads) select_reg_kernel(SelectParams a) {
 #pragma unroll
     for (int u = 0; u < kRegRows; ++u)
       if (rq + 16 * u == j) v[u] = vj;
-    // ---- reflect, and the next squared norms (rows j+1 .. l-1)
+    // ---- reflect, and the next squared norms (rows j+1 .. l-1); the four
+    // columns go through each stage together, so that their dependent
+    // chains (fma chains, lane exchanges) overlap
+    double dot[kRegCols], sq[kRegCols];
+#pragma unroll
+    for (int e = 0; e < kRegCols; ++e) dot[e] = 0.0;
+#pragma unroll
+    for (int u = 0; u < kRegRows; ++u)
+#pragma unroll
+      for (int e = 0; e < kRegCols; ++e) dot[e] = fma(v[u], d[u][e], dot[e]);
+    sum16_cols(dot);
 #pragma unroll
     for (int e = 0; e < kRegCols; ++e) {
-      double dot = 0.0;
+      dot[e] *= -beta;
+      sq[e] = 0.0;
+    }
 #pragma unroll
-      for (int u = 0; u < kRegRows; ++u) dot = fma(v[u], d[u][e], dot);
-      const double gmm = beta * sum16(dot);
-      double sq = 0.0;
+    for (int u = 0; u < kRegRows; ++u) {
+      const int i = rq + 16 * u;
+      const bool in = i > j && i < l;
 #pragma unroll
-      for (int u = 0; u < kRegRows; ++u) {
-        const int i = rq + 16 * u;
-        d[u][e] = fma(-gmm, v[u], d[u][e]);
-        const double f = fma(d[u][e], d[u][e], sq);
-        sq = (i > j && i < l) ? f : sq;
+      for (int e = 0; e < kRegCols; ++e) {
+        d[u][e] = fma(dot[e], v[u], d[u][e]);
+        const double dm = in ? d[u][e] : 0.0;   // finite register values
+        sq[e] = fma(dm, dm, sq[e]);
       }
-      const double t = sum16(sq);
-      if (rq == 0 && posl[4 * cg + e] > j) nrm[4 * cg + e] = t;
+    }
+    sum16_cols(sq);
+    if (rq == 0) {
+#pragma unroll
+      for (int e = 0; e < kRegCols; ++e)
+        if (live[e]) nrm[4 * cg + e] = sq[e];
     }
     __syncthreads();
   }
