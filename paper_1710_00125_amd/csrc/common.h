@@ -224,13 +224,32 @@ __device__ __forceinline__ T dot_chunk16(const T* __restrict__ x, const T* __res
   return s;
 }
 
-// four lanes of a quad (q = lane & 3): returns the full sum in all four
+// four lanes of a quad (q = lane & 3): returns the full sum in all four.
+// Lane q forms chunks 4q .. 4q+3 together (their terms of one step are four
+// consecutive words), so the four fma chains overlap; each chunk's chain and
+// the tree are those of dot_chunk16, so the bits are the same.
 template <typename T>
 __device__ __forceinline__ T dot16_quad(const T* __restrict__ x, const T* __restrict__ y, int i,
                                         int q) {
-  const T a = dot_chunk16(x, y, i, 4 * q), b = dot_chunk16(x, y, i, 4 * q + 1);
-  const T c = dot_chunk16(x, y, i, 4 * q + 2), d = dot_chunk16(x, y, i, 4 * q + 3);
-  T v = (a + b) + (c + d);
+  T s[4] = {T(0), T(0), T(0), T(0)};
+  for (int b = 4 * q; b < i; b += 128) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = b + 16 * u;
+      T xs[4], ys[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        xs[c] = x[t + c];
+        ys[c] = y[t + c];
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const T f = fma(xs[c], ys[c], s[c]);   // select, never multiply by a masked zero
+        s[c] = (t + c < i) ? f : s[c];
+      }
+    }
+  }
+  T v = (s[0] + s[1]) + (s[2] + s[3]);
   v += xchg<1>(v);
   v += xchg<2>(v);
   return v;
