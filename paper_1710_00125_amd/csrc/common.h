@@ -269,7 +269,8 @@ __device__ __forceinline__ T dot16_lanes(const T* __restrict__ x, const T* __res
 
 // Element (i, j) of the symmetric matrix whose lower triangle is stored
 // column-major in A with leading dimension ld.
+// (One load from a selected address, not a branch between two loads.)
 template <typename T>
 __device__ __forceinline__ T sym_at(const T* __restrict__ A, int64_t ld, int64_t i, int64_t j) {
-  return (i >= j) ? A[i + j * ld] : A[j + i * ld];
+  return A[(i >= j) ? i + j * ld : j + i * ld];
 }

@@ -69,12 +69,16 @@ __device__ __forceinline__ void mult_2x2(double v, double w, double e00, double 
 
 // W(t) = sum_u L(u) D(u, t) for one row of L; kind[t]: 1 = 1x1,
 // 2 = first of a 2x2 (partner t+1), 0 = second of a 2x2 (partner t-1)
+// (all three forms evaluated and one selected: no branches; the neighbour
+// reads are clamped into the row, and only used where they exist)
 __device__ __forceinline__ double w_entry(const double* x, const double* Dd, const double* Ds,
                                           const int* kind, int t) {
   const int kd = kind[t];
-  if (kd == 1) return x[t] * Dd[t];
-  if (kd == 2) return fma(x[t], Dd[t], x[t + 1] * Ds[t]);
-  return fma(x[t - 1], Ds[t - 1], x[t] * Dd[t]);
+  const int tm = max(t - 1, 0);
+  const double own = x[t] * Dd[t];
+  const double first = fma(x[t], Dd[t], x[t + 1] * Ds[t]);
+  const double second = fma(x[tm], Ds[tm], own);
+  return kd == 1 ? own : (kd == 2 ? first : second);
 }
 
 // sum_{t<i} x[t] W(t) with W(t) = w_entry(x, .., t) formed on the fly: the
@@ -264,8 +268,12 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
     // ---- gap: prefetch the columns of the two window candidates for the
     // next step, and extend T by the previous step's pivots
     for (int r = tid; r < nown; r += kThreads) {
-      if (c1 >= 0) acol1[r] = sym_at(A, ld, (int64_t)(s0 + r), (int64_t)c1);
-      if (c2 >= 0) acol2[r] = sym_at(A, ld, (int64_t)(s0 + r), (int64_t)c2);
+      // both loads issued before either store (sources clamped: a value for
+      // an absent candidate is not stored)
+      const double v1 = sym_at(A, ld, (int64_t)(s0 + r), (int64_t)max(c1, 0));
+      const double v2 = sym_at(A, ld, (int64_t)(s0 + r), (int64_t)max(c2, 0));
+      if (c1 >= 0) acol1[r] = v1;
+      if (c2 >= 0) acol2[r] = v2;
     }
     if (tid == 64 && c1 >= 0) {
       sh_A1c = sym_at(A, ld, (int64_t)c1, (int64_t)c);
