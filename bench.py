@@ -186,7 +186,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="householder16384")
-    ap.add_argument("--cpu-sample", type=int, default=7168,
+    ap.add_argument("--cpu-sample", type=int, default=8192,
                     help="order of the oracle sample (0 skips it)")
     ap.add_argument("--mixed", default="fp32,bf16x3",
                     help="reduced-precision forms to time after the FP64 one "

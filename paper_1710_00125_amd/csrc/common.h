@@ -36,8 +36,13 @@ __device__ __forceinline__ T ld_agent(const T* p) {
 // rounding of the value itself); the index word: (step + 1) in the top 16
 // bits, then 24 bits of position and 24 bits of source (all-ones: none).
 // A record is current when every word carries the step; zeroed memory never
-// is.  Everything a workgroup stored before its record is visible to a
-// reader that has seen the record.
+// is (its index word fails).  The writer stores the index word last (or in
+// the same store instruction as the value words, one 32-byte run of one
+// line) and a reader loads it first: a value word's two tag bits alone
+// cannot tell the step from a zeroed record or from the step four before,
+// so value words are only trusted when read after a current index word.
+// Everything a workgroup stored before its record is visible to a reader
+// that has seen the record.
 // ---------------------------------------------------------------------------
 #define RCP_REC_STRIDE 16   // 64-bit words per record line
 __device__ __forceinline__ unsigned long long rec_tag(double val, int step) {
