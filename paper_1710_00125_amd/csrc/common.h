@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <climits>
 
 #define RCP_WAVE 64
 
@@ -139,24 +140,32 @@ __device__ __forceinline__ bool key_better(const ArgKey& a, const ArgKey& b) {
   return a.pos < b.pos;
 }
 
-template <int K>
-__device__ __forceinline__ void argmax_stage(ArgKey& k) {
-  ArgKey o;
-  o.val = xchg<K>(k.val);
-  o.pos = xchg_i<K>(k.pos);
-  o.idx = xchg_i<K>(k.idx);
-  if (key_better(o, k)) k = o;
-}
-
 // argmax over the 64 lanes of a wave; the result is in every lane
+// (in three cheaper passes than a butterfly over whole keys: the maximum
+// value, then the smallest position among the lanes holding it, then the
+// payload of that lane -- the same winner as key_better picks)
 __device__ __forceinline__ ArgKey wave_argmax(ArgKey k) {
-  argmax_stage<1>(k);
-  argmax_stage<2>(k);
-  argmax_stage<4>(k);
-  argmax_stage<8>(k);
-  argmax_stage<16>(k);
-  argmax_stage<32>(k);
-  return k;
+  double m = k.val;
+  m = fmax(m, xchg<1>(m));
+  m = fmax(m, xchg<2>(m));
+  m = fmax(m, xchg<4>(m));
+  m = fmax(m, xchg<8>(m));
+  m = fmax(m, xchg<16>(m));
+  m = fmax(m, xchg<32>(m));
+  int p = (k.val == m) ? k.pos : INT_MAX;
+  p = min(p, xchg_i<1>(p));
+  p = min(p, xchg_i<2>(p));
+  p = min(p, xchg_i<4>(p));
+  p = min(p, xchg_i<8>(p));
+  p = min(p, xchg_i<16>(p));
+  p = min(p, xchg_i<32>(p));
+  const unsigned long long who = __ballot(k.val == m && k.pos == p);
+  const int src = __ffsll((long long)who) - 1;
+  ArgKey r;
+  r.val = m;
+  r.pos = p;
+  r.idx = __builtin_amdgcn_readlane(k.idx, src);
+  return r;
 }
 
 // Workgroup-wide argmax over NW waves (the workgroup size / 64); the result
