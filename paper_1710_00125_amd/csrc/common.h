@@ -188,6 +188,22 @@ __device__ __forceinline__ ArgKey block_argmax(ArgKey k, ArgKey* sh) {
   return best;
 }
 
+// block_argmax with one barrier: the caller guarantees another barrier
+// before sh is written again
+template <int NW = 4>
+__device__ __forceinline__ ArgKey block_argmax1(ArgKey k, ArgKey* sh) {
+  const int lane = threadIdx.x & (RCP_WAVE - 1);
+  const int wid = threadIdx.x / RCP_WAVE;
+  k = wave_argmax(k);
+  if (lane == 0) sh[wid] = k;
+  __syncthreads();
+  ArgKey best = sh[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w)
+    if (key_better(sh[w], best)) best = sh[w];
+  return best;
+}
+
 // sum over the 64 lanes of a wave (butterfly); the result is in every lane
 __device__ __forceinline__ double wave_sum64(double v) {
   v += xchg<1>(v);

@@ -95,22 +95,6 @@ __device__ __forceinline__ double dot16_lanes_w(const double* x, const double* D
   return s;
 }
 
-// block_argmax with one barrier: the caller guarantees another barrier
-// before sh is written again
-template <int NW = 4>
-__device__ __forceinline__ ArgKey block_argmax1(ArgKey k, ArgKey* sh) {
-  const int lane = threadIdx.x & (RCP_WAVE - 1);
-  const int wid = threadIdx.x / RCP_WAVE;
-  k = wave_argmax(k);
-  if (lane == 0) sh[wid] = k;
-  __syncthreads();
-  ArgKey best = sh[0];
-#pragma unroll
-  for (int w = 1; w < NW; ++w)
-    if (key_better(sh[w], best)) best = sh[w];
-  return best;
-}
-
 // one workgroup's candidate, as read back after the barrier
 struct Rec {
   double val;   // |a(r)|, -1 if the workgroup had no candidate
@@ -324,7 +308,7 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
       if (c1 >= 0) Ln1[t] = ld_agent(&a.Lpanel[(size_t)c1 * ldp + t]);
       if (c2 >= 0) Ln2[t] = ld_agent(&a.Lpanel[(size_t)c2 * ldp + t]);
     }
-    rk = block_argmax(rk, shk);   // (its barriers also order the LDS lookups below)
+    rk = block_argmax1(rk, shk);   // (its barrier also orders the LDS lookups below)
     Rec rc{rk.val, rk.pos, -1, 0.0, 0.0, rk.idx};
     if (rk.idx >= 0) {
       rc.src = sh_rsrc[par][rk.idx];

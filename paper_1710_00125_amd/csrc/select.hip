@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(kThreads) select_kernel(SelectParams a) {
         if (key_better(k, best)) best = k;
       }
     }
-    best = block_argmax(best, shk);
+    best = block_argmax1(best, shk);   // (later barriers precede the next use of shk)
     // ---- publish my candidate's residual, then its record: two 64-bit words
     // that both carry the step, so that one poll of them is the barrier and
     // the read at once (a workgroup's record appears only after its vector)
@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(kThreads) select_kernel(SelectParams a) {
       sh_src[par][w] = rec_src(w1);
       if (key_better(o, cand)) cand = o;
     }
-    cand = block_argmax(cand, shr);
+    cand = block_argmax1(cand, shr);   // (its barrier also orders the sh_src lookup)
     if (cand.val <= 0.0) break;   // all residuals zero: no further pivots
     const int gw = cand.idx;
     const int pw = cand.pos;
@@ -322,7 +322,7 @@ __global__ void __launch_bounds__(kThreads) select_reg_kernel(SelectParams a) {
     // ---- my best untaken column (position >= j) by squared residual norm
     ArgKey best{-1.0, 0x7fffffff, -1};
     if (tid < 16 * kRegCols && posl[tid] >= j) best = ArgKey{nrm[tid], posl[tid], s0 + tid};
-    best = block_argmax(best, shk);
+    best = block_argmax1(best, shk);   // (later barriers precede the next use of shk)
     // ---- publish my candidate's residual (the 16 lanes of its column
     // group), then its record
     if (best.idx >= 0 && (best.idx - s0) / kRegCols == cg) {
@@ -369,7 +369,7 @@ __global__ void __launch_bounds__(kThreads) select_reg_kernel(SelectParams a) {
       sh_src[par][w] = rec_src(w1);
       if (key_better(o, cand)) cand = o;
     }
-    cand = block_argmax(cand, shr);
+    cand = block_argmax1(cand, shr);   // (its barrier also orders the sh_src lookup)
     if (cand.val <= 0.0) break;   // all residuals zero: no further pivots
     const int gw = cand.idx;
     const int pw = cand.pos;
