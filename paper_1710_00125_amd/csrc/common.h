@@ -84,7 +84,9 @@ __device__ __forceinline__ int rec_src(unsigned long long w1) {
 // ---------------------------------------------------------------------------
 template <int CTRL>
 __device__ __forceinline__ int dpp_i(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+  // every lane reads a valid source lane for these controls, so no old value
+  // is needed (no extra move to set one)
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
 }
 template <int K>
 __device__ __forceinline__ int xchg_i(int v);
