@@ -426,11 +426,11 @@ __global__ void __launch_bounds__(kThreads) select_reg_kernel(SelectParams a) {
 #pragma unroll
     for (int u = 0; u < kRegRows; ++u) {
       const int i = rq + 16 * u;
-      const bool in = i > j && i < l;
+      const double in = (i > j && i < l) ? 1.0 : 0.0;   // row mask as a factor
 #pragma unroll
       for (int e = 0; e < kRegCols; ++e) {
         d[u][e] = fma(dot[e], v[u], d[u][e]);
-        const double dm = in ? d[u][e] : 0.0;   // finite register values
+        const double dm = d[u][e] * in;   // finite register values: exact
         sq[e] = fma(dm, dm, sq[e]);
       }
     }
