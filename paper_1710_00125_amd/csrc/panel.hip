@@ -95,6 +95,47 @@ __device__ __forceinline__ double dot16_lanes_w(const double* x, const double* D
   return s;
 }
 
+// dot16_quad for a row of L and a W row whose entries at and past i, up to
+// index 127, are zero (the kernel zeroes its L rows and W rows at the start
+// and only ever writes entries below the current column; both rows hold at
+// least 128 entries, i.e. b >= 126): the first 128 terms need no per-term
+// selects.  Terms 128 and up (a 2x2 pivot at the end
+// of a block of 128) keep them.  Same chunks, chains and tree as
+// dot16_quad; an exactly zero sum may differ in its sign.
+__device__ __forceinline__ double dot16_quad_z(const double* __restrict__ x,
+                                               const double* __restrict__ y, int i, int q) {
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int t = 4 * q + 16 * u;
+    double xs[4], ys[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      xs[c] = x[t + c];
+      ys[c] = y[t + c];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) s[c] = fma(xs[c], ys[c], s[c]);
+  }
+  if (i > 128) {
+    for (int b = 128 + 4 * q; b < i; b += 128) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int t = b + 16 * u;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double f = fma(x[t + c], y[t + c], s[c]);
+          s[c] = (t + c < i) ? f : s[c];
+        }
+      }
+    }
+  }
+  double v = (s[0] + s[1]) + (s[2] + s[3]);
+  v += xchg<1>(v);
+  v += xchg<2>(v);
+  return v;
+}
+
 // one workgroup's candidate, as read back after the barrier
 struct Rec {
   double val;   // |a(r)|, -1 if the workgroup had no candidate
@@ -119,6 +160,7 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
   extern __shared__ double smem[];
   const int R = P.R, ldp = a.ldp, ldt = P.ldt, ntr = P.ntr;
   const int ldl = ldp | 1;                  // odd LDS row stride (fewer bank conflicts)
+  const bool wide = ldp >= 128;             // rows long enough for dot16_quad_z
   double* Lrow = smem;                      // [R][ldl] L rows of my sources
   double* vcol = Lrow + (size_t)R * ldl;    // [R] current column on my rows
   double* acolv = vcol + R;                 // [3][R] A(s, .) for c, win[k+1], win[k+2]
@@ -171,6 +213,14 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
   }
   for (int t = tid; t <= bb && t < a.N; t += kThreads) win[t] = a.win[t];
   for (int e = tid; e < ntr * ldt; e += kThreads) Tl[e] = 0.0;
+  // L rows and W rows start at zero: entries past the current column stay
+  // zero (the contract of dot16_quad_z)
+  for (int e = tid; e < R * ldl; e += kThreads) Lrow[e] = 0.0;
+  for (int t = tid; t < ldp; t += kThreads) {
+    Wp[t] = 0.0;
+    Wn[t] = 0.0;
+    Wr[t] = 0.0;
+  }
   if (tid == 0) sh_pend_n = 0;
   __syncthreads();
   int cur = 0;   // which of the three acolv slots holds the pivot column
@@ -225,7 +275,9 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
     for (int rb = 0; rb < nown; rb += kRowsPerPass) {
       const int r = rb + rho;
       const bool live = r < nown && posl[r] > k;
-      const double dsum = dot16_quad(Lrow + (size_t)(live ? r : 0) * ldl, Wp, live ? k : 0, q);
+      const double* xr = Lrow + (size_t)(live ? r : 0) * ldl;
+      const double dsum =
+          wide ? dot16_quad_z(xr, Wp, live ? k : 0, q) : dot16_quad(xr, Wp, live ? k : 0, q);
       if (live && q == 0) {
         const double v = acol[r] - dsum;
         vcol[r] = v;
@@ -371,7 +423,9 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
       const bool live = r < nown && pr >= k + sstep;
       double vr = 0.0;
       if (kase >= 2) {
-        const double dsum = dot16_quad(Lrow + (size_t)(live ? r : 0) * ldl, Wr, live ? k : 0, q);
+        const double* xr = Lrow + (size_t)(live ? r : 0) * ldl;
+        const double dsum =
+            wide ? dot16_quad_z(xr, Wr, live ? k : 0, q) : dot16_quad(xr, Wr, live ? k : 0, q);
         if (live) vr = avec[r] - dsum;
       }
       if (r < nown && q == 0) {
