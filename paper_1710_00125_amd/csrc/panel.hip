@@ -492,6 +492,10 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
       sh_pend_t = k;
       sh_pend_s1 = piv1;
       sh_pend_s2 = piv2;
+    }
+    // (the block's D, kind and the global D / ipiv from wave 2, beside wave
+    // 0's bookkeeping: wave 2 is idle here unless the step took case 2 or 3)
+    if (tid == 128) {
       if (kase == 3) {
         Dd[k] = akk;
         Dd[k + 1] = arr;
@@ -566,8 +570,8 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
     const int r = tr0 + j * P.G;
     if (r < lpad) a.T[(size_t)t * lpad + r] = Tl[(size_t)j * ldt + t];
   }
-  if (g == 0 && tid == 0) {
-    a.ctrl->m = k;
+  if (g == 0 && tid == 0) a.ctrl->m = k;
+  if (g == 0 && tid == 128) {
     for (int i = 0; i < 4; ++i)
       atomicAdd((unsigned long long*)&a.ctrl->ncase[i], (unsigned long long)ncase[i]);
   }
