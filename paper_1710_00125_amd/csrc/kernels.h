@@ -125,11 +125,15 @@ void launch_finalize_L(int64_t n, const void* Lwork, const int64_t* P, const int
 void launch_find_zero_pivot(int64_t n, const double* D, const int8_t* ipiv, int* out,
                             hipStream_t s);
 // B <- A^{-1} B with the factors (L double when l_f32 == 0, float otherwise;
-// the right-hand sides and all arithmetic stay FP64).
+// the right-hand sides and all arithmetic stay FP64).  work holds
+// solve_work_doubles(n, nrhs) doubles, sync solve_sync_words() words; the
+// caller zeroes sync once: the last word is an abort word that the solves
+// only ever raise (a wait that timed out).
 void launch_solve(int64_t n, const void* L, int l_f32, const double* D, const int8_t* ipiv,
-                  const int64_t* perm, int64_t nrhs, double* B, int64_t ldb, double* Y,
+                  const int64_t* perm, int64_t nrhs, double* B, int64_t ldb, double* work,
                   unsigned int* sync, hipStream_t s);
 size_t solve_sync_words(int64_t n);
+size_t solve_work_doubles(int64_t n, int64_t nrhs);
 
 // ---- batched.hip  (many small systems, one workgroup each)
 constexpr int kBatchMaxN = 512;

@@ -456,12 +456,13 @@ int solve_impl(int64_t n, const void* L, int l_f32, const double* D, const int8_
   int dev = 0;
   hipGetDevice(&dev);
   const size_t words = solve_sync_words(n);
-  const size_t bytes = al((size_t)n * 8 * 8) + al(words * 4) + al(64);
+  const size_t bytes = al(solve_work_doubles(n, nrhs) * 8) + al(words * 4) + al(64);
   if (!g_solve.reserve(bytes, dev)) return RCP_ENOMEM;
-  double* Y = g_solve.take<double>((size_t)n * 8);
+  double* Y = g_solve.take<double>(solve_work_doubles(n, nrhs));
   unsigned int* sync = g_solve.take<unsigned int>(words);
   int* zp = g_solve.take<int>(16);
   hipStream_t s = g_stream;
+  RCP_CHECK(hipMemsetAsync(sync, 0, words * sizeof(unsigned int), s));
   const int zhost = zero_pivot(n, D, ipiv, zp, s);
   if (zhost < 0) return zhost;
   if (zhost != INT_MAX) return zhost;
@@ -571,13 +572,14 @@ int rcp_solve_ir(int64_t n, const double* A, int64_t lda, const float* L, const 
   const double tol_in = 1e-6;
   const size_t words = solve_sync_words(n);
   const size_t nvec = (size_t)n * NR;
-  const size_t bytes = al(nvec * 8) * 5 + al((size_t)(m + 1) * nvec * 8) +
+  const size_t bytes = al(solve_work_doubles(n, NR) * 8) + al(nvec * 8) * 4 +
+                       al((size_t)(m + 1) * nvec * 8) +
                        al(symv_work_doubles(n, NR) * 8) + al(gmres_dot_doubles(m + 1, NR) * 8) +
                        al((size_t)(m + 2) * NR * 8) * 3 + al((size_t)NR * (m + 1) * 8) * 3 +
                        al((size_t)NR * m * m * 8) + al(NR * 8) * 2 + al(NR * 4) +
                        al(gmres_state_bytes(NR)) + al(4 * 8) + al(words * 4) + al(64) + 4096;
   if (!g_solve.reserve(bytes, dev)) return RCP_ENOMEM;
-  double* Y = g_solve.take<double>(nvec);          // solve scratch
+  double* Y = g_solve.take<double>(solve_work_doubles(n, NR));   // solve scratch
   double* xk = g_solve.take<double>(nvec);         // current iterate
   double* r = g_solve.take<double>(nvec);          // residual / preconditioned residual
   double* w = g_solve.take<double>(nvec);          // Arnoldi vector
@@ -600,6 +602,7 @@ int rcp_solve_ir(int64_t n, const double* A, int64_t lda, const float* L, const 
   unsigned int* sync = g_solve.take<unsigned int>(words);
   int* zp = g_solve.take<int>(16);
   (void)yls;
+  RCP_CHECK(hipMemsetAsync(sync, 0, words * sizeof(unsigned int), s));
 
   const int zhost = zero_pivot(n, D, ipiv, zp, s);
   if (zhost < 0) return zhost;

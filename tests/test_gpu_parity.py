@@ -107,10 +107,13 @@ def test_factor_kkt_matches_oracle(rcp, n, b, p, seed):
     _factor_case(rcp, A, b, p, seed)
 
 
-@pytest.mark.parametrize("nrhs", [1, 4])
-def test_solve_backward_error(rcp, nrhs):
+# the chained triangular solves work on 64-row blocks and hold up to eight
+# right-hand sides at once (two at a time going back): ragged orders, a single
+# block, and counts that split into uneven groups
+@pytest.mark.parametrize("n,nrhs", [(300, 1), (300, 4), (300, 3), (300, 11), (50, 2), (1000, 5)])
+def test_solve_backward_error(rcp, n, nrhs):
     import torch
-    n, b, p, seed = 300, 32, 8, 4
+    b, p, seed = 32, 8, 4
     _say(f"solve n={n} nrhs={nrhs}")
     A = gen.gaussian_sym(n, seed)
     rhs = gen.rhs(n, nrhs, seed)
