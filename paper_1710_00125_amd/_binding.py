@@ -177,6 +177,13 @@ class Factors:
     precision: int = 0   # 0 = FP64, RCP_PREC_FP32, RCP_PREC_BF16X3
 
 
+def _colmajor(A):
+    """The column-major storage of A (memory[i + j n] = A[i, j]): A's own
+    memory when A is a transposed view of a contiguous tensor, else a copy."""
+    At = A.t()
+    return At if At.is_contiguous() else At.contiguous()
+
+
 def rcp_factor(A, b, p, seed):
     """P A P^T = L D L^T of the symmetric matrix whose lower triangle is A's.
 
@@ -186,7 +193,7 @@ def rcp_factor(A, b, p, seed):
     torch = _torch()
     n = A.shape[0]
     assert A.dim() == 2 and A.shape[1] == n and A.dtype == torch.float64 and A.is_cuda
-    Acm = A.t().contiguous()                   # memory[i + j n] = A[i, j] (read only)
+    Acm = _colmajor(A)                         # memory[i + j n] = A[i, j] (read only)
     dev = A.device
     perm = torch.empty(n, dtype=torch.int64, device=dev)
     Lbuf = torch.empty((n, n), dtype=torch.float64, device=dev)
@@ -205,7 +212,7 @@ def rcp_factor_mp(A, b, p, seed, precision=RCP_PREC_FP32):
     torch = _torch()
     n = A.shape[0]
     assert A.dim() == 2 and A.shape[1] == n and A.dtype == torch.float64 and A.is_cuda
-    Acm = A.t().contiguous()
+    Acm = _colmajor(A)
     dev = A.device
     perm = torch.empty(n, dtype=torch.int64, device=dev)
     Lbuf = torch.empty((n, n), dtype=torch.float32, device=dev)
@@ -259,7 +266,7 @@ def rcp_solve_ir(A, f, B, tol=1e-13, max_outer=10, restart=30, raise_on_noconv=T
     torch = _torch()
     assert f.precision, "rcp_solve_ir needs the factors of rcp_factor_mp"
     n = A.shape[0]
-    Acm = A.t().contiguous()
+    Acm = _colmajor(A)
     Bcm, vec = _rhs_cm(B)
     nrhs = Bcm.shape[0]
     Xcm = torch.empty_like(Bcm)

@@ -573,7 +573,7 @@ int rcp_solve_ir(int64_t n, const double* A, int64_t lda, const float* L, const 
   const size_t words = solve_sync_words(n);
   const size_t nvec = (size_t)n * NR;
   const size_t bytes = al(solve_work_doubles(n, NR) * 8) + al(nvec * 8) * 4 +
-                       al((size_t)(m + 1) * nvec * 8) +
+                       al((size_t)(m + 1) * nvec * 8) + al((size_t)m * nvec * 8) +
                        al(symv_work_doubles(n, NR) * 8) + al(gmres_dot_doubles(m + 1, NR) * 8) +
                        al((size_t)(m + 2) * NR * 8) * 3 + al((size_t)NR * (m + 1) * 8) * 3 +
                        al((size_t)NR * m * m * 8) + al(NR * 8) * 2 + al(NR * 4) +
@@ -585,6 +585,7 @@ int rcp_solve_ir(int64_t n, const double* A, int64_t lda, const float* L, const 
   double* w = g_solve.take<double>(nvec);          // Arnoldi vector
   double* bb = g_solve.take<double>(nvec);         // right-hand sides, ld n
   double* V = g_solve.take<double>((size_t)(m + 1) * nvec);
+  double* Zb = g_solve.take<double>((size_t)m * nvec);   // M^{-1} of the basis vectors
   double* swork = g_solve.take<double>(symv_work_doubles(n, NR));
   double* part = g_solve.take<double>(gmres_dot_doubles(m + 1, NR));
   double* h = g_solve.take<double>((size_t)(m + 2) * NR);
@@ -665,15 +666,18 @@ int rcp_solve_ir(int64_t n, const double* A, int64_t lda, const float* L, const 
       if (outer >= max_outer) break;
       ++outer;
       // one GMRES cycle on A M^{-1} y = r (right preconditioning: the true
-      // residual is the one minimised), then d = M^{-1} V y
+      // residual is the one minimised), then d = M^{-1} V y, formed as Z y
+      // from the preconditioned basis vectors z_k = M^{-1} v_k kept on the
+      // way (one solve fewer per cycle than applying M^{-1} to V y)
       launch_norm2(n, nr, r, part, nrm, s);
       launch_gmres_start(nr, m, nrm, st, g, s);
       launch_scale(n, nr, r, nrm, V, s);
       for (int k = 0; k < m; ++k) {
         const double* vk = V + (size_t)k * nr * n;
-        RCP_CHECK(hipMemcpyAsync(w, vk, (size_t)n * nr * 8, hipMemcpyDeviceToDevice, s));
-        precond(w, nr);
-        launch_symv(n, A, lda, w, n, nr, 0, nullptr, n, w, n, 0, swork, s);
+        double* zk = Zb + (size_t)k * nr * n;
+        RCP_CHECK(hipMemcpyAsync(zk, vk, (size_t)n * nr * 8, hipMemcpyDeviceToDevice, s));
+        precond(zk, nr);
+        launch_symv(n, A, lda, zk, n, nr, 0, nullptr, n, w, n, 0, swork, s);
         launch_mdot(n, nr, k + 1, V, w, part, h, nullptr, s);
         launch_mgs_sub(n, nr, k + 1, V, h, w, s);
         launch_mdot(n, nr, k + 1, V, w, part, h2, h, s);
@@ -691,10 +695,9 @@ int rcp_solve_ir(int64_t n, const double* A, int64_t lda, const float* L, const 
       int it = 0;
       for (int c = 0; c < nr; ++c) it = std::max(it, gmres_state_iters(st_host.data(), c));
       inner += it;
-      // w = V y, then x += M^{-1} w
+      // w = Z y = M^{-1} V y, then x += w
       RCP_CHECK(hipMemsetAsync(w, 0, (size_t)n * nr * 8, s));
-      launch_lsq_update(n, nr, m, st, g, R, yls, kk, V, w, n, s);
-      precond(w, nr);
+      launch_lsq_update(n, nr, m, st, g, R, yls, kk, Zb, w, n, s);
       launch_axpy(n, nr, w, xk, s);
     }
     RCP_CHECK(hipMemcpy2DAsync(X + c0 * ldx, ldx * 8, xk, n * 8, n * 8, nr,

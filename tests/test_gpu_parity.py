@@ -126,3 +126,24 @@ def test_solve_backward_error(rcp, n, nrhs):
     xr = orcp.solve(ref, rhs)
     assert np.all(tb.backward_error(A, X, rhs) <= 1e-13)
     assert np.max(np.abs(X - xr)) <= 1e-9 * max(1.0, np.max(np.abs(xr)))
+
+
+def test_column_major_view_reads_the_same_triangle(rcp):
+    """A tensor whose transpose is contiguous is handed over without a copy;
+    only the lower triangle is read either way (garbage above it here)."""
+    import torch
+    n, b, p, seed = 260, 32, 8, 6
+    _say(f"column-major view n={n}")
+    A = gen.gaussian_sym(n, seed)
+    M = A.copy()
+    M[np.triu_indices(n, 1)] = 1e30          # never read
+    row_major = torch.from_numpy(M).to(_dev())
+    col_major = torch.from_numpy(np.ascontiguousarray(M.T)).to(_dev()).t()
+    assert not col_major.is_contiguous() and col_major.t().is_contiguous()
+    assert torch.equal(row_major, col_major)
+    f1 = rcp.rcp_factor(row_major, b, p, seed)
+    f2 = rcp.rcp_factor(col_major, b, p, seed)
+    assert torch.equal(f1.perm, f2.perm) and torch.equal(f1.ipiv, f2.ipiv)
+    assert torch.equal(f1.L, f2.L) and torch.equal(f1.D, f2.D)
+    ref = orcp.factor(A, b, p, seed=seed)
+    assert np.array_equal(f2.perm.cpu().numpy(), ref.perm)
