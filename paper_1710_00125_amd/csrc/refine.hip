@@ -25,22 +25,25 @@ constexpr int kChunkTiles = 16;    // tiles per workgroup along a strip
 __device__ __forceinline__ double wave_sum(double v) { return wave_sum64(v); }
 
 // ABS = true: |A| and x = 1 (row sums of |A|); NR = right-hand sides.
-// Per tile every thread loads 16 entries of one row (a wave reads 16 column
-// runs of 64 rows), keeps them for its part of the row sums and stages them
-// in LDS, from where it takes 16 entries of one column for the column sums.
+// Lane = row of the tile, wave g = columns 16 g + u (u < 16): every load is
+// a coalesced column run, and the next tile's loads are in flight while the
+// current one is used.  Row sums: each wave's 16-column share, added over
+// the four waves through LDS (one barrier per tile, two alternating
+// buffers).  Column sums: each lane accumulates its rows' products for the
+// wave's 16 columns over the whole chunk in registers; they are added over
+// the lanes once at the end (through a wave-private LDS transpose).
 template <bool ABS, int NR>
 __global__ void __launch_bounds__(256) symv_tiles_kernel(int64_t n, const double* __restrict__ A,
                                                         int64_t lda, const double* __restrict__ X,
                                                         int64_t ldx, int nr, int nb, int nch,
                                                         double* __restrict__ Prow,
                                                         double* __restrict__ Pcol) {
-  __shared__ double tile[kT][kT + 1];   // tile[jj][ii] = A(i0 + ii, j0 + jj)
   __shared__ double xj[NR][kT];
-  __shared__ double xi[NR][kT];
-  __shared__ double red[4][NR][kT];
+  __shared__ double red[2][4][NR][kT];
+  __shared__ double tr[4][16][kT + 1];   // per wave: column u, lane
   const int tid = threadIdx.x;
-  const int r = tid & 63;           // load: row within the tile; column pass: column
-  const int grp = tid >> 6;         // load: 16-column group; column pass: 16-row group
+  const int r = tid & 63;
+  const int g = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int J = blockIdx.x / nch;
   const int sc = blockIdx.x % nch;
   const int I0 = J + sc * kChunkTiles;
@@ -52,62 +55,88 @@ __global__ void __launch_bounds__(256) symv_tiles_kernel(int64_t n, const double
     const int64_t j = j0 + jj;
     xj[c][jj] = (j < n && c < nr) ? (ABS ? 1.0 : X[j + c * ldx]) : 0.0;
   }
-  double colacc[NR];
+  // my 16 entries of tile I (row i0 + r, columns j0 + 16 g + u) and my
+  // row's x: straight-line loads from clamped addresses, zero outside the
+  // matrix; the strict upper part of the diagonal tile is masked where it
+  // is used
+  auto load_a = [&](int I, double (&a)[16], double (&xi)[NR]) {
+    const int64_t i = (int64_t)I * kT + r;
+    const int64_t ic = min(i, n - 1);
+    double v[16];
 #pragma unroll
-  for (int c = 0; c < NR; ++c) colacc[c] = 0.0;
-
+    for (int u = 0; u < 16; ++u) v[u] = A[ic + min(j0 + 16 * g + u, n - 1) * lda];
+    double xv[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) xv[c] = ABS ? 1.0 : X[ic + min(c, nr - 1) * ldx];
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      a[u] = (i < n && j0 + 16 * g + u < n) ? (ABS ? fabs(v[u]) : v[u]) : 0.0;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) xi[c] = (c < nr && i < n) ? xv[c] : 0.0;
+  };
+  double colacc[16][NR];
+#pragma unroll
+  for (int u = 0; u < 16; ++u)
+#pragma unroll
+    for (int c = 0; c < NR; ++c) colacc[u][c] = 0.0;
+  double a0[16], a1[16], x0[NR], x1[NR];
+  load_a(I0, a0, x0);
+  __syncthreads();   // xj
   for (int I = I0; I < I1; ++I) {
-    const int64_t i0 = (int64_t)I * kT;
-    const int64_t i = i0 + r;
-    double a[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int64_t j = j0 + grp * 16 + u;
-      double v = 0.0;
-      if (i < n && j < n && (I > J || i >= j)) v = A[i + j * lda];
-      a[u] = ABS ? fabs(v) : v;
-      tile[grp * 16 + u][r] = a[u];
-    }
-    if (tid < 64)
-#pragma unroll
-      for (int c = 0; c < NR; ++c) xi[c][r] = (c < nr && i < n) ? (ABS ? 1.0 : X[i + c * ldx]) : 0.0;
-    __syncthreads();
-    // row sums: my row r over my 16 columns
+    load_a(min(I + 1, I1 - 1), a1, x1);   // the last tile again at the end
+    const bool diag = I == J;
     double rowacc[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c) rowacc[c] = 0.0;
 #pragma unroll
-    for (int u = 0; u < 16; ++u)
+    for (int u = 0; u < 16; ++u) {
+      const int jj = 16 * g + u;
+      const double ar = (!diag || r >= jj) ? a0[u] : 0.0;   // lower, diagonal included
+      const double ac = (!diag || r > jj) ? a0[u] : 0.0;    // strictly lower
 #pragma unroll
-      for (int c = 0; c < NR; ++c) rowacc[c] = fma(a[u], xj[c][grp * 16 + u], rowacc[c]);
-#pragma unroll
-    for (int c = 0; c < NR; ++c) red[grp][c][r] = rowacc[c];
-    // column sums: column r over my 16 rows, strictly below the diagonal
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int ii = grp * 16 + v;
-      if (I > J || ii > r) {
-        const double t = tile[r][ii];
-#pragma unroll
-        for (int c = 0; c < NR; ++c) colacc[c] = fma(t, xi[c][ii], colacc[c]);
+      for (int c = 0; c < NR; ++c) {
+        rowacc[c] = fma(ar, xj[c][jj], rowacc[c]);
+        colacc[u][c] = fma(ac, x0[c], colacc[u][c]);
       }
     }
+    const int buf = (I - I0) & 1;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) red[buf][g][c][r] = rowacc[c];
     __syncthreads();
-    if (tid < 64) {
+    if (g == 0) {
+      const int64_t i = (int64_t)I * kT + r;
       for (int c = 0; c < nr; ++c) {
-        const double v = (red[0][c][r] + red[1][c][r]) + (red[2][c][r] + red[3][c][r]);
+        const double v = (red[buf][0][c][r] + red[buf][1][c][r]) +
+                         (red[buf][2][c][r] + red[buf][3][c][r]);
         if (i < n) Prow[((int64_t)c * nb + J) * n + i] = v;
       }
     }
-  }
-  __syncthreads();
 #pragma unroll
-  for (int c = 0; c < NR; ++c) red[grp][c][r] = colacc[c];
-  __syncthreads();
-  if (tid < 64)
-    for (int c = 0; c < nr; ++c)
-      Pcol[(((int64_t)c * nb + J) * nch + sc) * kT + r] =
-          (red[0][c][r] + red[1][c][r]) + (red[2][c][r] + red[3][c][r]);
+    for (int u = 0; u < 16; ++u) a0[u] = a1[u];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) x0[c] = x1[c];
+  }
+  // column sums over the lanes: column 16 g + (r >> 2) from lanes h, h + 4,
+  // ... (h = r & 3) of my own wave
+  const int uc = r >> 2, h = r & 3;
+#pragma unroll
+  for (int c = 0; c < NR; ++c) {
+    if (c >= nr) break;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) tr[g][u][r] = colacc[u][c];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double sum = 0.0;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) sum += tr[g][uc][4 * t + h];
+    sum += xchg<1>(sum);
+    sum += xchg<2>(sum);
+    if (h == 0) Pcol[(((int64_t)c * nb + J) * nch + sc) * kT + 16 * g + uc] = sum;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
 }
 
 // Y(i, c) = sum_{J <= I(i)} Prow[c][J][i] + sum_s Pcol[c][I(i)][s][i % 64];
@@ -121,6 +150,7 @@ __global__ void symv_reduce_kernel(int64_t n, int nr, int nb, int nch,
     const int64_t c = e / n, i = e - c * n;
     const int I = (int)(i / kT);
     double y = 0.0;
+#pragma unroll 8
     for (int J = 0; J <= I; ++J) y += Prow[((int64_t)c * nb + J) * n + i];
     const int nchI = (nb - I + kChunkTiles - 1) / kChunkTiles;
     for (int s = 0; s < nchI; ++s) y += Pcol[(((int64_t)c * nb + I) * nch + s) * kT + (i % kT)];
