@@ -62,13 +62,12 @@ void launch_iota64(int64_t n, int64_t* P, hipStream_t s);
 // ---- select.hip  (partial QRCP on the block's sketch)
 // B: sketch of the trailing block (lpad x N column-major), picks bb columns.
 // Writes posof[0..N) (block-relative positions of the sources) and
-// win[0..bb] (source at each window position).  reg_ok allows the
-// register-resident kernel (about 130 registers per lane) where the shape
-// fits it; false keeps the LDS kernel (80 registers), which fits beside a
-// concurrent update with more than 184 registers.
+// win[0..bb] (source at each window position).  The register-resident
+// kernel (about 140 registers per lane) runs where the shape fits it, the
+// LDS kernel elsewhere.
 int select_grid(int N, int lpad, int num_cu);
 void launch_select(const double* B, int lpad, int l, int N, int bb, int* posof, int* win,
-                   Exchange ex, int G, bool reg_ok, hipStream_t s);
+                   Exchange ex, int G, hipStream_t s);
 
 // ---- panel.hip  (SBKP elimination of one block)
 struct PanelArgs {

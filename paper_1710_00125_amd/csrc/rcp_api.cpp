@@ -307,8 +307,7 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
     Scope sc(KSelect);
     const int Gs = select_grid(Nb, lpad, ncu);
     hipMemsetAsync(ex.rec, 0, (size_t)32 * Gmax * sizeof(unsigned long long), s);
-    launch_select(Bc, lpad, l, Nb, std::min<int>(b, Nb), posof, win, ex, Gs,
-                  prec != kPrecBF16x3, s);
+    launch_select(Bc, lpad, l, Nb, std::min<int>(b, Nb), posof, win, ex, Gs, s);
   };
   while (K0 < n) {
     const int N = (int)(n - K0);

@@ -463,7 +463,7 @@ int select_grid(int N, int lpad, int num_cu) {
 }
 
 void launch_select(const double* B, int lpad, int l, int N, int bb, int* posof, int* win,
-                   Exchange ex, int G, bool reg_ok, hipStream_t s) {
+                   Exchange ex, int G, hipStream_t s) {
   SelectParams p;
   p.B = B;
   p.lpad = lpad;
@@ -476,7 +476,7 @@ void launch_select(const double* B, int lpad, int l, int N, int bb, int* posof, 
   p.win = win;
   p.ex = ex;
   void* args[] = {&p};
-  if (reg_ok && l <= 16 * kRegRows && p.R <= 16 * kRegCols && G <= 256) {
+  if (l <= 16 * kRegRows && p.R <= 16 * kRegCols && G <= 256) {
     const size_t lds = (size_t)(bb + 2) * 4;
     hipLaunchCooperativeKernel((const void*)select_reg_kernel, dim3(G), dim3(kThreads), args, lds,
                                s);

@@ -203,9 +203,12 @@ void launch_update(const void* Acur, void* Anext, int64_t ld, const int* rowsrc,
   const int64_t T = (N2 + kTile - 1) / kTile;
   const int64_t ntiles = T * (T + 1) / 2;
   const int64_t per = (ntiles + kXcd - 1) / kXcd;
-  // two workgroups per CU (leaves registers for a concurrent selection
-  // kernel), never more than the tiles need
-  const int64_t nwg = std::min<int64_t>((int64_t)2 * num_cu / kXcd, per) * kXcd;
+  // workgroups per CU: as many as leave room in the register file for the
+  // concurrent register-resident selection kernel (about 140 registers):
+  // two of the FP64 and FP32 forms (at most 184), one of the BF16x3 form
+  // (about 210); never more than the tiles need
+  const int wpc = prec == kPrecBF16x3 ? 1 : 2;
+  const int64_t nwg = std::min<int64_t>((int64_t)wpc * num_cu / kXcd, per) * kXcd;
   const dim3 grid((unsigned)std::max<int64_t>(kXcd, nwg));
   if (prec == kPrecF64)
     hipLaunchKernelGGL(update_kernel<PackF64>, grid, dim3(256), 0, s, (const double*)Acur,
