@@ -28,6 +28,8 @@ constexpr int kBMaxN = kBatchMaxN;  // largest system
 constexpr int kBMaxL = kBatchMaxL;  // largest l = b + p
 constexpr int kBMaxB = kBatchMaxB;  // largest block size
 constexpr int kBldp = kBMaxB + 2;   // row stride of the block L rows (b + 1 used)
+constexpr int kQc = 8;              // QRCP: sketch rows per batch of loads
+constexpr int kQr = 16;             // QRCP: longest column segment held in registers
 
 struct KernelArgs {
   const BatchSys* sys;
@@ -59,6 +61,7 @@ struct Shared {
   int info;                  // first exactly zero 1x1 pivot (1-based), INT_MAX if none
   int n2x2;
   union {                    // phase-specific buffers
+    double qn[kBMaxN];       // QRCP: squared norm of each residual column
     struct {
       double colv[kBMaxN];   // current column (position s - k)
       double colv2[kBMaxN];  // second column of a 2x2 pivot
@@ -137,25 +140,100 @@ struct Sys {
 // interchange positions p < q (both >= kc, the first live position) in the
 // trailing working matrix, the sketch (and residual while the QRCP runs),
 // the rows of the block's L columns so far (kk of them), the rows of the
-// finished L columns, and the permutation
+// finished L columns, and the permutation.  Every thread first loads all of
+// its pairs (at most two of W and of the finished L, one of the sketch,
+// residual and block L), then stores them: one round trip to memory
+// instead of one per loop.  Pairs that do not exist for a thread load from
+// a valid address and store nothing.
 template <typename TA>
 __device__ void swap_positions(Sys<TA>& S, int p, int q, int kc, int kk) {
   if (p == q) return;
   if (p > q) swp(p, q);
-  const int n = S.n, tid = threadIdx.x;
+  const int n = S.n, l = S.l, tid = threadIdx.x;
   TA* W = S.W;
-  for (int t = kc + tid; t < n; t += kBT) {
-    if (t < p) swp(W[p + (int64_t)t * n], W[q + (int64_t)t * n]);
-    else if (t == p) swp(W[p + (int64_t)p * n], W[q + (int64_t)q * n]);
-    else if (t < q) swp(W[t + (int64_t)p * n], W[q + (int64_t)t * n]);
-    else if (t > q) swp(W[t + (int64_t)p * n], W[t + (int64_t)q * n]);
+  // W (lower triangle, column-major): the element pairs of row/column p and q
+  static_assert(kBMaxN <= 2 * kBT, "two W and finished-L pairs per thread");
+  int64_t wa[2], wb[2];
+  bool wl[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int t = kc + tid + i * kBT;
+    int64_t x, y;
+    if (t < p) {
+      x = p + (int64_t)t * n;
+      y = q + (int64_t)t * n;
+    } else if (t == p) {
+      x = p + (int64_t)p * n;
+      y = q + (int64_t)q * n;
+    } else if (t < q) {
+      x = t + (int64_t)p * n;
+      y = q + (int64_t)t * n;
+    } else {
+      x = t + (int64_t)p * n;
+      y = t + (int64_t)q * n;
+    }
+    wl[i] = t < n && t != q;
+    wa[i] = wl[i] ? x : 0;
+    wb[i] = wl[i] ? y : 0;
   }
-  for (int e = tid; e < S.l; e += kBT) {
-    swp(S.B[(int64_t)p * S.l + e], S.B[(int64_t)q * S.l + e]);
-    if (S.r_live) swp(S.R[(int64_t)p * S.l + e], S.R[(int64_t)q * S.l + e]);
+  TA wx[2], wy[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    wx[i] = W[wa[i]];
+    wy[i] = W[wb[i]];
   }
-  for (int t = tid; t < kk; t += kBT) swp(S.Lp[p * kBldp + t], S.Lp[q * kBldp + t]);
-  for (int t = tid; t < S.K0; t += kBT) swp(S.Lw[p + (int64_t)t * n], S.Lw[q + (int64_t)t * n]);
+  // sketch and residual rows e = tid (< l), block L column t = tid (< kk),
+  // finished L columns t = tid, tid + kBT (< K0)
+  const int e = min(tid, l - 1);
+  const bool he = tid < l;
+  double* Bp_ = S.B + (int64_t)p * l + e;
+  double* Bq_ = S.B + (int64_t)q * l + e;
+  double* Rp_ = S.R + (int64_t)p * l + e;
+  double* Rq_ = S.R + (int64_t)q * l + e;
+  const double bx = *Bp_, by = *Bq_;
+  const double rx = *Rp_, ry = *Rq_;
+  const int tk = min(tid, max(kk - 1, 0));
+  const bool hk = tid < kk;
+  const double lx = S.Lp[p * kBldp + tk], ly = S.Lp[q * kBldp + tk];
+  int64_t fa[2], fb[2];
+  bool fl[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int t = tid + i * kBT;
+    fl[i] = t < S.K0;
+    fa[i] = fl[i] ? p + (int64_t)t * n : 0;
+    fb[i] = fl[i] ? q + (int64_t)t * n : 0;
+  }
+  TA fx[2], fy[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    fx[i] = S.Lw[fa[i]];
+    fy[i] = S.Lw[fb[i]];
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+    if (wl[i]) {
+      W[wa[i]] = wy[i];
+      W[wb[i]] = wx[i];
+    }
+  if (he) {
+    *Bp_ = by;
+    *Bq_ = bx;
+    if (S.r_live) {
+      *Rp_ = ry;
+      *Rq_ = rx;
+    }
+  }
+  if (hk) {
+    S.Lp[p * kBldp + tk] = ly;
+    S.Lp[q * kBldp + tk] = lx;
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+    if (fl[i]) {
+      S.Lw[fa[i]] = fy[i];
+      S.Lw[fb[i]] = fx[i];
+    }
   if (tid == 0) swp(S.perm[p], S.perm[q]);
   __syncthreads();
 }
@@ -282,8 +360,26 @@ __global__ void __launch_bounds__(kBT) batched_kernel(KernelArgs a) {
     S.K0 = K0;
     const int N = n - K0;
     const int bb = min(b, N);
-    // ---- partial QRCP on the sketch of the trailing matrix
+    // ---- partial QRCP on the sketch of the trailing matrix.  The squared
+    // norm of every residual column (rows j .. l-1, summed in increasing
+    // row order) is kept in LDS: formed here for j = 0, then by each
+    // reflection from the values it stores.  Column segments are read in
+    // batches of kQc independent loads (clamped addresses), the sums still
+    // taken in row order.
     for (int64_t e = tid; e < (int64_t)l * N; e += kBT) S.R[(int64_t)K0 * l + e] = S.B[(int64_t)K0 * l + e];
+    for (int c = K0 + tid; c < n; c += kBT) {
+      const double* rc = S.B + (int64_t)c * l;
+      double ss = 0.0;
+      for (int r0 = 0; r0 < l; r0 += kQc) {
+        double t[kQc];
+#pragma unroll
+        for (int u = 0; u < kQc; ++u) t[u] = rc[min(r0 + u, l - 1)];
+#pragma unroll
+        for (int u = 0; u < kQc; ++u)
+          if (r0 + u < l) ss = fma(t[u], t[u], ss);
+      }
+      sh.qn[c] = ss;
+    }
     S.r_live = true;
     __syncthreads();
     const int qsteps = min(bb, l);
@@ -292,9 +388,7 @@ __global__ void __launch_bounds__(kBT) batched_kernel(KernelArgs a) {
       double best = -1.0;
       int bpos = INT_MAX;
       for (int c = pj + tid; c < n; c += kBT) {
-        const double* rc = S.R + (int64_t)c * l;
-        double ss = 0.0;
-        for (int r = j; r < l; ++r) ss = fma(rc[r], rc[r], ss);
+        const double ss = sh.qn[c];
         if (key_gt(ss, c, best, bpos)) {
           best = ss;
           bpos = c;
@@ -302,6 +396,7 @@ __global__ void __launch_bounds__(kBT) batched_kernel(KernelArgs a) {
       }
       wg_argmax(best, bpos, sh);
       if (!(best > 0.0)) break;
+      if (tid == 0 && bpos != pj) swp(sh.qn[pj], sh.qn[bpos]);
       swap_positions(S, pj, bpos, K0, 0);
       // Householder vector of x = R(j:l, pj): v = x + sign(x_j) ||x|| e_j,
       // beta = 2 / v.v = 1 / (||x|| (||x|| + |x_j|))
@@ -311,12 +406,59 @@ __global__ void __launch_bounds__(kBT) batched_kernel(KernelArgs a) {
       const double beta = 1.0 / (nx * (nx + fabs(xj)));
       for (int r = j + tid; r < l; r += kBT) sh.v[r] = (r == j) ? xj + copysign(nx, xj) : xr[r];
       __syncthreads();
+      if (l - j <= kQr) {
+        // my column segments one at a time in registers: one round of
+        // loads per column
+        for (int c = pj + 1 + tid; c < n; c += kBT) {
+          double* rc = S.R + (int64_t)c * l;
+          double x[kQr];
+#pragma unroll
+          for (int u = 0; u < kQr; ++u) x[u] = rc[min(j + u, l - 1)];
+          double g = 0.0;
+#pragma unroll
+          for (int u = 0; u < kQr; ++u)
+            if (j + u < l) g = fma(sh.v[j + u], x[u], g);
+          g *= beta;
+          double ss = 0.0;   // the next pick's squared norm: rows j+1 .. l-1
+#pragma unroll
+          for (int u = 0; u < kQr; ++u)
+            if (j + u < l) {
+              const double nv = fma(-g, sh.v[j + u], x[u]);
+              rc[j + u] = nv;
+              if (u > 0) ss = fma(nv, nv, ss);
+            }
+          sh.qn[c] = ss;
+        }
+      } else {
       for (int c = pj + 1 + tid; c < n; c += kBT) {
         double* rc = S.R + (int64_t)c * l;
         double g = 0.0;
-        for (int r = j; r < l; ++r) g = fma(sh.v[r], rc[r], g);
+        for (int r0 = j; r0 < l; r0 += kQc) {
+          double t[kQc];
+#pragma unroll
+          for (int u = 0; u < kQc; ++u) t[u] = rc[min(r0 + u, l - 1)];
+#pragma unroll
+          for (int u = 0; u < kQc; ++u)
+            if (r0 + u < l) g = fma(sh.v[r0 + u], t[u], g);
+        }
         g *= beta;
-        for (int r = j; r < l; ++r) rc[r] = fma(-g, sh.v[r], rc[r]);
+        double ss = 0.0;   // the next pick's squared norm: rows j+1 .. l-1
+        for (int r0 = j; r0 < l; r0 += kQc) {
+          double t[kQc];
+#pragma unroll
+          for (int u = 0; u < kQc; ++u) t[u] = rc[min(r0 + u, l - 1)];
+#pragma unroll
+          for (int u = 0; u < kQc; ++u) {
+            const int r = r0 + u;
+            if (r < l) {
+              const double nv = fma(-g, sh.v[r], t[u]);
+              rc[r] = nv;
+              if (r > j) ss = fma(nv, nv, ss);
+            }
+          }
+        }
+        sh.qn[c] = ss;
+      }
       }
       __syncthreads();
     }
