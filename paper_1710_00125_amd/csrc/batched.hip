@@ -58,6 +58,9 @@ struct Shared {
   double red_v[4];
   int red_p[4];
   double sc[8];
+  double bd[kBMaxB];         // the block's D: diagonal
+  double bs[kBMaxB];         //                sub-diagonal of its 2x2 blocks
+  int bk[kBMaxB];            //                kinds (ipiv)
   int info;                  // first exactly zero 1x1 pivot (1-based), INT_MAX if none
   int n2x2;
   union {                    // phase-specific buffers
@@ -66,7 +69,10 @@ struct Shared {
       double colv[kBMaxN];   // current column (position s - k)
       double colv2[kBMaxN];  // second column of a 2x2 pivot
     } p;
-    double T[kBMaxL][kBldp];   // sketch update factor B~_1 L11^{-T}
+    struct {
+      double T[kBMaxL][kBldp];           // sketch update factor B~_1 L11^{-T}
+      double l11[kBMaxB][kBMaxB + 1];    // the block's L11 (rows t, columns u < t)
+    } su;
     struct {
       double ta[64][kBMaxB + 1];   // trailing-update tiles: L21 rows
       double tb[64][kBMaxB + 1];   //                        W21 rows
@@ -567,41 +573,112 @@ __global__ void __launch_bounds__(kBT) batched_kernel(KernelArgs a) {
     const int m = kk;
     const int K1 = K0 + m;
     const int N2 = n - K1;
-    // ---- store the block's L columns (strictly lower part)
-    for (int64_t e = tid; e < (int64_t)m * N; e += kBT) {
-      const int t = (int)(e / N), s = K0 + (int)(e - (int64_t)t * N);
-      if (s > K0 + t) S.Lw[s + (int64_t)(K0 + t) * n] = (TA)S.Lp[s * kBldp + t];
+    // ---- store the block's L columns (strictly lower part), the sketch
+    // update B(:, K1:n) -= T L21^T with T = B~_1 L11^{-T}, and the W rows
+    // of the trailing positions
+    if (N2 > 0) {
+      // T in place: the block's sketch columns and L11 staged in LDS (one
+      // round of loads), then the substitution (a thread per sketch row)
+      for (int e = tid; e < l * m; e += kBT) {
+        const int t = e / l, r = e - t * l;
+        sh.su.T[r][t] = S.B[(int64_t)(K0 + t) * l + r];
+      }
+      for (int e = tid; e < m * m; e += kBT) {
+        const int t = e / m, u = e - t * m;
+        sh.su.l11[t][u] = S.Lp[(K0 + t) * kBldp + u];
+      }
+      __syncthreads();
+      if (tid < l)
+        for (int t = 1; t < m; ++t) {
+          double v = sh.su.T[tid][t];
+          for (int u = 0; u < t; ++u) v = fma(-sh.su.T[tid][u], sh.su.l11[t][u], v);
+          sh.su.T[tid][t] = v;
+        }
+    }
+    // the block's D entries and kinds for the W rows
+    if (tid < m) {
+      sh.bd[tid] = S.D[K0 + tid];
+      sh.bs[tid] = S.D[n + K0 + tid];
+      sh.bk[tid] = S.ipiv[K0 + tid];
+    }
+    __syncthreads();   // T, D
+    if (m <= kQr) {
+      // one pass per position s: its L row loaded once (one round of
+      // loads) gives its entries of the block's L columns, its W row and
+      // the update of its sketch column (rows in batches of kQc loads)
+      for (int s = K0 + 1 + tid; s < n; s += kBT) {
+        // compiler barrier: the LDS reads below are loop-invariant, and
+        // hoisted out of this (at most two-trip) loop they would hold ~150
+        // registers for the whole kernel and cut the systems per CU from
+        // four to two
+        __asm__ volatile("" ::: "memory");
+        double x[kQr + 1];
+#pragma unroll
+        for (int t = 0; t <= kQr; ++t) x[t] = S.Lp[s * kBldp + min(t, m)];
+#pragma unroll
+        for (int t = 0; t < kQr; ++t)
+          if (t < m && s > K0 + t) S.Lw[s + (int64_t)(K0 + t) * n] = (TA)x[t];
+        if (s >= K1) {
+          // W(t) = sum_u L(u) D(u, t) for the block's 1x1 / 2x2 kinds
+#pragma unroll
+          for (int t = 0; t < kQr; ++t) {
+            if (t < m) {
+              const int tm = max(t - 1, 0);
+              const int k = sh.bk[t];
+              const double own = x[t] * sh.bd[t];
+              const double first = fma(x[t], sh.bd[t], x[t + 1] * sh.bs[t]);
+              const double second = fma(x[tm], sh.bs[tm], own);
+              S.Wp[s * kBldp + t] = k == 1 ? own : (k == 2 ? first : second);
+            }
+          }
+          double* bc = S.B + (int64_t)s * l;
+          for (int r0 = 0; r0 < l; r0 += kQc) {
+            double v[kQc];
+#pragma unroll
+            for (int u = 0; u < kQc; ++u) v[u] = bc[min(r0 + u, l - 1)];
+            const int rl = min(l - 1, r0 + kQc - 1);   // T rows past l: clamped, unused
+#pragma unroll
+            for (int t = 0; t < kQr; ++t)
+              if (t < m)
+#pragma unroll
+                for (int u = 0; u < kQc; ++u)
+                  v[u] = fma(-sh.su.T[min(r0 + u, rl)][t], x[t], v[u]);
+#pragma unroll
+            for (int u = 0; u < kQc; ++u)
+              if (r0 + u < l) bc[r0 + u] = v[u];
+          }
+        }
+      }
+    } else {
+      // wider blocks: the same three steps as separate passes
+      for (int64_t e = tid; e < (int64_t)m * N; e += kBT) {
+        const int t = (int)(e / N), s = K0 + (int)(e - (int64_t)t * N);
+        if (s > K0 + t) S.Lw[s + (int64_t)(K0 + t) * n] = (TA)S.Lp[s * kBldp + t];
+      }
+      if (N2 > 0) {
+        // W rows of the trailing positions for the update
+        for (int e = tid; e < N2 * m; e += kBT) {
+          const int s = K1 + e / m, t = e % m;
+          const double* x = S.Lp + s * kBldp;
+          const int kd = S.ipiv[K0 + t];
+          double w;
+          if (kd == 1) w = x[t] * S.D[K0 + t];
+          else if (kd == 2) w = fma(x[t], S.D[K0 + t], x[t + 1] * S.D[n + K0 + t]);
+          else w = fma(x[t - 1], S.D[n + K0 + t - 1], x[t] * S.D[K0 + t]);
+          S.Wp[s * kBldp + t] = w;
+        }
+        __syncthreads();
+        for (int e = tid; e < N2 * l; e += kBT) {
+          const int j = K1 + e / l, rr = e % l;
+          double v = S.B[(int64_t)j * l + rr];
+          const double* x = S.Lp + j * kBldp;
+          for (int t = 0; t < m; ++t) v = fma(-sh.su.T[rr][t], x[t], v);
+          S.B[(int64_t)j * l + rr] = v;
+        }
+      }
     }
     __syncthreads();
     if (N2 > 0) {
-      // ---- sketch update: T = B~_1 L11^{-T} (a thread per sketch row),
-      // then B(:, K1:n) -= T L21^T
-      if (tid < l) {
-        for (int t = 0; t < m; ++t) {
-          double v = S.B[(int64_t)(K0 + t) * l + tid];
-          for (int u = 0; u < t; ++u) v = fma(-sh.T[tid][u], S.Lp[(K0 + t) * kBldp + u], v);
-          sh.T[tid][t] = v;
-        }
-      }
-      // W rows of the trailing positions for the update
-      for (int e = tid; e < N2 * m; e += kBT) {
-        const int s = K1 + e / m, t = e % m;
-        const double* x = S.Lp + s * kBldp;
-        const int kd = S.ipiv[K0 + t];
-        double w;
-        if (kd == 1) w = x[t] * S.D[K0 + t];
-        else if (kd == 2) w = fma(x[t], S.D[K0 + t], x[t + 1] * S.D[n + K0 + t]);
-        else w = fma(x[t - 1], S.D[n + K0 + t - 1], x[t] * S.D[K0 + t]);
-        S.Wp[s * kBldp + t] = w;
-      }
-      __syncthreads();
-      for (int e = tid; e < N2 * l; e += kBT) {
-        const int j = K1 + e / l, rr = e % l;
-        double v = S.B[(int64_t)j * l + rr];
-        const double* x = S.Lp + j * kBldp;
-        for (int t = 0; t < m; ++t) v = fma(-sh.T[rr][t], x[t], v);
-        S.B[(int64_t)j * l + rr] = v;
-      }
       __syncthreads();   // T and the update tiles share LDS
       // ---- trailing update W(i, j) -= sum_t L(i, t) W(j, t), K1 <= j <= i,
       // in 64 x 64 tiles through LDS, 4 x 4 outputs per thread
@@ -611,14 +688,29 @@ __global__ void __launch_bounds__(kBT) batched_kernel(KernelArgs a) {
         while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
         const int tj = tile - ti * (ti + 1) / 2;
         const int i0 = K1 + 64 * ti, j0 = K1 + 64 * tj;
+        const int ri = (tid & 15) * 4, rj = (tid >> 4) * 4;
         __syncthreads();
-        for (int e = tid; e < 64 * m; e += kBT) {
-          const int rr = e / m, t = e % m;
-          sh.u.ta[rr][t] = (i0 + rr < n) ? S.Lp[(i0 + rr) * kBldp + t] : 0.0;
-          sh.u.tb[rr][t] = (j0 + rr < n) ? S.Wp[(j0 + rr) * kBldp + t] : 0.0;
+        // the tile's L and W rows, two entries of each per thread per round
+        for (int e0 = tid; e0 < 64 * m; e0 += 2 * kBT) {
+          double va[2], vb[2];
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const int e = min(e0 + q * kBT, 64 * m - 1);
+            const int rr = e / m, t = e - rr * m;
+            va[q] = S.Lp[min(i0 + rr, n - 1) * kBldp + t];
+            vb[q] = S.Wp[min(j0 + rr, n - 1) * kBldp + t];
+          }
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const int e = e0 + q * kBT;
+            if (e < 64 * m) {
+              const int rr = e / m, t = e - rr * m;
+              sh.u.ta[rr][t] = (i0 + rr < n) ? va[q] : 0.0;
+              sh.u.tb[rr][t] = (j0 + rr < n) ? vb[q] : 0.0;
+            }
+          }
         }
         __syncthreads();
-        const int ri = (tid & 15) * 4, rj = (tid >> 4) * 4;
         double acc[4][4];
 #pragma unroll
         for (int x = 0; x < 4; ++x)
@@ -636,15 +728,21 @@ __global__ void __launch_bounds__(kBT) batched_kernel(KernelArgs a) {
 #pragma unroll
             for (int y = 0; y < 4; ++y) acc[x][y] = fma(av[x], bv[y], acc[x][y]);
         }
+        // my 16 entries of W: all loaded, then all stored (one round trip)
+        TA wv[4][4];
 #pragma unroll
         for (int x = 0; x < 4; ++x)
 #pragma unroll
           for (int y = 0; y < 4; ++y) {
             const int i = i0 + ri + x, j = j0 + rj + y;
-            if (i < n && j < n && i >= j) {
-              TA* wp = &S.W[i + (int64_t)j * n];
-              *wp = (TA)((double)*wp - acc[x][y]);
-            }
+            wv[x][y] = S.W[(i < n && j < n && i >= j) ? i + (int64_t)j * n : 0];
+          }
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) {
+            const int i = i0 + ri + x, j = j0 + rj + y;
+            if (i < n && j < n && i >= j) S.W[i + (int64_t)j * n] = (TA)((double)wv[x][y] - acc[x][y]);
           }
       }
       __syncthreads();
