@@ -319,10 +319,23 @@ __global__ void __launch_bounds__(kBT) batched_kernel(KernelArgs a) {
 
   // ---- set-up: W = sym(A) (both triangles, the upper one only for the
   // sketch), Lw = 0, perm = identity, Omega
-  for (int64_t e = tid; e < (int64_t)n * n; e += kBT) {
-    const int j = (int)(e / n), i = (int)(e - (int64_t)j * n);
-    S.W[e] = (TA)((i >= j) ? A[e] : A[j + (int64_t)i * n]);
-    S.Lw[e] = (TA)0;
+  // (eight entries per thread per round: all loaded, then all stored)
+  for (int64_t e0 = tid; e0 < (int64_t)n * n; e0 += 8 * kBT) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t e = min(e0 + (int64_t)q * kBT, (int64_t)n * n - 1);
+      const int j = (int)(e / n), i = (int)(e - (int64_t)j * n);
+      v[q] = A[(i >= j) ? e : j + (int64_t)i * n];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t e = e0 + (int64_t)q * kBT;
+      if (e < (int64_t)n * n) {
+        S.W[e] = (TA)v[q];
+        S.Lw[e] = (TA)0;
+      }
+    }
   }
   for (int i = tid; i < n; i += kBT) {
     S.perm[i] = i;
@@ -347,11 +360,17 @@ __global__ void __launch_bounds__(kBT) batched_kernel(KernelArgs a) {
       double acc[16];
 #pragma unroll
       for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+      // Omega rows clamped into range (the extra sums are never stored):
+      // no load sits behind a branch, and the loads, uniform across the
+      // wave, can all be issued at once
+      const double* om[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) om[u] = S.Om + (int64_t)min(r0 + u, l - 1) * n;
+#pragma unroll 2
       for (int i = 0; i < n; ++i) {
         const double av = (double)S.W[j + (int64_t)i * n];
 #pragma unroll
-        for (int u = 0; u < 16; ++u)
-          if (r0 + u < l) acc[u] = fma(S.Om[(int64_t)(r0 + u) * n + i], av, acc[u]);
+        for (int u = 0; u < 16; ++u) acc[u] = fma(om[u][i], av, acc[u]);
       }
 #pragma unroll
       for (int u = 0; u < 16; ++u)
@@ -771,8 +790,8 @@ __global__ void __launch_bounds__(kBT) batched_kernel(KernelArgs a) {
     double rs_max = 0.0;
     for (int i = tid; i < n; i += kBT) {
       double s = 0.0;
-      for (int j = 0; j <= i; ++j) s += fabs(A[i + (int64_t)j * n]);
-      for (int j = i + 1; j < n; ++j) s += fabs(A[j + (int64_t)i * n]);
+#pragma unroll 8
+      for (int j = 0; j < n; ++j) s += fabs(A[(j <= i) ? i + (int64_t)j * n : j + (int64_t)i * n]);
       rs_max = fmax(rs_max, s);
     }
     int dummy = 0;
@@ -780,14 +799,21 @@ __global__ void __launch_bounds__(kBT) batched_kernel(KernelArgs a) {
     const double anorm = rs_max;
     for (;;) {
       // r = b - A x, in FP64 from the input matrix
+      // (all right-hand sides share each load of A; the loads of eight
+      // consecutive j are issued together)
+      static_assert(kBatchMaxRhs <= 4, "residual accumulators");
       for (int i = tid; i < n; i += kBT) {
-        for (int c = 0; c < nrhs; ++c) {
-          const double* xc = S.x + (int64_t)c * n;
-          double s = 0.0;
-          for (int j = 0; j <= i; ++j) s = fma(A[i + (int64_t)j * n], xc[j], s);
-          for (int j = i + 1; j < n; ++j) s = fma(A[j + (int64_t)i * n], xc[j], s);
-          S.r[i + (int64_t)c * n] = Bv[i + (int64_t)c * n] - s;
+        double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+        for (int j = 0; j < n; ++j) {
+          const double av = A[(j <= i) ? i + (int64_t)j * n : j + (int64_t)i * n];
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            if (c < nrhs) s[c] = fma(av, S.x[j + (int64_t)c * n], s[c]);
         }
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          if (c < nrhs) S.r[i + (int64_t)c * n] = Bv[i + (int64_t)c * n] - s[c];
       }
       __syncthreads();
       berr = 0.0;
@@ -859,11 +885,22 @@ __device__ void blocked_solve(Sys<TA>& S, int nrhs, double* yv, Shared& sh) {
     if (tid < 64) {
       double yc[4];
       for (int c = 0; c < nrhs; ++c) yc[c] = (lane < jn) ? tmp[j0 + lane + (int64_t)c * n] : 0.0;
-      for (int t = 0; t < jn; ++t) {
-        const double lv = (lane > t && lane < jn) ? (double)S.Lw[(j0 + lane) + (int64_t)(j0 + t) * n] : 0.0;
-        for (int c = 0; c < nrhs; ++c) {
-          const double yt = bcast_lane(yc[c], t);
-          yc[c] = fma(-lv, yt, yc[c]);
+      // my row of the diagonal block, sixteen entries per round of loads
+      for (int t0 = 0; t0 < jn; t0 += 16) {
+        double lr[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          lr[u] = (double)S.Lw[(j0 + min(lane, jn - 1)) + (int64_t)(j0 + min(t0 + u, jn - 1)) * n];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int t = t0 + u;
+          if (t < jn) {
+            const double lv = (lane > t && lane < jn) ? lr[u] : 0.0;
+            for (int c = 0; c < nrhs; ++c) {
+              const double yt = bcast_lane(yc[c], t);
+              yc[c] = fma(-lv, yt, yc[c]);
+            }
+          }
         }
       }
       for (int c = 0; c < nrhs; ++c) {
@@ -874,6 +911,7 @@ __device__ void blocked_solve(Sys<TA>& S, int nrhs, double* yv, Shared& sh) {
     __syncthreads();
     for (int i = j0 + jn + tid; i < n; i += kBT) {
       double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
       for (int t = 0; t < jn; ++t) {
         const double lv = (double)S.Lw[i + (int64_t)(j0 + t) * n];
         for (int c = 0; c < nrhs; ++c) acc[c] = fma(lv, sh.s.yb[c][t], acc[c]);
@@ -908,6 +946,7 @@ __device__ void blocked_solve(Sys<TA>& S, int nrhs, double* yv, Shared& sh) {
       const int t = tid & 63, qtr = tid >> 6;
       double acc[4] = {0.0, 0.0, 0.0, 0.0};
       if (t < jn)
+#pragma unroll 8
         for (int i = j0 + jn + qtr; i < n; i += 4) {
           const double lv = (double)S.Lw[i + (int64_t)(j0 + t) * n];
           for (int c = 0; c < nrhs; ++c) acc[c] = fma(lv, tmp[i + (int64_t)c * n], acc[c]);
@@ -922,11 +961,22 @@ __device__ void blocked_solve(Sys<TA>& S, int nrhs, double* yv, Shared& sh) {
                                   ((sh.s.part[0][c][lane] + sh.s.part[1][c][lane]) +
                                    (sh.s.part[2][c][lane] + sh.s.part[3][c][lane]))
                             : 0.0;
-      for (int t = jn - 1; t >= 0; --t) {
-        const double lv = (lane < t) ? (double)S.Lw[(j0 + t) + (int64_t)(j0 + lane) * n] : 0.0;
-        for (int c = 0; c < nrhs; ++c) {
-          const double yt = bcast_lane(yc[c], t);
-          yc[c] = fma(-lv, yt, yc[c]);
+      // my column of the diagonal block, sixteen entries per round of loads
+      for (int t1 = jn - 1; t1 >= 0; t1 -= 16) {
+        double lc[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          lc[u] = (double)S.Lw[(j0 + max(t1 - u, 0)) + (int64_t)(j0 + min(lane, jn - 1)) * n];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int t = t1 - u;
+          if (t >= 0) {
+            const double lv = (lane < t) ? lc[u] : 0.0;
+            for (int c = 0; c < nrhs; ++c) {
+              const double yt = bcast_lane(yc[c], t);
+              yc[c] = fma(-lv, yt, yc[c]);
+            }
+          }
         }
       }
       for (int c = 0; c < nrhs; ++c)

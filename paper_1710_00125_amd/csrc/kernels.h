@@ -138,6 +138,7 @@ size_t solve_work_doubles(int64_t n, int64_t nrhs);
 constexpr int kBatchMaxN = 512;
 constexpr int kBatchMaxL = 64;
 constexpr int kBatchMaxB = 32;
+constexpr int kBatchMaxRhs = 4;
 struct BatchSys {
   int n, b, l, pad;
   uint64_t seed;

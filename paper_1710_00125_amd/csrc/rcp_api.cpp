@@ -842,7 +842,7 @@ int rcp_batch_create(int64_t count, const int32_t* n, int32_t p, uint64_t seed0,
   if (count > 0 && !n) return -2;
   if (p < 0 || p + kBatchMaxB > kBatchMaxL) return -3;
   if (precision != 0 && precision != RCP_PREC_FP32) return -5;
-  if (nrhs < 1 || nrhs > 4) return -6;
+  if (nrhs < 1 || nrhs > kBatchMaxRhs) return -6;
   if (count > 0 && (!Apool || !Bpool || !Xpool)) return -7;
   if (!out) return -15;
   for (int64_t i = 0; i < count; ++i)
