@@ -30,6 +30,7 @@ constexpr int kBMaxB = kBatchMaxB;  // largest block size
 constexpr int kBldp = kBMaxB + 2;   // row stride of the block L rows (b + 1 used)
 constexpr int kQc = 8;              // QRCP: sketch rows per batch of loads
 constexpr int kQr = 16;             // QRCP: longest column segment held in registers
+static_assert(kBMaxL <= kBT, "a thread per sketch row");
 
 struct KernelArgs {
   const BatchSys* sys;
@@ -422,15 +423,21 @@ __global__ void __launch_bounds__(kBT) batched_kernel(KernelArgs a) {
       wg_argmax(best, bpos, sh);
       if (!(best > 0.0)) break;
       if (tid == 0 && bpos != pj) swp(sh.qn[pj], sh.qn[bpos]);
-      swap_positions(S, pj, bpos, K0, 0);
-      // Householder vector of x = R(j:l, pj): v = x + sign(x_j) ||x|| e_j,
-      // beta = 2 / v.v = 1 / (||x|| (||x|| + |x_j|))
+      // Householder vector of x = R(j:l, pj) after the interchange, i.e. of
+      // column bpos before it: v = x + sign(x_j) ||x|| e_j, beta = 2 / v.v
+      // = 1 / (||x|| (||x|| + |x_j|)).  Thread r reads row r of the pivot
+      // column in the same round as its interchange loads (it alone moves
+      // that row).
       const double nx = sqrt(best);
-      const double* xr = S.R + (int64_t)pj * l;
-      const double xj = xr[j];
+      if (tid >= j && tid < l) {
+        const double xr = S.R[(int64_t)bpos * l + tid];
+        sh.v[tid] = (tid == j) ? xr + copysign(nx, xr) : xr;
+        if (tid == j) sh.sc[0] = xr;
+      }
+      swap_positions(S, pj, bpos, K0, 0);   // ends with a barrier when it swaps
+      if (bpos == pj) __syncthreads();
+      const double xj = sh.sc[0];
       const double beta = 1.0 / (nx * (nx + fabs(xj)));
-      for (int r = j + tid; r < l; r += kBT) sh.v[r] = (r == j) ? xj + copysign(nx, xj) : xr[r];
-      __syncthreads();
       if (l - j <= kQr) {
         // my column segments one at a time in registers: one round of
         // loads per column
