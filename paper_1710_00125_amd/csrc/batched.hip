@@ -261,13 +261,22 @@ __device__ void w_row(const Sys<TA>& S, int c, int kk, double* dst) {
 }
 
 // current column of position c on positions [k, n): A(s, c) - L(s, :) W(c, :)
+// (the L row in batches of eight loads from clamped addresses, issued with
+// the load of A(s, c); the sum still in order t = 0, 1, ...)
 template <typename TA>
 __device__ void cur_column(const Sys<TA>& S, int c, int k, int kk, const double* wr, double* out) {
   const int n = S.n;
   for (int s = k + threadIdx.x; s < n; s += kBT) {
     double a = symw(S.W, n, s, c);
     const double* x = S.Lp + s * kBldp;
-    for (int t = 0; t < kk; ++t) a = fma(-x[t], wr[t], a);
+    for (int t0 = 0; t0 < kk; t0 += 8) {
+      double xv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) xv[u] = x[min(t0 + u, kk - 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (t0 + u < kk) a = fma(-xv[u], wr[t0 + u], a);
+    }
     out[s - k] = a;
   }
 }
