@@ -229,6 +229,12 @@ int rcp_batch_destroy(rcp_batch* plan);
  * precision 0 or RCP_PREC_FP32 (HOST int32[4]).  Returns 0, -1 or -2. */
 int rcp_batch_get_table(int32_t precision, int32_t* b_by_class);
 
+/* Set the block size per size class (HOST int32[4], each 1..32) for
+ * precision 0 or RCP_PREC_FP32, used by plans created afterwards without
+ * autotuning (autotuning overwrites it).  Returns 0, -1 (precision) or -2
+ * (NULL or an entry out of range). */
+int rcp_batch_set_table(int32_t precision, const int32_t* b_by_class);
+
 #ifdef __cplusplus
 }
 #endif

@@ -81,6 +81,7 @@ _SIGS = {
     "rcp_batch_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_BatchInfo)]),
     "rcp_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "rcp_batch_get_table": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "rcp_batch_set_table": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
 }
 
 
@@ -367,3 +368,10 @@ def rcp_batch_get_table(precision=0):
     arr = (ctypes.c_int32 * 4)()
     _check("rcp_batch_get_table", load().rcp_batch_get_table(int(precision), arr))
     return list(arr)
+
+
+def rcp_batch_set_table(b_by_class, precision=0):
+    """Block size per size class (n <= 64, 128, 256, 512) for plans created
+    afterwards without autotuning."""
+    arr = (ctypes.c_int32 * 4)(*[int(b) for b in b_by_class])
+    _check("rcp_batch_set_table", load().rcp_batch_set_table(int(precision), arr))

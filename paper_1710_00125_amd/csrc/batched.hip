@@ -59,9 +59,10 @@ struct Shared {
   double red_v[4];
   int red_p[4];
   double sc[8];
-  double bd[kBMaxB];         // the block's D: diagonal
-  double bs[kBMaxB];         //                sub-diagonal of its 2x2 blocks
-  int bk[kBMaxB];            //                kinds (ipiv)
+  // (a block eliminates up to b + 1 columns: a 2x2 pivot may close it)
+  double bd[kBMaxB + 1];     // the block's D: diagonal
+  double bs[kBMaxB + 1];     //                sub-diagonal of its 2x2 blocks
+  int bk[kBMaxB + 1];        //                kinds (ipiv)
   int info;                  // first exactly zero 1x1 pivot (1-based), INT_MAX if none
   int n2x2;
   union {                    // phase-specific buffers
@@ -72,7 +73,7 @@ struct Shared {
     } p;
     struct {
       double T[kBMaxL][kBldp];           // sketch update factor B~_1 L11^{-T}
-      double l11[kBMaxB][kBMaxB + 1];    // the block's L11 (rows t, columns u < t)
+      double l11[kBMaxB + 1][kBMaxB + 1];   // the block's L11 (rows t, columns u < t)
     } su;
     struct {
       double ta[64][kBMaxB + 1];   // trailing-update tiles: L21 rows

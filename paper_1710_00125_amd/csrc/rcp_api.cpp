@@ -834,6 +834,15 @@ int rcp_batch_get_table(int32_t precision, int32_t* b_by_class) {
   return 0;
 }
 
+int rcp_batch_set_table(int32_t precision, const int32_t* b_by_class) {
+  if (precision != 0 && precision != RCP_PREC_FP32) return -1;
+  if (!b_by_class) return -2;
+  for (int c = 0; c < 4; ++c)
+    if (b_by_class[c] < 1 || b_by_class[c] > kBatchMaxB) return -2;
+  for (int c = 0; c < 4; ++c) g_batch_b[precision ? 1 : 0][c] = b_by_class[c];
+  return 0;
+}
+
 int rcp_batch_create(int64_t count, const int32_t* n, int32_t p, uint64_t seed0,
                      int32_t precision, int32_t nrhs, const double* Apool, const double* Bpool,
                      double* Xpool, int64_t* perm, void* L, double* D, int8_t* ipiv,

@@ -78,6 +78,26 @@ def _dmat(D, ipiv):
 def test_batched_fp64_matches_oracle(rcp, autotune):
     nrhs = 4
     _say(f"batched fp64 autotune={autotune} count={len(NS)}")
+    _fp64_case(rcp, nrhs, autotune)
+
+
+# wider blocks than the autotuner picks on this mix: 24 and 32 columns take
+# the kernel's separate-pass path after each block (blocks of more than
+# sixteen eliminated columns)
+@pytest.mark.parametrize("b", [24, 32])
+def test_batched_fp64_wide_blocks(rcp, b):
+    nrhs = 2
+    saved = rcp.rcp_batch_get_table(0)
+    _say(f"batched fp64 fixed b={b} count={len(NS)}")
+    try:
+        rcp.rcp_batch_set_table([b] * 4, 0)
+        assert rcp.rcp_batch_get_table(0) == [b] * 4
+        _fp64_case(rcp, nrhs, False)
+    finally:
+        rcp.rcp_batch_set_table(saved, 0)
+
+
+def _fp64_case(rcp, nrhs, autotune):
     systems = _systems(NS, nrhs)
     ns, Ap, Bp = rcp.pack_batch(systems, nrhs)
     batch = rcp.rcp_batch_create(ns, Ap, Bp, P, SEED0, 0, nrhs, factors=True, autotune=autotune)
