@@ -163,6 +163,31 @@ def test_refine_reports_stagnation_at_cond_1e10(rcp, precision):
     assert r1 <= r0 * 1.01
 
 
+# right-hand-side counts that exercise every residual kernel width (one,
+# two, four at a time) and the refinement's groups of four
+@pytest.mark.parametrize("nrhs", [2, 3, 6])
+def test_refine_many_rhs(rcp, nrhs):
+    import torch
+    n, b, p, seed = 300, 32, 8, 12
+    _say(f"refine fp32 n={n} nrhs={nrhs}")
+    A = gen.gaussian_sym(n, seed)
+    B = gen.rhs(n, nrhs, seed)
+    dev = torch.device("cuda:0")
+    Ad = torch.from_numpy(A).to(dev)
+    f = rcp.rcp_factor_mp(Ad, b, p, seed, 1)
+    X, info = rcp.rcp_solve_ir(Ad, f, torch.from_numpy(B).to(dev))
+    x = X.cpu().numpy()
+    be = tb.backward_error(A, x, B)
+    _say(f"  backward errors {np.array2string(be, precision=2)}, {info}")
+    assert info["converged"]
+    assert np.all(be <= 1e-13)
+    assert abs(info["berr"] - np.max(be)) <= 1e-3 * np.max(be) + 10 * n * np.finfo(float).eps / 2
+    ref = orcp.factor(A, b, p, seed=seed)
+    xr = orcp.solve(ref, B)
+    kappa = np.linalg.cond(A, np.inf)
+    assert np.max(np.abs(x - xr)) <= kappa * 1e-12 * max(1.0, np.max(np.abs(xr)))
+
+
 def test_refine_already_converged(rcp):
     """A zero right-hand side: x0 = 0 is exact, no GMRES cycle runs."""
     import torch
