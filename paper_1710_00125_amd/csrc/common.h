@@ -34,7 +34,9 @@ __device__ __forceinline__ T ld_agent(const T* p) {
 // carrying the step, so that polling the records is the barrier and the
 // read at once.  Value words: a double with its two lowest mantissa bits
 // replaced by step & 3 (a change below 2^-50 relative, far inside the
-// rounding of the value itself); the index word: (step + 1) in the top 16
+// rounding of the value itself), and cleared again when the value is read
+// (so the value read is the same in every workgroup, and an exact zero --
+// SBKP case (0), an exhausted selection -- stays zero); the index word: (step + 1) in the top 16
 // bits, then 24 bits of position and 24 bits of source (all-ones: none).
 // A record is current when every word carries the step; zeroed memory never
 // is (its index word fails).  The writer stores the index word last (or in
@@ -61,7 +63,7 @@ __device__ __forceinline__ bool rec_index_current(unsigned long long w1, int ste
   return (w1 >> 48) == (unsigned long long)((step + 1) & 0xFFFF);
 }
 __device__ __forceinline__ double rec_untag(unsigned long long w0) {
-  return __longlong_as_double((long long)w0);
+  return __longlong_as_double((long long)(w0 & ~3ull));
 }
 __device__ __forceinline__ int rec_pos(unsigned long long w1) {
   const int p = (int)((w1 >> 24) & 0xFFFFFF);

@@ -193,3 +193,39 @@ def test_batched_graph_replays_identical(rcp):
         x = outs[0][n1[i] * nrhs:n1[i + 1] * nrhs].reshape(nrhs, n).T
         assert np.max(tb.backward_error(A, x, B)) <= 1e-13
     batch.close()
+
+
+def test_batched_singular_systems(rcp):
+    """Exactly singular systems among regular ones: each reports the oracle's
+    first zero pivot (info), with the oracle's permutation, and leaves its
+    solution unwritten; the regular systems are unaffected."""
+    import torch
+    nrhs = 1
+    specs = [(12, 0), (40, 7), (100, 20), (64, 64), (33, 33)]   # (n, rank of the corner)
+    systems = []
+    for i, (n, r) in enumerate(specs):
+        A = np.zeros((n, n))
+        if r:
+            A[:r, :r] = gen.gaussian_sym(r, SEED0 + i)
+        systems.append((A, gen.rhs(n, nrhs, SEED0 + i)))
+    _say(f"batched singular systems {specs}")
+    ns, Ap, Bp = rcp.pack_batch(systems, nrhs)
+    batch = rcp.rcp_batch_create(ns, Ap, Bp, P, SEED0, 0, nrhs, factors=True, autotune=False)
+    batch.Xpool.fill_(7.0)
+    batch.run()
+    info = batch.info()
+    X = batch.Xpool.cpu().numpy()
+    perm = batch.perm.cpu().numpy()
+    n1, _ = _offsets(ns)
+    for i, (A, B) in enumerate(systems):
+        n, r = specs[i]
+        ref = orcp.factor(A, info[i]["b"], P, seed=SEED0 + i)
+        x = X[n1[i] * nrhs:n1[i + 1] * nrhs]
+        _say(f"  system {i}: n={n} rank {r} info={info[i]['info']} oracle {ref.info}")
+        assert info[i]["info"] == ref.info
+        assert np.array_equal(perm[n1[i]:n1[i + 1]], ref.perm)
+        if ref.info > 0:
+            assert np.all(x == 7.0)       # unwritten
+        else:
+            assert np.max(tb.backward_error(A, x.reshape(nrhs, n).T, B)) <= 1e-13
+    batch.close()
