@@ -185,3 +185,25 @@ def test_factor_singular_reports_zero_pivot(rcp, name, n, r, b, p):
     assert f.info == ref.info
     with pytest.raises(rcp.RCPError):
         rcp.rcp_solve(f, torch.ones(n, dtype=torch.float64, device=_dev()))
+
+
+# non-finite input: a NaN or an Inf in the lower triangle reaches the sketch
+# and the factorization stops with RCP_ENONFINITE; the same entries in the
+# strict upper triangle are never read
+@pytest.mark.parametrize("bad", [np.nan, np.inf])
+def test_nonfinite_input(rcp, bad):
+    import torch
+    from paper_1710_00125_amd._binding import RCP_ENONFINITE
+    n, b, p, seed = 150, 16, 8, 41
+    _say(f"non-finite input {bad}")
+    A = gen.gaussian_sym(n, seed)
+    lower = A.copy()
+    lower[97, 12] = bad
+    with pytest.raises(rcp.RCPError) as e:
+        rcp.rcp_factor(torch.from_numpy(lower).to(_dev()), b, p, seed)
+    assert e.value.code == RCP_ENONFINITE
+    upper = A.copy()
+    upper[12, 97] = bad
+    f = rcp.rcp_factor(torch.from_numpy(upper).to(_dev()), b, p, seed)
+    ref = orcp.factor(A, b, p, seed=seed)
+    assert np.array_equal(f.perm.cpu().numpy(), ref.perm)
