@@ -46,32 +46,49 @@ __global__ void __launch_bounds__(256) sketch_partial_kernel(int64_t n, const TA
 #pragma unroll
   for (int f = 0; f < kTC / 16; ++f) acc[f] = Acc{0, 0, 0, 0};
 
-  for (int64_t i0 = kbeg; i0 < kend; i0 += kTK) {
-    // ---- stage A tile (rows j0.., cols i0..) of the symmetric matrix
-    const bool all_lower = (i0 + kTK - 1) <= j0;
+  // A tile (rows j0.., columns i0..) of the symmetric matrix of one
+  // contraction chunk: each thread's share is loaded into registers from
+  // clamped addresses (straight-line code), the next chunk's while the
+  // matrix cores work on the current one, and stored to LDS with the
+  // entries outside the matrix zeroed.  Omega^T rows i0.., columns c0..
+  // (read by every workgroup: L2 hits) are staged after the barrier.
+  constexpr int kQa = kTJ * kTK / 256;
+  TA ra[kQa];
+  auto load_chunk = [&](int64_t i0) {
     const bool all_upper = i0 > (j0 + kTJ - 1);
-    for (int e = tid; e < kTJ * kTK; e += 256) {
-      int jj, ii;
-      if (all_upper) {
-        ii = e % kTK;
-        jj = e / kTK;
-      } else {
-        jj = e % kTJ;
-        ii = e / kTJ;
-      }
-      const int64_t j = j0 + jj, i = i0 + ii;
-      TA v = 0;
-      if (j < n && i < kend) v = (j >= i) ? A[j + i * ld] : A[i + j * ld];
-      As[jj][ii] = v;
+#pragma unroll
+    for (int q = 0; q < kQa; ++q) {
+      const int e = tid + 256 * q;
+      const int jj = all_upper ? e / kTK : e % kTJ;
+      const int ii = all_upper ? e % kTK : e / kTJ;
+      const int64_t j = min(j0 + jj, n - 1), i = min(i0 + ii, kend - 1);
+      ra[q] = (j >= i) ? A[j + i * ld] : A[i + j * ld];
     }
-    (void)all_lower;
-    // ---- stage Omega^T rows i0.., columns c0..
+  };
+  auto store_chunk = [&](int64_t i0) {
+    const bool all_upper = i0 > (j0 + kTJ - 1);
+#pragma unroll
+    for (int q = 0; q < kQa; ++q) {
+      const int e = tid + 256 * q;
+      const int jj = all_upper ? e / kTK : e % kTJ;
+      const int ii = all_upper ? e % kTK : e / kTJ;
+      As[jj][ii] = (j0 + jj < n && i0 + ii < kend) ? ra[q] : (TA)0;
+    }
     for (int e = tid; e < kTK * ncols; e += 256) {
       const int ii = e / ncols, cc = e - ii * ncols;
       const int64_t i = i0 + ii;
       Bs[ii][cc] = (i < kend) ? (TA)OmT[i * lpad + c0 + cc] : (TA)0;
     }
-    __syncthreads();
+  };
+
+  if (kbeg < kend) {
+    load_chunk(kbeg);
+    store_chunk(kbeg);
+  }
+  __syncthreads();
+  for (int64_t i0 = kbeg; i0 < kend; i0 += kTK) {
+    const bool more = i0 + kTK < kend;
+    if (more) load_chunk(i0 + kTK);
 #pragma unroll
     for (int kk = 0; kk < kTK / 4; ++kk) {
       const TA a = As[16 * w + frag_row(lane)][4 * kk + frag_k(lane)];
@@ -83,6 +100,8 @@ __global__ void __launch_bounds__(256) sketch_partial_kernel(int64_t n, const TA
         }
       }
     }
+    __syncthreads();
+    if (more) store_chunk(i0 + kTK);
     __syncthreads();
   }
   double* Pz = P + (int64_t)blockIdx.y * n * lpad;
