@@ -12,8 +12,10 @@
 // Unlike the single-system path, interchanges are applied physically: the
 // workgroup owns all of a system's data, and a swap of two positions costs
 // O(n) element moves inside the workgroup.  All arrays of a system live in
-// its slice of a workspace pool (L2 / MALL resident at these sizes); small
-// per-step vectors live in LDS.
+// its slice of a workspace pool; small per-step vectors live in LDS.  With
+// four systems per CU the pool does not stay in L2, so every dependent
+// access is a trip beyond it: each phase issues its loads in batches (all
+// of a thread's loads, then its stores) rather than one per loop step.
 #include <climits>
 
 #include "common.h"
