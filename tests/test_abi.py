@@ -88,3 +88,40 @@ def test_mixed_precision_argument_errors_without_gpu():
     a = list(args)
     a[0] = 0
     assert ir(*a) == 0
+
+
+def test_batch_table_set_and_get_without_gpu():
+    # the block-size table is host state: set, read back, reject bad entries
+    import paper_1710_00125_amd as pkg
+    if not os.path.exists(pkg.lib_path()):
+        pytest.skip("librcp.so not built")
+    lib = pkg.load()
+    saved = pkg.rcp_batch_get_table(0)
+    try:
+        pkg.rcp_batch_set_table([8, 16, 24, 32], 0)
+        assert pkg.rcp_batch_get_table(0) == [8, 16, 24, 32]
+        bad = (ctypes.c_int32 * 4)(8, 0, 16, 16)
+        assert lib.rcp_batch_set_table(0, bad) == -2
+        too_big = (ctypes.c_int32 * 4)(8, 16, 16, 33)
+        assert lib.rcp_batch_set_table(0, too_big) == -2
+        assert lib.rcp_batch_set_table(7, bad) == -1
+        assert lib.rcp_batch_set_table(0, ctypes.POINTER(ctypes.c_int32)()) == -2
+        assert pkg.rcp_batch_get_table(0) == [8, 16, 24, 32]   # unchanged by rejected calls
+    finally:
+        pkg.rcp_batch_set_table(saved, 0)
+
+
+def test_column_major_view_is_passed_without_copy():
+    # the binding hands the library a transposed view's own memory and
+    # copies anything else (host logic only; CPU tensors)
+    import torch
+    from paper_1710_00125_amd._binding import _colmajor
+    X = torch.arange(12.0, dtype=torch.float64).reshape(3, 4)
+    view = X.t()                           # 4 x 3, its transpose is X
+    cm = _colmajor(view)
+    assert cm.data_ptr() == X.data_ptr()   # no copy
+    assert torch.equal(cm.t(), view)
+    row_major = torch.arange(9.0, dtype=torch.float64).reshape(3, 3)
+    cm2 = _colmajor(row_major)
+    assert cm2.data_ptr() != row_major.data_ptr() and cm2.is_contiguous()
+    assert torch.equal(cm2.t(), row_major)    # memory[i + j n] = A[i, j]
