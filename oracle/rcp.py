@@ -63,6 +63,7 @@ class Factorization:
         self.rho_elem = None           # element growth (eager schedule only)
         self.block_starts = []
         self.sketch_at_block_start = []   # (K0, perm copy, B(:, K0:) copy) if recorded
+        self.sketch_scale = 0.0        # largest column norm of the initial sketch
 
     def dmatrix(self):
         """D as an n x n block-diagonal matrix."""
@@ -107,6 +108,9 @@ def factor(A, b, p, seed=0, omega=None, schedule="delayed", record_sketch=False,
         Om = np.asarray(omega, dtype=np.float64)
     l = Om.shape[0]
     B = Om @ S                       # the sketch B = Omega A
+    # largest column norm of the first sketch: the scale of the absolute
+    # errors of every later sketch value (used by decision_margins)
+    f.sketch_scale = float(np.sqrt(np.max(np.einsum("ij,ij->j", B, B))))
     L = np.zeros((n, n))             # strictly lower part of L, by position
     W = np.zeros((n, n))             # W = L D for the current block's columns
     perm = f.perm
@@ -308,3 +312,65 @@ def min_margin(f, scale=None):
                 ms.append(abs(abs(e["arr"]) - ALPHA * lam) / lam)
         best = min(best, (min(ms), idx))
     return best
+
+
+def decision_margins(f, scale):
+    """Margin of every logged decision, relative and absolute (near-tie data).
+
+    A decision compares computed values; a second FP64 implementation that
+    sums in another order gets each of them with an absolute error of order
+    n u times the problem's scale, so a decision is fragile when its gap is
+    small against that scale -- however large it is against the compared
+    values themselves, which at the end of a factorization are far below the
+    scale.  For every decision with at least one comparison this returns
+    (kind, position, rel, abs):
+
+      QRCP pick (kind 0, position K0 + j): the gap between the largest and
+        the second largest residual norm, sqrt(best) - sqrt(second);
+        rel = gap / sqrt(best), abs = gap / f.sketch_scale;
+      SBKP step (kind 1, position k): the gaps lambda - lambda_2 (choice of
+        r), | |a_kk| - alpha lambda | and, when it was evaluated,
+        | |a_rr| - alpha lambda | (Figure 2's threshold tests), and lambda
+        itself (the test lambda = 0); rel divides the smallest by lambda
+        (lambda = 0 gives rel = 0), abs divides it by ``scale`` (max |A|).
+
+    Decisions without a comparison (a lone candidate) are left out.  Returns
+    four NumPy arrays.
+    """
+    kinds, pos, rel, ab = [], [], [], []
+    sb = f.sketch_scale if f.sketch_scale > 0 else 1.0
+    sa = scale if scale > 0 else 1.0
+    for e in f.log:
+        if e["kind"] == "qrcp":
+            if e["best"] <= 0 or e["second"] <= 0:
+                continue
+            gap = np.sqrt(e["best"]) - np.sqrt(e["second"])
+            kinds.append(0)
+            pos.append(e["K0"] + e["j"])
+            rel.append(gap / np.sqrt(e["best"]))
+            ab.append(gap / sb)
+            continue
+        if e["r"] is None:
+            continue
+        lam = e["lam"]
+        gaps = [lam, lam - e["lam2"], abs(abs(e["akk"]) - ALPHA * lam)]
+        if e["arr"] is not None:
+            gaps.append(abs(abs(e["arr"]) - ALPHA * lam))
+        g = min(gaps)
+        kinds.append(1)
+        pos.append(e["k"])
+        rel.append(g / lam if lam > 0 else 0.0)
+        ab.append(g / sa)
+    return (np.array(kinds, dtype=np.int8), np.array(pos, dtype=np.int64),
+            np.array(rel, dtype=np.float64), np.array(ab, dtype=np.float64))
+
+
+def near_tie_prefix(f, scale, tau=1e-9):
+    """Length of the pivot sequence that no near-tie can change: the smallest
+    position decided by a decision whose absolute margin (decision_margins)
+    is <= tau, or n if there is none.  Positions before it are decided only
+    by decisions with margins above tau, and the interchanges of a later
+    decision never move an earlier position."""
+    _, pos, _, ab = decision_margins(f, scale)
+    bad = pos[ab <= tau]
+    return int(bad.min()) if bad.size else f.n

@@ -301,3 +301,88 @@ def test_min_margin_reports_ties():
     A = np.array([[0.1, 1.0, -1.0], [1.0, 0.2, 0.0], [-1.0, 0.0, 0.3]])
     f = rcp.factor(A, 3, 2, omega=np.eye(3))
     assert rcp.min_margin(f)[0] == 0.0
+
+
+# ---- decision margins (near-tie detector) on hand-built cases where every
+# compared quantity is known in closed form (Omega = I, so the sketch is A)
+
+ALPHA_REF = 0.70710678118654752440   # sqrt(2)/2
+
+
+def test_margins_threshold_test_and_qrcp_gap():
+    # [[0.7, 1], [1, 0.5]]: QRCP compares column norms sqrt(1.49) and
+    # sqrt(1.25) and takes column 0; SBKP then has a_kk = 0.7, lambda = 1,
+    # r = 1, |0.7| < alpha so a_rr = 0.5 is tested too (also < alpha: a 2x2
+    # pivot).  The smallest gap is | |a_kk| - alpha lambda | = alpha - 0.7.
+    A = np.array([[0.7, 1.0], [1.0, 0.5]])
+    f = rcp.factor(A, 1, 1, omega=np.eye(2))
+    assert list(f.ipiv) == [2, 0]
+    kind, pos, rel, ab = rcp.decision_margins(f, scale=1.0)
+    assert list(kind) == [0, 1] and list(pos) == [0, 0]
+    q_gap = np.sqrt(1.49) - np.sqrt(1.25)
+    assert rel[0] == pytest.approx(q_gap / np.sqrt(1.49), rel=1e-12)
+    assert ab[0] == pytest.approx(q_gap / np.sqrt(1.49), rel=1e-12)   # sketch scale = sqrt(1.49)
+    assert rel[1] == pytest.approx(ALPHA_REF - 0.7, rel=1e-12)
+    assert ab[1] == pytest.approx(ALPHA_REF - 0.7, rel=1e-12)
+    # the relative detector agrees: (best - second) / best on squared norms
+    m, at = rcp.min_margin(f, scale=1.0)
+    assert m == pytest.approx(ALPHA_REF - 0.7, rel=1e-12) and f.log[at]["kind"] == "sbkp"
+    assert rcp.near_tie_prefix(f, 1.0, tau=1e-3) == 2
+    assert rcp.near_tie_prefix(f, 1.0, tau=1e-2) == 0
+
+
+def test_margins_diagonal_test_of_the_candidate_row():
+    # [[0.2, 1], [1, 0.7]]: QRCP takes column 1 (norm sqrt(1.49) against
+    # sqrt(1.04)), so position 0 holds the 0.7 row: a_kk = 0.7 fails the
+    # test, a_rr = 0.2 is tested (gap alpha - 0.2) and fails; the smallest
+    # gap is still the a_kk one.  Scaled by max |A| = 1 and by lambda = 1.
+    A = np.array([[0.2, 1.0], [1.0, 0.7]])
+    f = rcp.factor(A, 1, 1, omega=np.eye(2))
+    assert list(f.perm) == [1, 0]
+    kind, pos, rel, ab = rcp.decision_margins(f, scale=2.0)
+    e = [x for x in f.log if x["kind"] == "sbkp"][0]
+    assert e["akk"] == 0.7 and e["arr"] == 0.2 and e["lam"] == 1.0
+    assert rel[1] == pytest.approx(ALPHA_REF - 0.7, rel=1e-12)
+    assert ab[1] == pytest.approx((ALPHA_REF - 0.7) / 2.0, rel=1e-12)
+
+
+def test_margins_choice_of_r():
+    # [[10, 3, 2.9], [3, 1, 0], [2.9, 0, 1]]: a_kk = 10 passes the test
+    # (case 1); lambda = 3 at r = 1 against lambda_2 = 2.9: gap 0.1, the
+    # smallest of {lambda, lambda - lambda_2, |10| - alpha 3}
+    A = np.array([[10.0, 3.0, 2.9], [3.0, 1.0, 0.0], [2.9, 0.0, 1.0]])
+    f = rcp.factor(A, 1, 2, omega=np.eye(3))
+    kind, pos, rel, ab = rcp.decision_margins(f, scale=10.0)
+    first_sbkp = int(np.nonzero(kind == 1)[0][0])
+    assert pos[first_sbkp] == 0
+    assert rel[first_sbkp] == pytest.approx(0.1 / 3.0, rel=1e-12)
+    assert ab[first_sbkp] == pytest.approx(0.1 / 10.0, rel=1e-12)
+    e = [x for x in f.log if x["kind"] == "sbkp"][0]
+    assert e["case"] == 1 and e["lam2"] == 2.9
+
+
+def test_margins_nearly_equal_columns():
+    # diag(3, 2.9999, 1): QRCP's gap between the two largest column norms is
+    # 1e-4 (relative 1e-4 / 3), and every SBKP step has lambda = 0 (a zero
+    # off-diagonal: rel 0 and abs 0, a near-tie of the lambda = 0 test)
+    A = np.diag([3.0, 2.9999, 1.0])
+    f = rcp.factor(A, 3, 0, omega=np.eye(3))
+    kind, pos, rel, ab = rcp.decision_margins(f, scale=3.0)
+    assert kind[0] == 0 and pos[0] == 0
+    assert rel[0] == pytest.approx(1e-4 / 3.0, rel=1e-9)
+    assert ab[0] == pytest.approx(1e-4 / 3.0, rel=1e-9)
+    sb = kind == 1
+    assert np.all(rel[sb] == 0.0) and np.all(ab[sb] == 0.0)
+    assert rcp.near_tie_prefix(f, 3.0) == 0
+
+
+def test_near_tie_prefix_without_ties_is_n():
+    A = gen.gaussian_sym(60, 12)
+    f = rcp.factor(A, 8, 4, seed=12)
+    kind, pos, rel, ab = rcp.decision_margins(f, scale=np.max(np.abs(A)))
+    assert ab.min() > 1e-9
+    assert rcp.near_tie_prefix(f, np.max(np.abs(A))) == 60
+    # both margins of an SBKP step measure the same gap: abs * max|A| = rel * lambda
+    lams = np.array([e["lam"] for e in f.log if e["kind"] == "sbkp" and e["r"] is not None])
+    sb = kind == 1
+    assert np.allclose(ab[sb] * np.max(np.abs(A)), rel[sb] * lams, rtol=1e-14, atol=0)
