@@ -2,10 +2,12 @@
 
 Each system is checked against the CPU oracle run with the block size the
 plan recorded for it and the same Omega seed:
-  * FP64 form: permutation and block pattern bit-exact where the oracle's
-    decision log has no near-tie (relative margin > 1e-9), L and D within
-    1e3 n u max(1, |oracle|), the solution within 1e-9 max(1, |x_oracle|) and
-    backward error <= 1e-13;
+  * FP64 form: permutation and block pattern bit-exact on every position
+    that no near-tie decides (oracle.rcp.near_tie_prefix: no decision with a
+    gap <= 1e-9 max|A| before it), L and D within 1e3 n u max(1, |oracle|)
+    there, the solution within 1e-9 max(1, |x_oracle|) and backward error
+    <= 1e-13; the systems with a near-tie are counted and reported (the
+    mixes here have none);
   * FP32 form (FP64 refinement): backward error <= 1e-13 and forward error
     against the oracle's solution <= kappa_inf 1e-12;
   * the captured graph replays to identical results with eager work on the
@@ -111,6 +113,7 @@ def _fp64_case(rcp, nrhs, autotune):
     Dp = batch.D.cpu().numpy()
     ip = batch.ipiv.cpu().numpy()
     n1, n2 = _offsets(ns)
+    partial = []   # systems whose pivots are compared only up to a near-tie
     for i, (A, B) in enumerate(systems):
         n = A.shape[0]
         cls = 0 if n <= 64 else 1 if n <= 128 else 2 if n <= 256 else 3
@@ -118,7 +121,7 @@ def _fp64_case(rcp, nrhs, autotune):
         assert info[i]["info"] == 0
         b = info[i]["b"]
         ref = orcp.factor(A, b, P, seed=SEED0 + i)
-        margin, _ = orcp.min_margin(ref, scale=np.max(np.abs(A)))
+        pre = orcp.near_tie_prefix(ref, np.max(np.abs(A)))
         pi = perm[n1[i]:n1[i + 1]]
         ii = ip[n1[i]:n1[i + 1]]
         L = Lp[n2[i]:n2[i + 1]].reshape(n, n).T
@@ -126,18 +129,29 @@ def _fp64_case(rcp, nrhs, autotune):
         x = X[n1[i] * nrhs:n1[i + 1] * nrhs].reshape(nrhs, n).T
         xr = orcp.solve(ref, B)
         be = np.max(tb.backward_error(A, x, B))
-        _say(f"  system {i}: n={n} b={b} margin={margin:.1e} berr={be:.2e} "
+        _say(f"  system {i}: n={n} b={b} near-tie prefix={pre} berr={be:.2e} "
              f"reported={info[i]['berr']:.2e} n2x2={info[i]['n2x2']}")
         assert be <= 1e-13
         assert abs(info[i]["berr"] - be) <= 1e-3 * be + 10 * n * U
         assert tb.reconstruction_error(A, pi, L, _dmat(D, ii)) <= 50 * n * U
-        if margin > 1e-9:
-            assert np.array_equal(pi, ref.perm)
-            assert np.array_equal(ii, ref.ipiv)
-            tol = 1e3 * n * U
+        # pivots bit-exact on every position no near-tie decides; L and D
+        # where they depend only on those positions
+        assert np.array_equal(pi[:pre], ref.perm[:pre])
+        assert np.array_equal(ii[:pre], ref.ipiv[:pre])
+        tol = 1e3 * n * U
+        assert np.all(np.abs(L[:pre, :pre] - ref.L[:pre, :pre]) <=
+                      tol * np.maximum(1.0, np.abs(ref.L[:pre, :pre])))
+        assert np.all(np.abs(D[:pre] - ref.D[:pre]) <= tol * np.maximum(1.0, np.abs(ref.D[:pre])))
+        if pre == n:
             assert np.all(np.abs(L - ref.L) <= tol * np.maximum(1.0, np.abs(ref.L)))
             assert np.all(np.abs(D - ref.D) <= tol * np.maximum(1.0, np.abs(ref.D)))
             assert np.max(np.abs(x - xr)) <= 1e-9 * max(1.0, np.max(np.abs(xr)))
+        else:
+            partial.append((i, n, pre))
+    _say(f"  systems compared up to a near-tie only: {len(partial)} {partial}")
+    # the mixes used here have none; a change of inputs that brings one in
+    # must be looked at, not passed silently
+    assert not partial
     batch.close()
 
 

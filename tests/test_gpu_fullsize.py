@@ -9,15 +9,22 @@ with the next block's selection).
     1e3 n u max(1, |oracle|), reconstruction <= 50 n u, solve backward error
     <= 1e-13 and the solution within 1e-9 of the oracle's;
   * householder16384 (n = 16384, b = 128, p = 16, cond 1e6, the headline):
-    too large for the oracle in test time, so sampled outputs and properties
-    that hold at any size: perm a permutation; ipiv a valid pattern; L unit
-    lower with L(i+1, i) = 0 inside every 2x2 block; 4096 sampled entries
-    (i >= j) of P A P^T - L D L^T each within 50 n u ||A||_inf (the bound of
-    the parity tests' norm check); solve backward error <= 1e-13; the same
-    factors bit for bit with the update overlapped or not, and on a repeat.
+    against the oracle's run stored in tests/golden/householder16384_oracle.npz
+    (written by tests/golden/make_householder16384.py, which calls only the
+    oracle): the permutation and the block pattern bit-exact on every
+    position that no near-tie decides (the stored prefix: before the first
+    decision whose gap is <= 1e-9 max|A|), D and the stored rows of L within
+    1e3 n u max(1, |oracle|) there, and the solution within cond * 1e-13 of
+    the oracle's; then properties that hold at any size: perm a permutation;
+    ipiv a valid pattern; L unit lower with L(i+1, i) = 0 inside every 2x2
+    block; 4096 sampled entries (i >= j) of P A P^T - L D L^T each within
+    50 n u ||A||_inf (the bound of the parity tests' norm check); solve
+    backward error <= 1e-13; the same factors bit for bit with the update
+    overlapped or not, and on a repeat.
 Every case prints its name before running.
 """
 
+import os
 import sys
 
 import numpy as np
@@ -29,6 +36,8 @@ from workloads import CONFIGS
 pytestmark = pytest.mark.gpu
 
 U = np.finfo(np.float64).eps / 2
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "householder16384_oracle.npz")
 
 
 def _say(msg):
@@ -114,6 +123,25 @@ def test_householder16384_full_size(rcp):
     assert f.info == 0
     perm, ipiv, L, D = _host(f)
     L = np.ascontiguousarray(L)     # row-major: the sampled products read rows
+    st = rcp.rcp_get_stats()
+    # ---- against the oracle's run of the same problem
+    gold = np.load(GOLDEN)
+    assert int(gold["n"]) == n and int(gold["b"]) == cfg.b and int(gold["p"]) == cfg.p
+    pre = int(gold["near_tie_prefix"])
+    first = int(np.argmax(perm != gold["perm"])) if np.any(perm != gold["perm"]) else n
+    _say(f"  oracle near-tie prefix {pre}; first differing position {first}; "
+         f"GPU threshold margin min {st['min_margin']:.2e}, near-ties {st['near_ties']}")
+    assert pre > n // 2      # the comparison below covers most of the sequence
+    assert np.array_equal(perm[:pre], gold["perm"][:pre])
+    assert np.array_equal(ipiv[:pre], gold["ipiv"][:pre])
+    tol = 1e3 * n * U
+    Dg = gold["D"]
+    assert np.all(np.abs(D[:pre] - Dg[:pre]) <= tol * np.maximum(1.0, np.abs(Dg[:pre])))
+    assert np.all(np.abs(D[n:n + pre] - Dg[n:n + pre]) <=
+                  tol * np.maximum(1.0, np.abs(Dg[n:n + pre])))
+    for r, row in zip(gold["L_row_pos"], gold["L_rows"]):
+        if r < pre:
+            assert np.all(np.abs(L[r] - row) <= tol * np.maximum(1.0, np.abs(row))), r
     # a permutation and a valid block pattern
     assert np.array_equal(np.sort(perm), np.arange(n))
     assert set(np.unique(ipiv)).issubset({0, 1, 2})
@@ -142,8 +170,11 @@ def test_householder16384_full_size(rcp):
     B = cfg.rhs()
     X = rcp.rcp_solve(f, torch.from_numpy(B).cuda()).cpu().numpy()
     be = np.max(tb.backward_error(A, X, B))
-    _say(f"  backward error {be:.2e}")
+    xg = gold["x"]
+    fwd = np.max(np.abs(X - xg)) / np.max(np.abs(xg))
+    _say(f"  backward error {be:.2e}; difference from the oracle's solution {fwd:.2e}")
     assert be <= 1e-13
+    assert fwd <= cfg.cond * 1e-13
     del f
     # bit-identical on a repeat, and with the update not overlapped
     for overlap in (1, 0):
