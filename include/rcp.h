@@ -42,6 +42,10 @@ extern "C" {
 #define RCP_ENOMEM       (-1002) /* device workspace could not be allocated  */
 #define RCP_EUNSUPPORTED (-1003) /* size outside what this build supports    */
 #define RCP_ENOCONV      (-1004) /* refinement did not reach the tolerance    */
+#define RCP_EABORT       (-1005) /* a persistent kernel's bounded wait for
+                                    another workgroup timed out (the
+                                    cross-workgroup protocol did not complete);
+                                    the outputs are unspecified              */
 
 /* Working precisions of rcp_factor_mp. */
 #define RCP_PREC_FP32    1  /* FP32 trailing matrix, L, sketch and update    */
@@ -61,7 +65,32 @@ typedef struct rcp_stats {
   int64_t launches_update; /* number of rcp_update launches                   */
   double  flops_update;    /* algorithmic flops of all rcp_update launches     */
   double  bytes_update;    /* algorithmic HBM bytes of all rcp_update launches */
+  /* pivoting diagnostics of the last factorization (Figure 2, Section 4) */
+  double  max_abs_a;       /* max |A(i,j)| over the lower triangle read        */
+  double  max_abs_l;       /* max |L(i,j)|, i > j (the multiplier bound)      */
+  double  max_abs_d;       /* max |D(i,j)| over the entries of D              */
+  double  rho_d;           /* growth max|D| / max|A| (0 when A is zero)        */
+  double  min_margin;      /* smallest relative margin | |a| - alpha lambda | /
+                              lambda of any SBKP threshold test evaluated
+                              (a_kk always, a_rr in cases (2)/(3)); +inf if
+                              no test was evaluated                           */
+  int64_t near_ties;       /* threshold tests with that margin <= 1e-9       */
 } rcp_stats;
+
+/* Launch shape the factorization would use for the first (largest) block
+ * of an order-n problem on a device with num_cu compute units (host only,
+ * no device call): the persistent selection and panel kernels' grids. */
+typedef struct rcp_launch_info {
+  int32_t select_grid;     /* workgroups of the QRCP selection kernel          */
+  int32_t select_cols;     /* sketch columns per workgroup (R)                 */
+  int32_t select_regs;     /* 1: register-resident slab, 0: LDS-resident slab  */
+  int32_t panel_grid;      /* workgroups of the SBKP panel kernel              */
+  int32_t panel_rows;      /* rows per panel workgroup                         */
+  int64_t panel_lds;       /* LDS bytes per panel workgroup                    */
+  int64_t select_lds;      /* LDS bytes per selection workgroup               */
+  int32_t supported;       /* 1 if the shape fits (else rcp_factor returns
+                              RCP_EUNSUPPORTED)                              */
+} rcp_launch_info;
 
 /* Set the HIP stream (a hipStream_t passed as void*) used by later calls.
  * NULL selects the null stream.  Returns 0. */
@@ -80,8 +109,25 @@ int rcp_set_overlap(int32_t on);
 /* Copy the statistics of the last call into *st.  Returns 0, -1 if st is NULL. */
 int rcp_get_stats(rcp_stats* st);
 
-/* Free the cached device workspace.  Returns 0. */
+/* Free every device resource the library holds for the current device's
+ * calls: the cached workspaces, the side stream of the overlapped update and
+ * its events, the profiling events and the pinned control block.  Later
+ * calls recreate what they need.  Returns 0. */
 int rcp_release(void);
+
+/* Upper bounds on the workgroup counts of the persistent selection and panel
+ * kernels (0 = no bound beyond one workgroup per compute unit).  A bound
+ * makes each workgroup own more columns (selection) or rows (panel) of the
+ * same problem; results are identical in exact arithmetic and the decisions
+ * follow the same rules.  A shape that no longer fits LDS makes rcp_factor
+ * return RCP_EUNSUPPORTED.  Returns 0, or -1 / -2 for a negative bound. */
+int rcp_set_grid_limit(int32_t select_max, int32_t panel_max);
+
+/* Fill *out with the launch shape of the first block (see rcp_launch_info)
+ * for order n, block size b, oversampling p on num_cu compute units, under
+ * the current grid limits.  Host only.  Returns 0, or -1 (n < 1), -2 (b out
+ * of 1..128), -3 (p < 0 or b + p > 512), -4 (num_cu < 1), -5 (out NULL). */
+int rcp_launch_shape(int64_t n, int32_t b, int32_t p, int32_t num_cu, rcp_launch_info* out);
 
 /* The sketch matrix Omega (Section 3: i.i.d. N(0,1) entries) exactly as
  * rcp_factor draws it for `seed`: Philox4x64-10, key (seed, 1), counter
@@ -96,8 +142,11 @@ int rcp_omega(uint64_t seed, int32_t l, int64_t n, double* out);
  *   n     order, n >= 0
  *   A     n x n, lda >= max(1,n); only the lower triangle (i >= j) is read,
  *         A is never written
- *   b     block size >= 1 (QRCP pivots chosen per block)
- *   p     oversampling >= 0; Omega has l = b + p rows (b + p <= 512)
+ *   b     block size, 1 <= b <= 128 (QRCP pivots chosen per block)
+ *   p     oversampling >= 0; Omega has l = b + p rows, l <= 512 (the
+ *         persistent kernels keep a block's panel and sketch columns in
+ *         LDS: shapes that do not fit return RCP_EUNSUPPORTED, see
+ *         rcp_launch_shape)
  *   seed  seed of Omega, see rcp_omega
  *   perm  int64[n]: (P A P^T)(i,j) = A(perm[i], perm[j]); 0-based
  *   L     n x n, ld = n: unit lower triangular with an explicit unit
@@ -107,7 +156,7 @@ int rcp_omega(uint64_t seed, int32_t l, int64_t n, double* out);
  *   ipiv  int8[n]: 1 = 1x1 block, 2 = first index of a 2x2 block, 0 = second
  * Returns 0, -i for a bad argument i, +k for an exactly zero 1x1 pivot at
  * 1-based position k (first one; the factorization is still complete),
- * RCP_ENONFINITE, RCP_EDEVICE, RCP_ENOMEM or RCP_EUNSUPPORTED. */
+ * RCP_ENONFINITE, RCP_EDEVICE, RCP_ENOMEM, RCP_EUNSUPPORTED or RCP_EABORT. */
 int rcp_factor(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p,
                uint64_t seed, int64_t* perm, double* L, double* D, int8_t* ipiv);
 
@@ -116,7 +165,8 @@ int rcp_factor(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p,
  *   L, D, ipiv, perm  as written by rcp_factor for the same n
  *   B     n x nrhs, ldb >= max(1,n), overwritten by X
  * Returns 0, -i for a bad argument, +k if D has an exactly zero 1x1 pivot at
- * 1-based position k (B is then left untouched), or RCP_EDEVICE. */
+ * 1-based position k (B is then left untouched), RCP_EDEVICE, RCP_ENOMEM or
+ * RCP_EABORT. */
 int rcp_solve(int64_t n, const double* L, const double* D, const int8_t* ipiv,
               const int64_t* perm, int64_t nrhs, double* B, int64_t ldb);
 

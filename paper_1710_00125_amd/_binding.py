@@ -1,5 +1,6 @@
 """ctypes marshalling for librcp.so (see include/rcp.h for the contract)."""
 
+import atexit
 import ctypes
 import os
 from dataclasses import dataclass
@@ -12,6 +13,7 @@ RCP_EDEVICE = -1001
 RCP_ENOMEM = -1002
 RCP_EUNSUPPORTED = -1003
 RCP_ENOCONV = -1004
+RCP_EABORT = -1005
 RCP_PREC_FP32 = 1
 RCP_PREC_BF16X3 = 2
 
@@ -30,7 +32,17 @@ class _Stats(ctypes.Structure):
                 ("ms_sketch_update", ctypes.c_double), ("ms_commit", ctypes.c_double),
                 ("ms_update", ctypes.c_double), ("ms_finalize", ctypes.c_double),
                 ("ms_solve", ctypes.c_double), ("launches_update", ctypes.c_int64),
-                ("flops_update", ctypes.c_double), ("bytes_update", ctypes.c_double)]
+                ("flops_update", ctypes.c_double), ("bytes_update", ctypes.c_double),
+                ("max_abs_a", ctypes.c_double), ("max_abs_l", ctypes.c_double),
+                ("max_abs_d", ctypes.c_double), ("rho_d", ctypes.c_double),
+                ("min_margin", ctypes.c_double), ("near_ties", ctypes.c_int64)]
+
+
+class _LaunchInfo(ctypes.Structure):
+    _fields_ = [("select_grid", ctypes.c_int32), ("select_cols", ctypes.c_int32),
+                ("select_regs", ctypes.c_int32), ("panel_grid", ctypes.c_int32),
+                ("panel_rows", ctypes.c_int32), ("panel_lds", ctypes.c_int64),
+                ("select_lds", ctypes.c_int64), ("supported", ctypes.c_int32)]
 
 
 class _IrResult(ctypes.Structure):
@@ -49,6 +61,9 @@ _SIGS = {
     "rcp_set_overlap": (ctypes.c_int, [ctypes.c_int32]),
     "rcp_get_stats": (ctypes.c_int, [ctypes.POINTER(_Stats)]),
     "rcp_release": (ctypes.c_int, []),
+    "rcp_set_grid_limit": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32]),
+    "rcp_launch_shape": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.POINTER(_LaunchInfo)]),
     "rcp_omega": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64,
                                  ctypes.c_void_p]),
     "rcp_factor": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
@@ -103,7 +118,18 @@ def load():
             f.restype = res
             f.argtypes = args
         _LIB = lib
+        # free the library's device resources before the interpreter (and
+        # with it torch and the HIP runtime) shuts down
+        atexit.register(_release_at_exit)
     return _LIB
+
+
+def _release_at_exit():
+    if _LIB is not None:
+        try:
+            _LIB.rcp_release()
+        except Exception:
+            pass
 
 
 def exported_symbols():
@@ -148,6 +174,20 @@ def rcp_set_overlap(on):
 
 def rcp_release():
     return load().rcp_release()
+
+
+def rcp_set_grid_limit(select_max=0, panel_max=0):
+    """Bound the persistent selection / panel grids (0: one workgroup per CU)."""
+    return _check("rcp_set_grid_limit",
+                  load().rcp_set_grid_limit(int(select_max), int(panel_max)))
+
+
+def rcp_launch_shape(n, b, p, num_cu=256):
+    """Launch shape of the first block (host-only query), as a dict."""
+    info = _LaunchInfo()
+    _check("rcp_launch_shape", load().rcp_launch_shape(int(n), int(b), int(p), int(num_cu),
+                                                       ctypes.byref(info)))
+    return {name: getattr(info, name) for name, _ in _LaunchInfo._fields_}
 
 
 def rcp_get_stats():

@@ -20,14 +20,23 @@ enum Prec : int {
 };
 inline size_t prec_elem_bytes(int prec) { return prec == kPrecF64 ? 8 : 4; }
 
-// Device-resident control block of one factorization.
+// Device-resident control block of one factorization.  The unsigned 64-bit
+// fields hold the bit patterns of non-negative doubles, which order like the
+// integers, so that atomicMax / atomicMin on them compare the values.
 struct Ctrl {
   int m;            // columns eliminated by the last panel (b or b+1)
   int info;         // first exactly-zero 1x1 pivot, 1-based (INT_MAX: none)
   int nonfinite;    // set if the sketch held a NaN or Inf
   int abort_flag;   // set if a wait for another workgroup's record timed out
   long long ncase[4];  // SBKP cases (0)..(3) of Figure 2
+  unsigned long long max_abs_a;   // max |A| over the lower triangle read
+  unsigned long long max_abs_l;   // max |L| over the multipliers
+  unsigned long long max_abs_d;   // max |D| over the entries of D
+  unsigned long long min_margin;  // min | |a| - alpha lambda | / lambda of the SBKP tests
+  long long near_ties;            // SBKP tests with that margin <= kNearTie
 };
+// a decision margin at or below this is a near-tie (relative)
+constexpr double kNearTie = 1e-9;
 
 // Scratch used by the persistent kernels to exchange per-workgroup
 // candidates (two parities, see the kernels).
@@ -46,9 +55,10 @@ void launch_omega(uint64_t seed, int l, int64_t n, double* out, int transposed, 
                   hipStream_t s);
 
 // ---- sketch.hip
-// Acur (n x n, ld n, lower; double or float by prec) <- lower triangle of A (lda)
+// Acur (n x n, ld n, lower; double or float by prec) <- lower triangle of A
+// (lda); ctrl->max_abs_a <- max |A| over that triangle
 void launch_copy_lower(int64_t n, const double* A, int64_t lda, void* Acur, int prec,
-                       hipStream_t s);
+                       Ctrl* ctrl, hipStream_t s);
 // B (lpad x n column-major, B(r,j) at j*lpad + r) = Omega * sym(A)
 // using Omega^T (n x lpad) and a split-K partial buffer of ksplit*n*lpad doubles;
 // FP64 matrix cores for prec == kPrecF64, FP32 matrix cores otherwise
@@ -66,6 +76,10 @@ void launch_iota64(int64_t n, int64_t* P, hipStream_t s);
 // kernel (about 140 registers per lane) runs where the shape fits it, the
 // LDS kernel elsewhere.
 int select_grid(int N, int lpad, int num_cu);
+// the register-resident kernel is taken for this shape (else the LDS one)
+bool select_uses_registers(int l, int R, int G);
+// dynamic LDS bytes of one selection workgroup
+size_t select_lds_bytes(int l, int lpad, int R, int bb, bool regs);
 void launch_select(const double* B, int lpad, int l, int N, int bb, int* posof, int* win,
                    Exchange ex, int G, hipStream_t s);
 
@@ -123,6 +137,9 @@ void launch_finalize_L(int64_t n, const void* Lwork, const int64_t* P, const int
                        void* L, int l_f32, hipStream_t s);
 void launch_find_zero_pivot(int64_t n, const double* D, const int8_t* ipiv, int* out,
                             hipStream_t s);
+// ctrl->max_abs_d <- max |D| over the entries of the block diagonal factor
+void launch_max_abs_d(int64_t n, const double* D, const int8_t* ipiv, Ctrl* ctrl,
+                      hipStream_t s);
 // B <- A^{-1} B with the factors (L double when l_f32 == 0, float otherwise;
 // the right-hand sides and all arithmetic stay FP64).  work holds
 // solve_work_doubles(n, nrhs) doubles, sync solve_sync_words() words; the
@@ -132,7 +149,18 @@ void launch_solve(int64_t n, const void* L, int l_f32, const double* D, const in
                   const int64_t* perm, int64_t nrhs, double* B, int64_t ldb, double* work,
                   unsigned int* sync, hipStream_t s);
 size_t solve_sync_words(int64_t n);
-size_t solve_work_doubles(int64_t n, int64_t nrhs);
+// doubles of solve scratch: three n x min(nrhs, 8) blocks of right-hand
+// sides and the inverses of the 64 x 64 diagonal blocks of L
+constexpr int kSolveBlk = 64;
+constexpr int kSolveMaxRhs = 8;
+constexpr size_t solve_work_doubles(int64_t n, int64_t nrhs) {
+  return (size_t)(3 * n * (nrhs < kSolveMaxRhs ? nrhs : kSolveMaxRhs) +
+                  ((n + kSolveBlk - 1) / kSolveBlk) * kSolveBlk * kSolveBlk);
+}
+// p[0..count) <- 0 by a kernel (no memset node when the stream is captured)
+void launch_zero_words(unsigned int* p, int count, hipStream_t s);
+// *p <- v by a kernel
+void launch_set_int(int* p, int v, hipStream_t s);
 
 // ---- batched.hip  (many small systems, one workgroup each)
 constexpr int kBatchMaxN = 512;
@@ -188,5 +216,17 @@ void launch_lsq_update(int64_t n, int nr, int m, const void* st, const double* g
                        hipStream_t s);
 int gmres_state_active(const void* host_st, int c);
 int gmres_state_iters(const void* host_st, int c);
+
+// ---- rcp_api.cpp  (host side shared by the solve entry points)
+// argument checks of rcp_solve (0 or -i for argument i)
+int solve_args(int64_t n, const void* L, const double* D, const int8_t* ipiv,
+               const int64_t* perm, int64_t nrhs, const double* B, int64_t ldb);
+// the solve on the library stream with caller-given scratch: Y holds
+// solve_work_doubles(n, nrhs) doubles, sync solve_sync_words(n) words, zp
+// one int; allocates nothing (timing events only when `timed`).  Returns as
+// rcp_solve.
+int solve_core(int64_t n, const void* L, int l_f32, const double* D, const int8_t* ipiv,
+               const int64_t* perm, int64_t nrhs, double* B, int64_t ldb, double* Y,
+               unsigned int* sync, int* zp, bool timed);
 
 }  // namespace rcp

@@ -205,6 +205,9 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
   int it = 0;   // iteration (decision) count: parity of the exchange slots and record tag
   long long ncase[4] = {0, 0, 0, 0};
   double bp1 = 0.0, bp2 = 0.0;    // prefetched B(r, pivot) for my first pass of T rows
+  double lmax = 0.0;              // largest |multiplier| this thread stored
+  double mmin = INFINITY;         // smallest threshold-test margin (workgroup 0)
+  long long nties = 0;            // threshold tests within kNearTie (workgroup 0)
 
   // ---- prologue
   for (int r = tid; r < nown; r += kThreads) {
@@ -442,12 +445,14 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
             Lrr[k + 1] = l2;
             st_agent(&Lg[k], l1);
             st_agent(&Lg[k + 1], l2);
+            lmax = fmax(lmax, fmax(fabs(l1), fabs(l2)));
             const double w1 = fma(l1, akk, l2 * ark), w2 = fma(l1, ark, l2 * arr);
             Adiag[r] -= fma(l1, w1, l2 * w2);
           } else {
             const double l1 = mult_1x1(kase == 2 ? vr : vcol[r], dpiv);
             Lrr[k] = l1;
             st_agent(&Lg[k], l1);
+            lmax = fmax(lmax, fabs(l1));
             Adiag[r] = fma(-l1, l1 * dpiv, Adiag[r]);
           }
         } else if (kase == 3 && s0 + r == rsrc) {
@@ -524,6 +529,13 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
           if (dpiv == 0.0) atomicMin(&a.ctrl->info, (int)(gk + 1));
         }
         ncase[kase] += 1;
+        // relative margins of the threshold tests this step evaluated
+        if (lam > 0.0) {
+          double mg = fabs(fabs(akk) - RCP_ALPHA * lam) / lam;
+          if (kase >= 2) mg = fmin(mg, fabs(fabs(arr) - RCP_ALPHA * lam) / lam);
+          mmin = fmin(mmin, mg);
+          nties += (mg <= kNearTie) ? 1 : 0;
+        }
       }
     }
     __syncthreads();
@@ -574,7 +586,19 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
   if (g == 0 && tid == 128) {
     for (int i = 0; i < 4; ++i)
       atomicAdd((unsigned long long*)&a.ctrl->ncase[i], (unsigned long long)ncase[i]);
+    if (mmin < INFINITY)
+      atomicMin(&a.ctrl->min_margin, (unsigned long long)__double_as_longlong(mmin));
+    if (nties) atomicAdd((unsigned long long*)&a.ctrl->near_ties, (unsigned long long)nties);
   }
+  // largest multiplier magnitude: one atomic per wave
+  lmax = fmax(lmax, xchg<1>(lmax));
+  lmax = fmax(lmax, xchg<2>(lmax));
+  lmax = fmax(lmax, xchg<4>(lmax));
+  lmax = fmax(lmax, xchg<8>(lmax));
+  lmax = fmax(lmax, xchg<16>(lmax));
+  lmax = fmax(lmax, xchg<32>(lmax));
+  if ((tid & 63) == 0 && lmax > 0.0)
+    atomicMax(&a.ctrl->max_abs_l, (unsigned long long)__double_as_longlong(lmax));
 }
 
 size_t panel_lds(int R, int ldp, int bb, int ntr, int ldt) {

@@ -26,6 +26,8 @@ hipStream_t g_stream = nullptr;
 bool g_prof = false;
 bool g_overlap = true;
 rcp_stats g_stats;
+int g_select_limit = 0;   // bounds on the persistent kernels' grids (0: none)
+int g_panel_limit = 0;
 
 struct Arena {
   int device = -1;
@@ -152,6 +154,38 @@ int num_cus() {
     if ((x) != hipSuccess) return RCP_EDEVICE; \
   } while (0)
 
+// LDS budget of one persistent workgroup's dynamic allocation (gfx950 has
+// 160 KB per CU; the rest is static shared memory and slack)
+constexpr size_t kLdsBudget = 140 * 1024;
+
+int capped(int ncu, int limit) { return limit > 0 ? std::min(ncu, limit) : ncu; }
+
+// Launch shape of the first (largest) block: the selection and panel grids
+// on `ncu` compute units under the current grid limits, and whether they
+// fit (later blocks are smaller and fit whenever the first one does).
+struct FirstBlockShape {
+  int Gs = 0, Rs = 0, Gp = 0, Rp = 0, ngr = 0;
+  bool sel_regs = false, ok = false;
+  size_t sel_lds = 0, pan_lds = 0;
+};
+FirstBlockShape first_block_shape(int64_t n, int b, int p, int ncu) {
+  FirstBlockShape sh;
+  const int l = b + p;
+  const int lpad = (l + 15) / 16 * 16;
+  const int ldp = (b + 2) | 1;
+  const int N = (int)n;
+  const int bb = std::min<int>(b, N);
+  sh.Gs = select_grid(N, lpad, capped(ncu, g_select_limit));
+  sh.Rs = (N + sh.Gs - 1) / sh.Gs;
+  sh.sel_regs = select_uses_registers(l, sh.Rs, sh.Gs);
+  sh.sel_lds = select_lds_bytes(l, lpad, sh.Rs, bb, sh.sel_regs);
+  sh.Gp = panel_grid(N, ldp, lpad, capped(ncu, g_panel_limit), &sh.pan_lds, &sh.ngr);
+  sh.Rp = (N + sh.Gp - 1) / sh.Gp;
+  sh.ok = (sh.sel_regs || (sh.sel_lds <= kLdsBudget && sh.Gs <= 1024)) &&
+          sh.pan_lds <= kLdsBudget && sh.Gp <= 256;
+  return sh;
+}
+
 }  // namespace
 
 extern "C" {
@@ -182,6 +216,44 @@ int rcp_release(void) {
   if (g_solve.base) hipFree(g_solve.base);
   g_fact = Arena();
   g_solve = Arena();
+  if (g_side.s) {
+    hipStreamSynchronize(g_side.s);
+    hipStreamDestroy(g_side.s);
+  }
+  if (g_side.committed) hipEventDestroy(g_side.committed);
+  if (g_side.updated) hipEventDestroy(g_side.updated);
+  g_side = SideStream();
+  for (hipEvent_t e : g_profiler.pool) hipEventDestroy(e);
+  g_profiler.pool.clear();
+  g_profiler.reset();
+  if (g_ctrl_host) hipHostFree(g_ctrl_host);
+  g_ctrl_host = nullptr;
+  return 0;
+}
+
+int rcp_set_grid_limit(int32_t select_max, int32_t panel_max) {
+  if (select_max < 0) return -1;
+  if (panel_max < 0) return -2;
+  g_select_limit = select_max;
+  g_panel_limit = panel_max;
+  return 0;
+}
+
+int rcp_launch_shape(int64_t n, int32_t b, int32_t p, int32_t num_cu, rcp_launch_info* out) {
+  if (n < 1) return -1;
+  if (b < 1 || b > kMaxB) return -2;
+  if (p < 0 || b + p > kMaxL) return -3;
+  if (num_cu < 1) return -4;
+  if (!out) return -5;
+  const FirstBlockShape sh = first_block_shape(n, b, p, num_cu);
+  out->select_grid = sh.Gs;
+  out->select_cols = sh.Rs;
+  out->select_regs = sh.sel_regs ? 1 : 0;
+  out->panel_grid = sh.Gp;
+  out->panel_rows = sh.Rp;
+  out->panel_lds = (int64_t)sh.pan_lds;
+  out->select_lds = (int64_t)sh.sel_lds;
+  out->supported = sh.ok ? 1 : 0;
   return 0;
 }
 
@@ -206,6 +278,7 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
                 int prec, int64_t* perm, void* L, double* D, int8_t* ipiv) {
   memset(&g_stats, 0, sizeof(g_stats));
   g_stats.n = n;
+  g_stats.min_margin = INFINITY;
   if (n == 0) return 0;
   if (n > INT_MAX / 2) return RCP_EUNSUPPORTED;
 
@@ -213,20 +286,13 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
   const int lpad = (l + 15) / 16 * 16;
   const int ldp = (b + 2) | 1;
   const int ncu = num_cus();
+  const int ncu_sel = capped(ncu, g_select_limit);
+  const int ncu_pan = capped(ncu, g_panel_limit);
   const int ksplit = 4;
   const int64_t rows_pad_max = (n + 127) / 128 * 128;
 
   // feasibility of the LDS-resident panels for the first (largest) block
-  {
-    const int Gs = select_grid((int)n, lpad, ncu);
-    const int Rs = (int)((n + Gs - 1) / Gs);
-    if ((size_t)Rs * (l | 1) * 8 + (size_t)lpad * 8 + (size_t)Rs * 12 + 4096 > 140 * 1024)
-      return RCP_EUNSUPPORTED;
-    size_t lds = 0;
-    int ngr = 0;
-    const int Gp = panel_grid((int)n, ldp, lpad, ncu, &lds, &ngr);
-    if (lds > 140 * 1024 || Gp > 256) return RCP_EUNSUPPORTED;
-  }
+  if (!first_block_shape(n, b, p, ncu).ok) return RCP_EUNSUPPORTED;
   const int Gmax = ncu;
   const int vec_stride = std::max(lpad, ldp);
 
@@ -266,29 +332,63 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
   ex.abort_flag = &ctrl->abort_flag;
 
   if (!g_ctrl_host) {
-    if (hipHostMalloc((void**)&g_ctrl_host, sizeof(Ctrl)) != hipSuccess) return RCP_EDEVICE;
+    if (hipHostMalloc((void**)&g_ctrl_host, sizeof(Ctrl)) != hipSuccess) {
+      g_ctrl_host = nullptr;
+      return RCP_EDEVICE;
+    }
   }
+  if (!side_stream_ready(dev)) return RCP_EDEVICE;
   hipStream_t s = g_stream;
-  hipEvent_t t0, t1;
-  hipEventCreate(&t0);
-  hipEventCreate(&t1);
-  hipEventRecord(t0, s);
+  hipStream_t s2 = g_side.s;
 
+  // Every exit below goes through `finish`: it waits for both streams (so
+  // that no kernel still writes the workspace when the call returns), reads
+  // the statistics and destroys the two timing events.
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) {
+    if (t0) hipEventDestroy(t0);
+    return RCP_EDEVICE;
+  }
+  int nblocks = 0;
+  auto finish = [&](int status) -> int {
+    bool dev_ok = hipEventRecord(t1, s) == hipSuccess;
+    dev_ok = (hipStreamSynchronize(s) == hipSuccess) && dev_ok;
+    dev_ok = (hipStreamSynchronize(s2) == hipSuccess) && dev_ok;
+    float ms = 0.f;
+    if (dev_ok) hipEventElapsedTime(&ms, t0, t1);
+    hipEventDestroy(t0);
+    hipEventDestroy(t1);
+    g_stats.ms_total = ms;
+    g_stats.nblocks = nblocks;
+    if (g_prof) collect_profile();
+    if (!dev_ok && status == 0) status = RCP_EDEVICE;
+    return status;
+  };
+#define RCP_TRY(x)                                   \
+  do {                                               \
+    if ((x) != hipSuccess) return finish(RCP_EDEVICE); \
+  } while (0)
+
+  RCP_TRY(hipEventRecord(t0, s));
   memset(g_ctrl_host, 0, sizeof(Ctrl));
   g_ctrl_host->info = INT_MAX;
-  RCP_CHECK(hipMemcpyAsync(ctrl, g_ctrl_host, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+  {
+    const double inf = INFINITY;
+    memcpy(&g_ctrl_host->min_margin, &inf, 8);
+  }
+  RCP_TRY(hipMemcpyAsync(ctrl, g_ctrl_host, sizeof(Ctrl), hipMemcpyHostToDevice, s));
   {
     Scope sc(KOmega);
     launch_omega(seed, l, n, OmT, 1, lpad, s);
   }
   {
     Scope sc(KSketch);
-    launch_copy_lower(n, A, lda, Acur, prec, s);
+    launch_copy_lower(n, A, lda, Acur, prec, ctrl, s);
     launch_sketch(n, Acur, prec, n, OmT, lpad, Bcur, partial, ksplit, s);
     launch_check_finite(n, Bcur, lpad, l, ctrl, s);
     launch_iota64(n, P0, s);
   }
-  RCP_CHECK(hipGetLastError());
+  RCP_TRY(hipGetLastError());
 
   int64_t* Pc = P0;
   int64_t* Pn = P1;
@@ -297,15 +397,12 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
   double* Bc = Bcur;
   double* Bn = Bnext;
   int64_t K0 = 0;
-  int nblocks = 0;
   int status = 0;
-  if (!side_stream_ready(dev)) return RCP_EDEVICE;
-  hipStream_t s2 = g_side.s;
   bool update_in_flight = false;
   bool selected = false;   // the selection of the current block is enqueued
   auto enqueue_select = [&](int Nb) {
     Scope sc(KSelect);
-    const int Gs = select_grid(Nb, lpad, ncu);
+    const int Gs = select_grid(Nb, lpad, ncu_sel);
     hipMemsetAsync(ex.rec, 0, (size_t)32 * Gmax * sizeof(unsigned long long), s);
     launch_select(Bc, lpad, l, Nb, std::min<int>(b, Nb), posof, win, ex, Gs, s);
   };
@@ -315,13 +412,13 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
     if (!selected) enqueue_select(N);
     selected = false;
     // the panel reads the trailing matrix: the previous block's update first
-    if (update_in_flight) RCP_CHECK(hipStreamWaitEvent(s, g_side.updated, 0));
+    if (update_in_flight) RCP_TRY(hipStreamWaitEvent(s, g_side.updated, 0));
     update_in_flight = false;
     {
       Scope sc(KPanel);
       size_t lds = 0;
       int ngr = 0;
-      const int Gp = panel_grid(N, ldp, lpad, ncu, &lds, &ngr);
+      const int Gp = panel_grid(N, ldp, lpad, ncu_pan, &lds, &ngr);
       PanelArgs pa;
       pa.A = Ac + (size_t)(K0 + K0 * n) * esz;
       pa.prec = prec;
@@ -345,11 +442,11 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
       hipMemsetAsync(ex.rec, 0, (size_t)32 * Gmax * sizeof(unsigned long long), s);
       launch_panel(pa, ex, Gp, ngr, lds, s);
     }
-    RCP_CHECK(hipGetLastError());
-    RCP_CHECK(hipMemcpyAsync(g_ctrl_host, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
-    RCP_CHECK(hipStreamSynchronize(s));
+    RCP_TRY(hipGetLastError());
+    RCP_TRY(hipMemcpyAsync(g_ctrl_host, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    RCP_TRY(hipStreamSynchronize(s));
     if (g_ctrl_host->abort_flag) {
-      status = RCP_EDEVICE;
+      status = RCP_EABORT;
       break;
     }
     if (g_ctrl_host->nonfinite) {
@@ -358,7 +455,7 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
     }
     const int m = g_ctrl_host->m;
     if (m < 1 || m > bb + 1 || K0 + m > n) {
-      status = RCP_EDEVICE;
+      status = RCP_EABORT;
       break;
     }
     const int64_t K1 = K0 + m;
@@ -375,24 +472,24 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
                     W21p, Qk, rows_pad, rowsrc, s);
     }
     if (N2 > 0) {
-      RCP_CHECK(hipEventRecord(g_side.committed, s));
-      RCP_CHECK(hipStreamWaitEvent(s2, g_side.committed, 0));
+      RCP_TRY(hipEventRecord(g_side.committed, s));
+      RCP_TRY(hipStreamWaitEvent(s2, g_side.committed, 0));
       {
         Scope sc(KUpdate, s2);
         launch_update(Ac + (size_t)(K0 + K0 * n) * esz, An + (size_t)(K1 + K1 * n) * esz, n,
                       rowsrc, N2, L21p, W21p, Qk, prec, ncu, s2);
       }
-      RCP_CHECK(hipEventRecord(g_side.updated, s2));
+      RCP_TRY(hipEventRecord(g_side.updated, s2));
       update_in_flight = true;
       if (!g_overlap) {
-        RCP_CHECK(hipStreamWaitEvent(s, g_side.updated, 0));
+        RCP_TRY(hipStreamWaitEvent(s, g_side.updated, 0));
         update_in_flight = false;
       }
       g_stats.launches_update += 1;
       g_stats.flops_update += (double)N2 * (N2 + 1) * m;           // lower triangle, 2m per entry
       g_stats.bytes_update += (double)N2 * (N2 + 1) / 2 * 2.0 * esz;   // read + write of each entry
     }
-    RCP_CHECK(hipGetLastError());
+    RCP_TRY(hipGetLastError());
     std::swap(Pc, Pn);
     std::swap(Ac, An);
     std::swap(Bc, Bn);
@@ -405,35 +502,35 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
       selected = true;
     }
   }
-  if (update_in_flight) RCP_CHECK(hipStreamWaitEvent(s, g_side.updated, 0));
+  if (update_in_flight) RCP_TRY(hipStreamWaitEvent(s, g_side.updated, 0));
   if (status == 0) {
     Scope sc(KFinal);
     launch_finalize_L(n, Lwork, Pc, ipiv, L, prec != kPrecF64, s);
-    RCP_CHECK(hipMemcpyAsync(perm, Pc, n * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
-    RCP_CHECK(hipMemcpyAsync(g_ctrl_host, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    launch_max_abs_d(n, D, ipiv, ctrl, s);
+    RCP_TRY(hipMemcpyAsync(perm, Pc, n * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
   }
-  hipEventRecord(t1, s);
-  RCP_CHECK(hipGetLastError());
-  RCP_CHECK(hipStreamSynchronize(s));
-  RCP_CHECK(hipStreamSynchronize(s2));
-  float ms = 0.f;
-  hipEventElapsedTime(&ms, t0, t1);
-  hipEventDestroy(t0);
-  hipEventDestroy(t1);
-  g_stats.ms_total = ms;
-  g_stats.nblocks = nblocks;
-  for (int i = 0; i < 4; ++i) g_stats.ncase[i] = g_ctrl_host->ncase[i];
-  g_stats.n2x2 = g_ctrl_host->ncase[3];
-  if (g_prof) collect_profile();
+  RCP_TRY(hipMemcpyAsync(g_ctrl_host, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+  RCP_TRY(hipGetLastError());
+  status = finish(status);
+#undef RCP_TRY
+  const Ctrl& c = *g_ctrl_host;
+  for (int i = 0; i < 4; ++i) g_stats.ncase[i] = c.ncase[i];
+  g_stats.n2x2 = c.ncase[3];
+  memcpy(&g_stats.max_abs_a, &c.max_abs_a, 8);
+  memcpy(&g_stats.max_abs_l, &c.max_abs_l, 8);
+  memcpy(&g_stats.max_abs_d, &c.max_abs_d, 8);
+  memcpy(&g_stats.min_margin, &c.min_margin, 8);
+  g_stats.near_ties = c.near_ties;
+  g_stats.rho_d = g_stats.max_abs_a > 0.0 ? g_stats.max_abs_d / g_stats.max_abs_a : 0.0;
   if (status != 0) return status;
-  if (g_ctrl_host->info != INT_MAX) return g_ctrl_host->info;
+  if (c.abort_flag) return RCP_EABORT;
+  if (c.info != INT_MAX) return c.info;
   return 0;
 }
 
 // first exactly zero 1x1 pivot (1-based), INT_MAX if none, or an RCP_E* code
 int zero_pivot(int64_t n, const double* D, const int8_t* ipiv, int* zp, hipStream_t s) {
-  const int big = INT_MAX;
-  RCP_CHECK(hipMemcpyAsync(zp, &big, sizeof(int), hipMemcpyHostToDevice, s));
+  launch_set_int(zp, INT_MAX, s);
   launch_find_zero_pivot(n, D, ipiv, zp, s);
   int zhost = 0;
   RCP_CHECK(hipMemcpyAsync(&zhost, zp, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -441,8 +538,29 @@ int zero_pivot(int64_t n, const double* D, const int8_t* ipiv, int* zp, hipStrea
   return zhost;
 }
 
-int solve_impl(int64_t n, const void* L, int l_f32, const double* D, const int8_t* ipiv,
-               const int64_t* perm, int64_t nrhs, double* B, int64_t ldb) {
+// HIP events that are destroyed on every exit of the scope that made them
+struct EventPair {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  bool make() {
+    return hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+  }
+  float ms() const {
+    float v = 0.f;
+    if (e0 && e1) hipEventElapsedTime(&v, e0, e1);
+    return v;
+  }
+  ~EventPair() {
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+  }
+};
+
+}  // namespace
+
+namespace rcp {
+
+int solve_args(int64_t n, const void* L, const double* D, const int8_t* ipiv,
+               const int64_t* perm, int64_t nrhs, const double* B, int64_t ldb) {
   if (n < 0) return -1;
   if (n > 0 && !L) return -2;
   if (n > 0 && !D) return -3;
@@ -451,6 +569,46 @@ int solve_impl(int64_t n, const void* L, int l_f32, const double* D, const int8_
   if (nrhs < 0) return -6;
   if (n > 0 && nrhs > 0 && !B) return -7;
   if (ldb < std::max<int64_t>(1, n)) return -8;
+  return 0;
+}
+
+// The solve on caller-given scratch: Y (solve_work_doubles(n, nrhs)
+// doubles), sync (solve_sync_words words), zp (one int).  Nothing is
+// allocated here.
+int solve_core(int64_t n, const void* L, int l_f32, const double* D, const int8_t* ipiv,
+               const int64_t* perm, int64_t nrhs, double* B, int64_t ldb, double* Y,
+               unsigned int* sync, int* zp, bool timed) {
+  hipStream_t s = g_stream;
+  const size_t words = solve_sync_words(n);
+  launch_zero_words(sync, (int)words, s);
+  const int zhost = zero_pivot(n, D, ipiv, zp, s);
+  if (zhost < 0) return zhost;
+  if (zhost != INT_MAX) return zhost;
+  EventPair ev;
+  if (timed) {
+    if (!ev.make()) return RCP_EDEVICE;
+    RCP_CHECK(hipEventRecord(ev.e0, s));
+  }
+  launch_solve(n, L, l_f32, D, ipiv, perm, nrhs, B, ldb, Y, sync, s);
+  if (timed) RCP_CHECK(hipEventRecord(ev.e1, s));
+  RCP_CHECK(hipGetLastError());
+  unsigned int abort_word = 0;
+  RCP_CHECK(hipMemcpyAsync(&abort_word, sync + (words - 1), sizeof(unsigned int),
+                           hipMemcpyDeviceToHost, s));
+  RCP_CHECK(hipStreamSynchronize(s));
+  if (abort_word) return RCP_EABORT;
+  if (timed) g_stats.ms_solve = ev.ms();
+  return 0;
+}
+
+}  // namespace rcp
+
+namespace {
+
+int solve_impl(int64_t n, const void* L, int l_f32, const double* D, const int8_t* ipiv,
+               const int64_t* perm, int64_t nrhs, double* B, int64_t ldb) {
+  const int bad = solve_args(n, L, D, ipiv, perm, nrhs, B, ldb);
+  if (bad) return bad;
   if (n == 0 || nrhs == 0) return 0;
   int dev = 0;
   hipGetDevice(&dev);
@@ -460,33 +618,7 @@ int solve_impl(int64_t n, const void* L, int l_f32, const double* D, const int8_
   double* Y = g_solve.take<double>(solve_work_doubles(n, nrhs));
   unsigned int* sync = g_solve.take<unsigned int>(words);
   int* zp = g_solve.take<int>(16);
-  hipStream_t s = g_stream;
-  RCP_CHECK(hipMemsetAsync(sync, 0, words * sizeof(unsigned int), s));
-  const int zhost = zero_pivot(n, D, ipiv, zp, s);
-  if (zhost < 0) return zhost;
-  if (zhost != INT_MAX) return zhost;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (g_prof) {
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
-    hipEventRecord(e0, s);
-  }
-  launch_solve(n, L, l_f32, D, ipiv, perm, nrhs, B, ldb, Y, sync, s);
-  if (g_prof) hipEventRecord(e1, s);
-  RCP_CHECK(hipGetLastError());
-  unsigned int abort_word = 0;
-  RCP_CHECK(hipMemcpyAsync(&abort_word, sync + (words - 1), sizeof(unsigned int),
-                           hipMemcpyDeviceToHost, s));
-  RCP_CHECK(hipStreamSynchronize(s));
-  if (abort_word) return RCP_EDEVICE;
-  if (g_prof) {
-    float ms = 0.f;
-    hipEventElapsedTime(&ms, e0, e1);
-    g_stats.ms_solve = ms;
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-  }
-  return 0;
+  return solve_core(n, L, l_f32, D, ipiv, perm, nrhs, B, ldb, Y, sync, zp, g_prof);
 }
 
 }  // namespace
@@ -721,7 +853,7 @@ int rcp_solve_ir(int64_t n, const double* A, int64_t lda, const float* L, const 
     res->berr = berr_max;
     res->ms = ms;
   }
-  if (abort_word) return RCP_EDEVICE;
+  if (abort_word) return RCP_EABORT;
   return status;
 }
 

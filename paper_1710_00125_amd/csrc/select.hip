@@ -462,6 +462,16 @@ int select_grid(int N, int lpad, int num_cu) {
   return G;
 }
 
+bool select_uses_registers(int l, int R, int G) {
+  return l <= 16 * kRegRows && R <= 16 * kRegCols && G <= 256;
+}
+
+size_t select_lds_bytes(int l, int lpad, int R, int bb, bool regs) {
+  if (regs) return (size_t)(bb + 2) * 4;
+  return (size_t)R * (l | 1) * 8 + (size_t)lpad * 8 + (size_t)R * 8 + (size_t)R * 4 +
+         (size_t)(bb + 2) * 4 + 64;
+}
+
 void launch_select(const double* B, int lpad, int l, int N, int bb, int* posof, int* win,
                    Exchange ex, int G, hipStream_t s) {
   SelectParams p;
@@ -476,14 +486,13 @@ void launch_select(const double* B, int lpad, int l, int N, int bb, int* posof, 
   p.win = win;
   p.ex = ex;
   void* args[] = {&p};
-  if (l <= 16 * kRegRows && p.R <= 16 * kRegCols && G <= 256) {
-    const size_t lds = (size_t)(bb + 2) * 4;
+  if (select_uses_registers(l, p.R, G)) {
+    const size_t lds = select_lds_bytes(l, lpad, p.R, bb, true);
     hipLaunchCooperativeKernel((const void*)select_reg_kernel, dim3(G), dim3(kThreads), args, lds,
                                s);
     return;
   }
-  const size_t lds = (size_t)p.R * (l | 1) * 8 + (size_t)lpad * 8 + (size_t)p.R * 8 +
-                     (size_t)p.R * 4 + (size_t)(bb + 2) * 4 + 64;
+  const size_t lds = select_lds_bytes(l, lpad, p.R, bb, false);
   hipFuncSetAttribute((const void*)select_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)lds);
   hipLaunchCooperativeKernel((const void*)select_kernel, dim3(G), dim3(kThreads), args, lds, s);

@@ -129,11 +129,25 @@ __global__ void sketch_reduce_kernel(int64_t total, int ksplit, int64_t stride,
 
 template <typename TA>
 __global__ void copy_lower_kernel(int64_t n, const double* __restrict__ A, int64_t lda,
-                                  TA* __restrict__ Acur) {
-  // one workgroup per column, rows j..n-1
+                                  TA* __restrict__ Acur, Ctrl* ctrl) {
+  // one workgroup per column, rows j..n-1; the largest magnitude read goes
+  // to ctrl->max_abs_a (one atomic per wave)
+  double mx = 0.0;
   for (int64_t j = blockIdx.x; j < n; j += gridDim.x) {
-    for (int64_t i = j + threadIdx.x; i < n; i += blockDim.x) Acur[i + j * n] = (TA)A[i + j * lda];
+    for (int64_t i = j + threadIdx.x; i < n; i += blockDim.x) {
+      const double v = A[i + j * lda];
+      Acur[i + j * n] = (TA)v;
+      mx = fmax(mx, fabs(v));   // fmax drops a NaN; non-finite input is caught by the sketch check
+    }
   }
+  mx = fmax(mx, xchg<1>(mx));
+  mx = fmax(mx, xchg<2>(mx));
+  mx = fmax(mx, xchg<4>(mx));
+  mx = fmax(mx, xchg<8>(mx));
+  mx = fmax(mx, xchg<16>(mx));
+  mx = fmax(mx, xchg<32>(mx));
+  if ((threadIdx.x & 63) == 0 && mx > 0.0)
+    atomicMax(&ctrl->max_abs_a, (unsigned long long)__double_as_longlong(mx));
 }
 
 __global__ void check_finite_kernel(int64_t n, const double* __restrict__ B, int lpad, int l,
@@ -163,14 +177,15 @@ unsigned grid1d(int64_t total, int threads = 256, int64_t cap = 65536) {
 }  // namespace
 
 void launch_copy_lower(int64_t n, const double* A, int64_t lda, void* Acur, int prec,
-                       hipStream_t s) {
+                       Ctrl* ctrl, hipStream_t s) {
   if (n <= 0) return;
   const dim3 grid((unsigned)std::min<int64_t>(n, 65536));
   if (prec == kPrecF64)
     hipLaunchKernelGGL(copy_lower_kernel<double>, grid, dim3(256), 0, s, n, A, lda,
-                       (double*)Acur);
+                       (double*)Acur, ctrl);
   else
-    hipLaunchKernelGGL(copy_lower_kernel<float>, grid, dim3(256), 0, s, n, A, lda, (float*)Acur);
+    hipLaunchKernelGGL(copy_lower_kernel<float>, grid, dim3(256), 0, s, n, A, lda, (float*)Acur,
+                       ctrl);
 }
 
 void launch_sketch(int64_t n, const void* Acur, int prec, int64_t ld, const double* OmT,

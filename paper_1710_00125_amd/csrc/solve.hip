@@ -19,8 +19,8 @@
 namespace rcp {
 namespace {
 
-constexpr int kBlk = 64;
-constexpr int kMaxRhs = 8;
+constexpr int kBlk = kSolveBlk;
+constexpr int kMaxRhs = kSolveMaxRhs;
 
 // ---------------------------------------------------------------------------
 // L(i, c) for the final order: row i of L is row P[i] (original index) of
@@ -58,6 +58,34 @@ __global__ void __launch_bounds__(256) finalize_L_kernel(int64_t n, const TL* __
     else v = tile[ii][cc];
     L[i + c * n] = v;
   }
+}
+
+// ctrl->max_abs_d <- max over the entries of D (diagonal, and the
+// off-diagonal entry of every 2x2 block); one atomic per wave
+__global__ void max_abs_d_kernel(int64_t n, const double* __restrict__ D,
+                                 const int8_t* __restrict__ ipiv, Ctrl* ctrl) {
+  double mx = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    mx = fmax(mx, fabs(D[i]));
+    if (ipiv[i] == 2) mx = fmax(mx, fabs(D[n + i]));
+  }
+  mx = fmax(mx, xchg<1>(mx));
+  mx = fmax(mx, xchg<2>(mx));
+  mx = fmax(mx, xchg<4>(mx));
+  mx = fmax(mx, xchg<8>(mx));
+  mx = fmax(mx, xchg<16>(mx));
+  mx = fmax(mx, xchg<32>(mx));
+  if ((threadIdx.x & 63) == 0 && mx > 0.0)
+    atomicMax(&ctrl->max_abs_d, (unsigned long long)__double_as_longlong(mx));
+}
+
+__global__ void zero_words_kernel(unsigned int* p, int count) {
+  for (int i = threadIdx.x; i < count; i += blockDim.x) p[i] = 0u;
+}
+
+__global__ void set_int_kernel(int* p, int v) {
+  if (threadIdx.x == 0) *p = v;
 }
 
 __global__ void find_zero_pivot_kernel(int64_t n, const double* __restrict__ D,
@@ -407,6 +435,12 @@ void launch_finalize_L(int64_t n, const void* Lwork, const int64_t* P, const int
                        P, ipiv, (double*)L);
 }
 
+void launch_max_abs_d(int64_t n, const double* D, const int8_t* ipiv, Ctrl* ctrl,
+                      hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(max_abs_d_kernel, dim3(grid1d(n)), dim3(256), 0, s, n, D, ipiv, ctrl);
+}
+
 void launch_find_zero_pivot(int64_t n, const double* D, const int8_t* ipiv, int* out,
                             hipStream_t s) {
   if (n <= 0) return;
@@ -414,9 +448,14 @@ void launch_find_zero_pivot(int64_t n, const double* D, const int8_t* ipiv, int*
 }
 
 size_t solve_sync_words(int64_t) { return 2; }
-size_t solve_work_doubles(int64_t n, int64_t nrhs) {
-  const int64_t nb = (n + kBlk - 1) / kBlk;
-  return (size_t)(3 * n * std::min<int64_t>(kMaxRhs, nrhs) + nb * kBlk * kBlk);
+
+void launch_zero_words(unsigned int* p, int count, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, s, p, count);
+}
+
+void launch_set_int(int* p, int v, hipStream_t s) {
+  hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, s, p, v);
 }
 
 void launch_solve(int64_t n, const void* L, int l_f32, const double* D, const int8_t* ipiv,
@@ -436,7 +475,7 @@ void launch_solve(int64_t n, const void* L, int l_f32, const double* D, const in
     constexpr bool LO = decltype(lower_tag)::value;
     const void* kern = (const void*)trsv_chain_kernel<TL, NR, LO>;
     hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)trsv_lds());
-    hipMemsetAsync(sync, 0, sizeof(unsigned int), s);   // ticket counter
+    launch_zero_words(sync, 1, s);   // ticket counter
     hipLaunchKernelGGL((trsv_chain_kernel<TL, NR, LO>), dim3((unsigned)nb), dim3(256), trsv_lds(),
                        s, n, nr, (const TL*)L, (const double*)Linv, Yc, Zc, sync);
   };

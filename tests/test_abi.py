@@ -125,3 +125,53 @@ def test_column_major_view_is_passed_without_copy():
     cm2 = _colmajor(row_major)
     assert cm2.data_ptr() != row_major.data_ptr() and cm2.is_contiguous()
     assert torch.equal(cm2.t(), row_major)    # memory[i + j n] = A[i, j]
+
+
+def test_launch_shape_dispatch_without_gpu():
+    # which selection kernel and grid each shape gets (host logic only)
+    import paper_1710_00125_amd as pkg
+    if not os.path.exists(pkg.lib_path()):
+        pytest.skip("librcp.so not built")
+    sh = pkg.rcp_launch_shape(16384, 128, 16, 256)
+    assert (sh["select_grid"], sh["select_cols"], sh["select_regs"]) == (256, 64, 1)
+    assert (sh["panel_grid"], sh["panel_rows"], sh["supported"]) == (256, 64, 1)
+    # 33..64 columns per workgroup for every trailing order in (8192, 16384]
+    assert pkg.rcp_launch_shape(9000, 128, 16, 256)["select_cols"] == 36
+    # one more column than the register slab holds, or a taller sketch: LDS
+    assert pkg.rcp_launch_shape(16385, 128, 16, 256)["select_regs"] == 0
+    assert pkg.rcp_launch_shape(1300, 128, 24, 256)["select_regs"] == 0
+    assert pkg.rcp_launch_shape(1300, 128, 16, 256)["select_regs"] == 1
+    # the LDS budget bounds the order
+    assert pkg.rcp_launch_shape(20000, 128, 16, 256)["supported"] == 1
+    assert pkg.rcp_launch_shape(30000, 128, 16, 256)["supported"] == 0
+    assert pkg.rcp_launch_shape(16384, 128, 200, 256)["supported"] == 0
+    # grid limits give the large per-workgroup shapes at small orders
+    try:
+        pkg.rcp_set_grid_limit(32, 32)
+        sh = pkg.rcp_launch_shape(2048, 128, 16, 256)
+        assert (sh["select_grid"], sh["select_cols"], sh["select_regs"]) == (32, 64, 1)
+        assert (sh["panel_grid"], sh["panel_rows"]) == (32, 64)
+        pkg.rcp_set_grid_limit(24, 0)
+        sh = pkg.rcp_launch_shape(2048, 128, 16, 256)
+        assert (sh["select_cols"], sh["select_regs"], sh["supported"]) == (86, 0, 1)
+        pkg.rcp_set_grid_limit(8, 8)
+        assert pkg.rcp_launch_shape(2048, 128, 16, 256)["supported"] == 0
+    finally:
+        pkg.rcp_set_grid_limit(0, 0)
+    lib = pkg.load()
+    info = pkg._binding._LaunchInfo()
+    assert lib.rcp_launch_shape(0, 128, 16, 256, ctypes.byref(info)) == -1
+    assert lib.rcp_launch_shape(16, 129, 16, 256, ctypes.byref(info)) == -2
+    assert lib.rcp_launch_shape(16, 128, 385, 256, ctypes.byref(info)) == -3
+    assert lib.rcp_launch_shape(16, 128, 16, 0, ctypes.byref(info)) == -4
+    assert lib.rcp_launch_shape(16, 128, 16, 256, None) == -5
+    assert lib.rcp_set_grid_limit(-1, 0) == -1 and lib.rcp_set_grid_limit(0, -1) == -2
+
+
+def test_release_without_device_work():
+    # nothing allocated yet: releasing is a no-op and may be repeated
+    import paper_1710_00125_amd as pkg
+    if not os.path.exists(pkg.lib_path()):
+        pytest.skip("librcp.so not built")
+    assert pkg.rcp_release() == 0
+    assert pkg.rcp_release() == 0

@@ -207,3 +207,58 @@ def test_nonfinite_input(rcp, bad):
     f = rcp.rcp_factor(torch.from_numpy(upper).to(_dev()), b, p, seed)
     ref = orcp.factor(A, b, p, seed=seed)
     assert np.array_equal(f.perm.cpu().numpy(), ref.perm)
+
+
+# The persistent kernels' other shapes at sizes the oracle checks in
+# seconds.  The selection keeps up to 64 sketch columns per workgroup in
+# registers (l <= 144) and more, or taller sketches, in LDS; at full size
+# (n = 16384, b = 128, p = 16) every workgroup owns 33..64 columns and 33..64
+# panel rows in the first half of the factorization.  Bounding the grids
+# gives the same per-workgroup shapes at n = 2048.
+@pytest.mark.parametrize("n,b,p,limits,regs,cols", [
+    (2048, 128, 16, (32, 32), 1, 64),    # register slab, 64 columns; panel rows 64
+    (2048, 128, 16, (48, 48), 1, 43),    # register slab, ragged 43 columns
+    (1300, 128, 24, (0, 0), 0, 32),      # l = 152 > 144: LDS slab
+    (2048, 128, 16, (24, 0), 0, 86),     # more than 64 columns: LDS slab
+])
+def test_factor_selection_shapes_match_oracle(rcp, n, b, p, limits, regs, cols):
+    seed = 60 + n % 7
+    _say(f"factor shapes n={n} b={b} p={p} grid limits={limits}")
+    shape = None
+    try:
+        rcp.rcp_set_grid_limit(*limits)
+        shape = rcp.rcp_launch_shape(n, b, p)
+        assert shape["supported"] == 1
+        assert shape["select_regs"] == regs and shape["select_cols"] == cols, shape
+        A = gen.householder_spectrum(n, seed, cond=1e6, nrefl=64)
+        _factor_case(rcp, A, b, p, seed)
+    finally:
+        rcp.rcp_set_grid_limit(0, 0)
+
+
+def test_factor_reports_pivoting_statistics(rcp):
+    """max|A|, max|L|, max|D| and rho_D in the call's statistics equal the
+    same quantities computed from the inputs and outputs; the threshold
+    margins are positive and no near-tie is reported for this input."""
+    import torch
+    n, b, p, seed = 700, 64, 10, 71
+    _say(f"statistics n={n}")
+    A = gen.kkt(n, (3 * n) // 4, seed, nrefl=64)
+    f = rcp.rcp_factor(torch.from_numpy(A).to(_dev()), b, p, seed)
+    st = rcp.rcp_get_stats()
+    L, D, ipiv = f.L.cpu().numpy(), f.D.cpu().numpy(), f.ipiv.cpu().numpy()
+    amax = np.max(np.abs(np.tril(A)))
+    lmax = np.max(np.abs(np.tril(L, -1)))
+    dmax = max(np.max(np.abs(D[:n])), np.max(np.abs(D[n:][ipiv == 2]), initial=0.0))
+    assert st["max_abs_a"] == amax
+    assert st["max_abs_l"] == lmax
+    assert st["max_abs_d"] == dmax
+    assert st["rho_d"] == pytest.approx(dmax / amax, rel=1e-15)
+    assert st["n2x2"] == int(np.sum(ipiv == 2))
+    assert 0.0 < st["min_margin"] < np.inf and st["near_ties"] == 0
+    ref = orcp.factor(A, b, p, seed=seed)
+    # the oracle's smallest threshold-test margin, relative to lambda
+    marg = [min([abs(abs(e["akk"]) - orcp.ALPHA * e["lam"])] +
+                ([abs(abs(e["arr"]) - orcp.ALPHA * e["lam"])] if e["arr"] is not None else []))
+            / e["lam"] for e in ref.log if e["kind"] == "sbkp" and e["lam"] > 0]
+    assert st["min_margin"] == pytest.approx(min(marg), rel=1e-6)
