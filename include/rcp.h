@@ -193,6 +193,27 @@ int rcp_factor_mp(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p,
 int rcp_solve_mp(int64_t n, const float* L, const double* D, const int8_t* ipiv,
                  const int64_t* perm, int64_t nrhs, double* B, int64_t ldb);
 
+/* Largest order rcp_solve_noalloc accepts. */
+#define RCP_NOALLOC_MAX_N 16384
+
+/* rcp_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, kernels and results as rcp_solve (FP64 L of rcp_factor),
+ * but the scratch (about 11.5 MB: right-hand-side blocks, the inverted
+ * 64 x 64 diagonal blocks of L and the chained solves' sync words) is one
+ * fixed device array inside the library, of the size needed for order
+ * RCP_NOALLOC_MAX_N, held by every device the library runs on until the
+ * process ends.  No hipMalloc, hipFree or other allocating call is made, and
+ * no timing events are recorded (ms_solve is not updated).  Every call on a
+ * device shares that device's array: calls that overlap on one device (from
+ * several host threads, or on several streams) race and must be serialised
+ * by the caller.  The sync words are cleared by a kernel at the start of
+ * each call.
+ * Returns as rcp_solve, and RCP_EUNSUPPORTED (nothing written) when
+ * n > RCP_NOALLOC_MAX_N. */
+int rcp_solve_noalloc(int64_t n, const double* L, const double* D, const int8_t* ipiv,
+                      const int64_t* perm, int64_t nrhs, double* B, int64_t ldb);
+
 /* Result of rcp_solve_ir. */
 typedef struct rcp_ir_result {
   int32_t outer;   /* residual evaluations after the first solve            */

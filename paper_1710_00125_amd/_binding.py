@@ -16,6 +16,7 @@ RCP_ENOCONV = -1004
 RCP_EABORT = -1005
 RCP_PREC_FP32 = 1
 RCP_PREC_BF16X3 = 2
+RCP_NOALLOC_MAX_N = 16384
 
 
 class RCPError(RuntimeError):
@@ -73,6 +74,9 @@ _SIGS = {
     "rcp_solve": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                  ctypes.c_void_p, ctypes.c_int64]),
+    "rcp_solve_noalloc": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                         ctypes.c_void_p, ctypes.c_int64]),
     "rcp_factor_mp": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
                                      ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
                                      ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
@@ -291,6 +295,25 @@ def rcp_solve(f, B):
     code = getattr(load(), fn)(n, _ptr(Lcm), _ptr(f.D), _ptr(f.ipiv), _ptr(f.perm), nrhs,
                                _ptr(Bcm), max(1, n))
     _check(fn, code)
+    X = Bcm.t()
+    return X[:, 0] if vec else X
+
+
+def rcp_solve_noalloc(f, B):
+    """rcp_solve on the library's fixed scratch array (no device allocation
+    inside the call; FP64 factors of rcp_factor, n <= RCP_NOALLOC_MAX_N).
+    The right-hand sides are copied into a fresh column-major tensor here,
+    as in rcp_solve; a caller that must not allocate at all calls the C entry
+    point directly on buffers it already holds."""
+    assert not f.precision, "rcp_solve_noalloc takes the FP64 factors of rcp_factor"
+    Bcm, vec = _rhs_cm(B)
+    nrhs, n = Bcm.shape
+    Lcm = f.L.t()
+    assert Lcm.is_contiguous()
+    rcp_set_stream()
+    code = load().rcp_solve_noalloc(n, _ptr(Lcm), _ptr(f.D), _ptr(f.ipiv), _ptr(f.perm), nrhs,
+                                    _ptr(Bcm), max(1, n))
+    _check("rcp_solve_noalloc", code)
     X = Bcm.t()
     return X[:, 0] if vec else X
 

@@ -149,6 +149,8 @@ void launch_solve(int64_t n, const void* L, int l_f32, const double* D, const in
                   const int64_t* perm, int64_t nrhs, double* B, int64_t ldb, double* work,
                   unsigned int* sync, hipStream_t s);
 size_t solve_sync_words(int64_t n);
+// upper bound of solve_sync_words over every n
+constexpr size_t kSolveSyncWordsMax = 2;
 // doubles of solve scratch: three n x min(nrhs, 8) blocks of right-hand
 // sides and the inverses of the 64 x 64 diagonal blocks of L
 constexpr int kSolveBlk = 64;

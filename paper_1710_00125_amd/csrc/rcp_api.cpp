@@ -621,6 +621,34 @@ int solve_impl(int64_t n, const void* L, int l_f32, const double* D, const int8_
   return solve_core(n, L, l_f32, D, ipiv, perm, nrhs, B, ldb, Y, sync, zp, g_prof);
 }
 
+// ---- the solve without device allocation (rcp_solve_noalloc)
+// Its scratch is one fixed array per device, sized for order
+// RCP_NOALLOC_MAX_N: the right-hand-side blocks and diagonal-block inverses
+// of the chained solves, then the sync words and the zero-pivot word.  In
+// host code `scratch` only names the symbol; kernels get the device address
+// that hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoAllocWork = solve_work_doubles(RCP_NOALLOC_MAX_N, kSolveMaxRhs);
+constexpr size_t kNoAllocSyncOff = kNoAllocWork;        // in doubles, 256-byte aligned
+constexpr size_t kNoAllocZpOff = kNoAllocSyncOff + 32;  // after 64 sync words
+constexpr size_t kNoAllocDoubles = kNoAllocZpOff + 32;
+static_assert(kNoAllocSyncOff % 32 == 0, "sync words start on a 256-byte boundary");
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+constexpr int kMaxDevices = 64;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of this device's scratch array, looked up once per device
+// (with that device current); nullptr if the lookup fails
+double* noalloc_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 extern "C" {
@@ -663,6 +691,24 @@ int rcp_solve(int64_t n, const double* L, const double* D, const int8_t* ipiv,
 int rcp_solve_mp(int64_t n, const float* L, const double* D, const int8_t* ipiv,
                  const int64_t* perm, int64_t nrhs, double* B, int64_t ldb) {
   return solve_impl(n, L, 1, D, ipiv, perm, nrhs, B, ldb);
+}
+
+// rcp_solve on the library's fixed per-device scratch array: the same
+// kernels with the same arguments, no allocation and no timing events.
+int rcp_solve_noalloc(int64_t n, const double* L, const double* D, const int8_t* ipiv,
+                      const int64_t* perm, int64_t nrhs, double* B, int64_t ldb) {
+  const int bad = solve_args(n, L, D, ipiv, perm, nrhs, B, ldb);
+  if (bad) return bad;
+  if (n > RCP_NOALLOC_MAX_N) return RCP_EUNSUPPORTED;
+  if (n == 0 || nrhs == 0) return 0;
+  int dev = 0;
+  RCP_CHECK(hipGetDevice(&dev));
+  double* base = noalloc_scratch(dev);
+  if (!base) return RCP_EDEVICE;
+  static_assert(kSolveSyncWordsMax <= 64, "sync words fit their slot");
+  return solve_core(n, L, 0, D, ipiv, perm, nrhs, B, ldb, base,
+                    (unsigned int*)(base + kNoAllocSyncOff), (int*)(base + kNoAllocZpOff),
+                    false);
 }
 
 // GMRES-IR: x0 = M^{-1} b; repeat { r = b - A x (FP64); stop if the

@@ -447,7 +447,7 @@ void launch_find_zero_pivot(int64_t n, const double* D, const int8_t* ipiv, int*
   hipLaunchKernelGGL(find_zero_pivot_kernel, dim3(grid1d(n)), dim3(256), 0, s, n, D, ipiv, out);
 }
 
-size_t solve_sync_words(int64_t) { return 2; }
+size_t solve_sync_words(int64_t) { return kSolveSyncWordsMax; }
 
 void launch_zero_words(unsigned int* p, int count, hipStream_t s) {
   if (count <= 0) return;

@@ -57,6 +57,11 @@ def test_argument_errors_without_gpu():
     assert lib.rcp_solve(4, one, one, one, one, 1, one, 3) == -8
     assert lib.rcp_solve(4, one, one, one, one, -1, one, 4) == -6
     assert lib.rcp_solve(0, null, null, null, null, 1, null, 1) == 0
+    assert lib.rcp_solve_noalloc(-1, null, null, null, null, 1, null, 1) == -1
+    assert lib.rcp_solve_noalloc(4, one, one, one, one, 1, one, 3) == -8
+    big = pkg.RCP_NOALLOC_MAX_N + 1   # beyond the fixed scratch array
+    assert lib.rcp_solve_noalloc(big, one, one, one, one, 1, one, big) == -1003
+    assert lib.rcp_solve_noalloc(0, null, null, null, null, 1, null, 1) == 0
     assert lib.rcp_omega(0, -1, 4, null) == -2
     assert lib.rcp_omega(0, 2, -4, null) == -3
     assert lib.rcp_omega(0, 2, 4, null) == -4
