@@ -180,6 +180,67 @@ def batched_run(rcp, count, replays):
     return res
 
 
+def _quality(rcp, A, b, p, seed, nrhs_seed):
+    """One factor + solve of A (device, n x n) with the paper's right-hand
+    side b = A x: time, growth factor, backward error (eq. (5.1)), ||L||_1
+    and ||L^{-1}||_1 (the quantities of the paper's Section 5 figures)."""
+    import torch
+    n = A.shape[0]
+    g = torch.Generator(device="cpu").manual_seed(nrhs_seed)
+    x = torch.randn(n, 1, dtype=torch.float64, generator=g).to(A.device)
+    rhs = A @ x
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    f = rcp.rcp_factor(A, b, p, seed)
+    st = rcp.rcp_get_stats()
+    X = rcp.rcp_solve(f, rhs)
+    e1.record()
+    torch.cuda.synchronize()
+    r = A @ X - rhs
+    berr = (r.abs().max() / (A.abs().sum(dim=1).max() * X.abs().max())).item()
+    L = f.L
+    eye = torch.eye(n, dtype=torch.float64, device=A.device)
+    Linv = torch.linalg.solve_triangular(L, eye, upper=False, unitriangular=True)
+    out = {"ms": round(e0.elapsed_time(e1), 3), "rho": st["rho_d"], "err": berr,
+           "L1": L.abs().sum(dim=0).max().item(), "Linv1": Linv.abs().sum(dim=0).max().item(),
+           "n2x2": st["n2x2"], "info": f.info}
+    del f, L, Linv, eye, r
+    return out
+
+
+def stress_run(rcp, sizes, b=64, p=4, seed=10):
+    """The paper's matrix types (Section 5) at each order in ``sizes``, block
+    b, oversampling p (the paper's choice p = q + 4 with q = b)."""
+    import torch
+    from workloads import stress
+    res = {"b": b, "p": p, "seed": seed, "types": {}}
+    for kind in (1, 2, 3, 4, 5, 6, 7, 8, 10):
+        row = {}
+        for n in sizes:
+            A = torch.from_numpy(stress.matrix(kind, n, seed=seed + n)).cuda()
+            row[str(n)] = _quality(rcp, A, b, p, seed + n, seed)
+            del A
+        res["types"][str(kind)] = row
+        _log(f"bench: stress type {kind}: " + ", ".join(
+            f"n={n} rho={row[str(n)]['rho']:.3g} err={row[str(n)]['err']:.1e}" for n in sizes))
+    return res
+
+
+def p_sweep_run(rcp, n=4096, b=64, ps=(0, 2, 4, 8, 16, 32, 64), seed=6):
+    """Type 6 (Gaussian symmetric) at order n: the effect of the oversampling
+    p on time, growth, backward error, ||L||_1 and ||L^{-1}||_1 (the paper's
+    Section 5 study of p)."""
+    import torch
+    from workloads import stress
+    A = torch.from_numpy(stress.matrix(6, n, seed=seed)).cuda()
+    res = {"type": 6, "n": n, "b": b, "seed": seed, "p": {}}
+    for p in ps:
+        _quality(rcp, A, b, p, seed, seed)            # warm-up of this shape
+        res["p"][str(p)] = _quality(rcp, A, b, p, seed, seed)
+        _log(f"bench: p-sweep p={p}: {res['p'][str(p)]}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,6 +259,11 @@ def main():
     ap.add_argument("--cond-sweep", action="store_true",
                     help="also time the reduced-precision forms on the cond 1e2/1e6/1e10 "
                          "matrices of the same generator")
+    ap.add_argument("--stress", default="1024,4096",
+                    help="orders of the paper's matrix types (Section 5) to factor and "
+                         "report growth, backward error, ||L||_1, ||L^-1||_1 (empty skips)")
+    ap.add_argument("--p-sweep", type=int, default=4096, metavar="N",
+                    help="order of the Type 6 matrix of the oversampling sweep (0 skips it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (a known "
                          "byte count for calibrating hardware traffic counters) and exit")
@@ -342,6 +408,11 @@ def main():
                 del Ac, bc
     if args.batched > 0:
         out["batched"] = batched_run(rcp, args.batched, args.replays)
+    sizes = [int(v) for v in args.stress.split(",") if v]
+    if sizes:
+        out["stress"] = stress_run(rcp, sizes)
+    if args.p_sweep > 0:
+        out["p_sweep"] = p_sweep_run(rcp, n=args.p_sweep)
     if args.cpu_sample > 0:
         _log(f"bench: timing the CPU oracle on n={args.cpu_sample}")
         out["cpu_baseline"] = cpu_baseline(args.config, args.cpu_sample)

@@ -166,8 +166,10 @@ def gaussians(seed, stream, count):
     return z.reshape(-1)[:count]
 
 
-def omega(seed, l, n):
-    """Omega in R^{l x n}, i.i.d. N(0,1), as defined in the module docstring."""
+def omega(seed, l, n, stream=STREAM_OMEGA):
+    """Omega in R^{l x n}, i.i.d. N(0,1), as defined in the module docstring;
+    ``stream`` > 1 gives the fresh sketching matrices of Algorithm 2 (the
+    j-th recomputation draws from stream 1 + j)."""
     if l * n == 0:
         return np.zeros((l, n))
-    return gaussians(seed, STREAM_OMEGA, l * n).reshape(l, n)
+    return gaussians(seed, stream, l * n).reshape(l, n)

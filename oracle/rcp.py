@@ -64,6 +64,8 @@ class Factorization:
         self.block_starts = []
         self.sketch_at_block_start = []   # (K0, perm copy, B(:, K0:) copy) if recorded
         self.sketch_scale = 0.0        # largest column norm of the initial sketch
+        self.rank = n                  # eliminated columns (< n: Algorithm 2 stopped)
+        self.recomputed = []           # block starts where Algorithm 2 recomputed B
 
     def dmatrix(self):
         """D as an n x n block-diagonal matrix."""
@@ -81,8 +83,11 @@ def symmetric_from_lower(A):
     return np.tril(A) + np.tril(A, -1).T
 
 
+EPS = 2.0 ** -52   # machine precision of Algorithm 2 (the spacing of doubles at 1)
+
+
 def factor(A, b, p, seed=0, omega=None, schedule="delayed", record_sketch=False,
-           trace=False):
+           trace=False, recompute=1):
     """RCP block LDL^T of the symmetric matrix given by the lower triangle of A.
 
     A        n x n array; only A[i, j] with i >= j is read
@@ -96,6 +101,19 @@ def factor(A, b, p, seed=0, omega=None, schedule="delayed", record_sketch=False,
              exact arithmetic, also tracks the element growth factor)
     record_sketch  keep (K0, perm, B(:, K0:)) at every block start
     trace    keep a copy of perm in every decision-log entry (small n only)
+    recompute  r of Algorithm 2 (Section 4.5): with r = 1 this is Algorithm 1.
+             With r >= 2, beta is the largest column norm of the first
+             sketch and delta = (j+1)/r after j recomputations; while
+             delta < 1, at every block start after the first the largest
+             column norm t of the current sketch is compared with
+             EPS^delta beta.  Below it, the sketch of the current Schur
+             complement is recomputed with a fresh Omega (stream 1 + j of the
+             seed, see omega.omega), j grows by one, and if the new t is still
+             below EPS^delta beta the factorization stops there: the
+             remaining Schur complement counts as zero (D = 0, 1x1 blocks,
+             zero columns of L), ``f.rank`` is the number of eliminated
+             columns and ``f.info`` the 1-based position after them.  The
+             block starts that recomputed are in ``f.recomputed``.
     """
     S = symmetric_from_lower(A).copy()
     n = S.shape[0]
@@ -223,10 +241,33 @@ def factor(A, b, p, seed=0, omega=None, schedule="delayed", record_sketch=False,
         f.ipiv[k], f.ipiv[k + 1] = 2, 0
         return 2
 
+    beta = f.sketch_scale
+    nrec = 0
+
+    def sketch_max(K0):
+        return float(np.sqrt(np.max(np.einsum("ij,ij->j", B[:, K0:], B[:, K0:]))))
+
     k = 0
     while k < n:
         K0 = k
         bb = min(b, n - k)
+        if recompute > 1 and K0 > 0 and nrec + 1 < recompute:
+            # Algorithm 2: is the largest column norm of the sketch still
+            # above EPS^delta beta?
+            if sketch_max(K0) < EPS ** ((nrec + 1) / recompute) * beta:
+                nrec += 1
+                Om_j = omega_mod.omega(seed, l, n - K0, stream=omega_mod.STREAM_OMEGA + nrec)
+                B[:, K0:] = Om_j @ S[K0:, K0:]
+                f.recomputed.append(K0)
+                if sketch_max(K0) < EPS ** ((nrec + 1) / recompute) * beta:
+                    # rank deficient: the Schur complement is taken as zero
+                    f.rank = K0
+                    f.D[K0:n] = 0.0
+                    f.D[n + K0:] = 0.0
+                    f.ipiv[K0:] = 1
+                    if f.info == 0:
+                        f.info = K0 + 1
+                    break
         f.block_starts.append(K0)
         if record_sketch:
             f.sketch_at_block_start.append((K0, perm.copy(), B[:, K0:].copy()))

@@ -11,11 +11,11 @@ with the next block's selection).
   * householder16384 (n = 16384, b = 128, p = 16, cond 1e6, the headline):
     against the oracle's run stored in tests/golden/householder16384_oracle.npz
     (written by tests/golden/make_householder16384.py, which calls only the
-    oracle): the permutation and the block pattern bit-exact on every
-    position that no near-tie decides (the stored prefix: before the first
-    decision whose gap is <= 1e-9 max|A|), D and the stored rows of L within
-    1e3 n u max(1, |oracle|) there, and the solution within cond * 1e-13 of
-    the oracle's; then properties that hold at any size: perm a permutation;
+    oracle): the permutation and the block pattern bit-exact on all n
+    positions (the measured result, also past the stored near-tie prefix,
+    the positions before the first decision whose gap is <= 1e-9 max|A|),
+    D and the stored rows of L within 1e3 n u max(1, |oracle|), and the
+    solution within cond * 1e-13 of the oracle's; then properties that hold at any size: perm a permutation;
     ipiv a valid pattern; L unit lower with L(i+1, i) = 0 inside every 2x2
     block; 4096 sampled entries (i >= j) of P A P^T - L D L^T each within
     50 n u ||A||_inf (the bound of the parity tests' norm check); solve
@@ -131,16 +131,23 @@ def test_householder16384_full_size(rcp):
     first = int(np.argmax(perm != gold["perm"])) if np.any(perm != gold["perm"]) else n
     _say(f"  oracle near-tie prefix {pre}; first differing position {first}; "
          f"GPU threshold margin min {st['min_margin']:.2e}, near-ties {st['near_ties']}")
-    assert pre > n // 2      # the comparison below covers most of the sequence
+    assert pre > n // 2
     assert np.array_equal(perm[:pre], gold["perm"][:pre])
     assert np.array_equal(ipiv[:pre], gold["ipiv"][:pre])
+    # measured: the GPU takes every decision as the oracle does, also the
+    # ones after the first decision the conservative near-tie reading flags
+    # (absolute margin <= 1e-9 max|A|, at position 9105), so the whole
+    # sequence is compared
+    idiff = np.nonzero(ipiv != gold["ipiv"])[0]
+    m = min(first, int(idiff[0]) if idiff.size else n)
+    assert m == n, f"pivots differ from the oracle's from position {m}"
     tol = 1e3 * n * U
     Dg = gold["D"]
-    assert np.all(np.abs(D[:pre] - Dg[:pre]) <= tol * np.maximum(1.0, np.abs(Dg[:pre])))
-    assert np.all(np.abs(D[n:n + pre] - Dg[n:n + pre]) <=
-                  tol * np.maximum(1.0, np.abs(Dg[n:n + pre])))
+    assert np.all(np.abs(D[:m] - Dg[:m]) <= tol * np.maximum(1.0, np.abs(Dg[:m])))
+    assert np.all(np.abs(D[n:n + m] - Dg[n:n + m]) <=
+                  tol * np.maximum(1.0, np.abs(Dg[n:n + m])))
     for r, row in zip(gold["L_row_pos"], gold["L_rows"]):
-        if r < pre:
+        if r < m:
             assert np.all(np.abs(L[r] - row) <= tol * np.maximum(1.0, np.abs(row))), r
     # a permutation and a valid block pattern
     assert np.array_equal(np.sort(perm), np.arange(n))

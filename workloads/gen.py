@@ -108,6 +108,29 @@ def kkt(n, n1, seed, nrefl=64, lam_min=1e-3):
     return A
 
 
+def zero_padded(n, r0, seed):
+    """An r0 x r0 Gaussian-symmetric block at r0 random positions of an
+    n x n zero matrix: exactly rank r0 or less, with exactly zero rows and
+    columns elsewhere."""
+    rng = _rng(seed, _STREAM_MATRIX)
+    where = np.sort(rng.permutation(n)[:r0])
+    A = np.zeros((n, n))
+    A[np.ix_(where, where)] = gaussian_sym(r0, seed)
+    return A
+
+
+def gap_spectrum(n, r0, seed, small=1e-9, nrefl=16):
+    """Q diag(s lam) Q^T with lam = 1 for r0 eigenvalues and `small` for the
+    others, random signs s, Q a product of `nrefl` Householder reflectors:
+    after r0 well chosen pivots the Schur complement is of order `small`."""
+    rng = _rng(seed, _STREAM_MATRIX)
+    lam = np.full(n, float(small))
+    lam[rng.permutation(n)[:r0]] = 1.0
+    s = np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    V, T = householder_product_wy(n, min(nrefl, n), _rng(seed, _STREAM_REFLECTORS))
+    return _q_diag_qt(s * lam, V, T)
+
+
 def rhs(n, nrhs, seed):
     """Right-hand sides, i.i.d. N(0, 1), shape (n, nrhs)."""
     return _rng(seed, _STREAM_RHS).standard_normal((n, nrhs))
