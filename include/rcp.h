@@ -75,6 +75,10 @@ typedef struct rcp_stats {
                               (a_kk always, a_rr in cases (2)/(3)); +inf if
                               no test was evaluated                           */
   int64_t near_ties;       /* threshold tests with that margin <= 1e-9       */
+  /* Algorithm 2 (rcp_set_recompute) */
+  int64_t recomputes;      /* sketches recomputed from the Schur complement   */
+  int64_t rank;            /* columns eliminated (n unless Algorithm 2 found
+                              the Schur complement negligible and stopped)    */
 } rcp_stats;
 
 /* Launch shape the factorization would use for the first (largest) block
@@ -105,6 +109,21 @@ int rcp_set_profiling(int32_t on);
  * it (on = 0; every kernel then runs alone, which is how per-kernel times
  * are measured in isolation).  Results are identical either way.  Returns 0. */
 int rcp_set_overlap(int32_t on);
+
+/* Algorithm 2 of the paper (Section 4.5) for later rcp_factor and
+ * rcp_factor_mp calls: r = 1 (the default) is Algorithm 1.  With r >= 2,
+ * beta is the largest column norm of the first sketch and delta = (j+1)/r
+ * after j recomputations.  While delta < 1, at the start of every block after
+ * the first the largest column norm t of the current sketch is compared
+ * with EPS^delta beta (EPS = 2^-52); below it, the sketch of the current
+ * Schur complement is recomputed with a fresh Omega (Philox key (seed,
+ * 1 + j), see rcp_omega), j grows by one, and if the new t is still below
+ * EPS^delta beta the factorization stops: the remaining Schur complement
+ * counts as zero, D and the multipliers of the remaining positions are zero,
+ * their blocks 1x1, and the call returns rank + 1 (the 1-based position of
+ * the first zero pivot; rcp_stats.rank holds the eliminated columns).  The
+ * check reads one number back per block.  Returns 0, or -1 for r < 1. */
+int rcp_set_recompute(int32_t r);
 
 /* Copy the statistics of the last call into *st.  Returns 0, -1 if st is NULL. */
 int rcp_get_stats(rcp_stats* st);

@@ -36,7 +36,8 @@ class _Stats(ctypes.Structure):
                 ("flops_update", ctypes.c_double), ("bytes_update", ctypes.c_double),
                 ("max_abs_a", ctypes.c_double), ("max_abs_l", ctypes.c_double),
                 ("max_abs_d", ctypes.c_double), ("rho_d", ctypes.c_double),
-                ("min_margin", ctypes.c_double), ("near_ties", ctypes.c_int64)]
+                ("min_margin", ctypes.c_double), ("near_ties", ctypes.c_int64),
+                ("recomputes", ctypes.c_int64), ("rank", ctypes.c_int64)]
 
 
 class _LaunchInfo(ctypes.Structure):
@@ -60,6 +61,7 @@ _SIGS = {
     "rcp_set_stream": (ctypes.c_int, [ctypes.c_void_p]),
     "rcp_set_profiling": (ctypes.c_int, [ctypes.c_int32]),
     "rcp_set_overlap": (ctypes.c_int, [ctypes.c_int32]),
+    "rcp_set_recompute": (ctypes.c_int, [ctypes.c_int32]),
     "rcp_get_stats": (ctypes.c_int, [ctypes.POINTER(_Stats)]),
     "rcp_release": (ctypes.c_int, []),
     "rcp_set_grid_limit": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32]),
@@ -174,6 +176,12 @@ def rcp_set_profiling(on):
 
 def rcp_set_overlap(on):
     return load().rcp_set_overlap(1 if on else 0)
+
+
+def rcp_set_recompute(r=1):
+    """Algorithm 2 with recompute budget r for later factorizations (1 =
+    Algorithm 1)."""
+    _check("rcp_set_recompute", load().rcp_set_recompute(int(r)))
 
 
 def rcp_release():

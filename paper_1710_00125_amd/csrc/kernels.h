@@ -34,6 +34,8 @@ struct Ctrl {
   unsigned long long max_abs_d;   // max |D| over the entries of D
   unsigned long long min_margin;  // min | |a| - alpha lambda | / lambda of the SBKP tests
   long long near_ties;            // SBKP tests with that margin <= kNearTie
+  unsigned long long sketch_max2; // largest squared column norm of a sketch
+                                  // (launch_sketch_colmax), as double bits
 };
 // a decision margin at or below this is a near-tie (relative)
 constexpr double kNearTie = 1e-9;
@@ -51,8 +53,10 @@ struct Exchange {
 // ---- omega.hip
 // Omega (l x n) for `seed`: row-major (out[i*n+j]) when transposed == 0,
 // otherwise as Omega^T, n x lpad row-major (out[j*lpad + i], rows i >= l zero).
+// stream 1 is the factorization's Omega; 1 + j the j-th recomputation of
+// Algorithm 2.
 void launch_omega(uint64_t seed, int l, int64_t n, double* out, int transposed, int lpad,
-                  hipStream_t s);
+                  hipStream_t s, uint64_t stream = 1);
 
 // ---- sketch.hip
 // Acur (n x n, ld n, lower; double or float by prec) <- lower triangle of A
@@ -68,6 +72,10 @@ void launch_sketch(int64_t n, const void* Acur, int prec, int64_t ld, const doub
 // ctrl->nonfinite |= any entry of B (first l rows) is NaN/Inf
 void launch_check_finite(int64_t n, const double* B, int lpad, int l, Ctrl* ctrl, hipStream_t s);
 void launch_iota64(int64_t n, int64_t* P, hipStream_t s);
+// ctrl->sketch_max2 <- the largest squared column norm of B (first l rows,
+// n columns) as double bits (Algorithm 2's comparison with EPS^delta beta)
+void launch_sketch_colmax(int64_t n, const double* B, int lpad, int l, Ctrl* ctrl,
+                          hipStream_t s);
 
 // ---- select.hip  (partial QRCP on the block's sketch)
 // B: sketch of the trailing block (lpad x N column-major), picks bb columns.
@@ -133,8 +141,12 @@ void launch_update(const void* Acur, void* Anext, int64_t ld, const int* rowsrc,
 // ---- solve.hip
 // L (n x n col-major) from Lwork rows by original index, final perm P
 // (double when l_f32 == 0, float otherwise, for both Lwork and L).
+// Columns at and past `ncols` are left as those of the identity (the
+// columns Algorithm 2 did not eliminate).
 void launch_finalize_L(int64_t n, const void* Lwork, const int64_t* P, const int8_t* ipiv,
-                       void* L, int l_f32, hipStream_t s);
+                       void* L, int l_f32, hipStream_t s, int64_t ncols);
+// D(k:n) <- 0 and ipiv(k:n) <- 1 (positions Algorithm 2 did not eliminate)
+void launch_zero_tail(int64_t n, int64_t k, double* D, int8_t* ipiv, hipStream_t s);
 void launch_find_zero_pivot(int64_t n, const double* D, const int8_t* ipiv, int* out,
                             hipStream_t s);
 // ctrl->max_abs_d <- max |D| over the entries of the block diagonal factor

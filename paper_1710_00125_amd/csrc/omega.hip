@@ -9,14 +9,14 @@ namespace {
 
 using namespace omega_dev;
 
-__global__ void omega_kernel(uint64_t seed, int l, int64_t n, double* out, int transposed,
-                             int lpad) {
+__global__ void omega_kernel(uint64_t seed, uint64_t stream, int l, int64_t n, double* out,
+                             int transposed, int lpad) {
   const int64_t total = (int64_t)l * n;
   const int64_t nctr = (total + 3) / 4;
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nctr;
        c += (int64_t)gridDim.x * blockDim.x) {
     double z[4];
-    omega_quad(seed, c, z);
+    omega_quad(seed, c, z, stream);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int64_t q = 4 * c + t;
@@ -45,12 +45,12 @@ __global__ void zero_pad_rows_kernel(double* out, int64_t n, int l, int lpad) {
 }  // namespace
 
 void launch_omega(uint64_t seed, int l, int64_t n, double* out, int transposed, int lpad,
-                  hipStream_t s) {
+                  hipStream_t s, uint64_t stream) {
   const int64_t nctr = ((int64_t)l * n + 3) / 4;
   if (nctr > 0) {
     const int64_t blocks = std::min<int64_t>((nctr + 255) / 256, 65536);
-    hipLaunchKernelGGL(omega_kernel, dim3((unsigned)blocks), dim3(256), 0, s, seed, l, n, out,
-                       transposed, lpad);
+    hipLaunchKernelGGL(omega_kernel, dim3((unsigned)blocks), dim3(256), 0, s, seed, stream, l, n,
+                       out, transposed, lpad);
   }
   if (transposed && lpad > l && n > 0) {
     const int64_t total = n * (lpad - l);

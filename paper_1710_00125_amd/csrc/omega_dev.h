@@ -143,9 +143,11 @@ __device__ inline void box_muller(uint64_t wa, uint64_t wb, double& z0, double& 
 }
 
 // the four entries of counter c
-__device__ __forceinline__ void omega_quad(uint64_t seed, int64_t c, double z[4]) {
+// (stream kStreamOmega + j: the j-th fresh sketching matrix of Algorithm 2)
+__device__ __forceinline__ void omega_quad(uint64_t seed, int64_t c, double z[4],
+                                           uint64_t stream = kStreamOmega) {
   uint64_t x0 = (uint64_t)c, x1 = 0, x2 = 0, x3 = 0;
-  philox4x64_10(x0, x1, x2, x3, seed, kStreamOmega);
+  philox4x64_10(x0, x1, x2, x3, seed, stream);
   box_muller(x0, x1, z[0], z[1]);
   box_muller(x2, x3, z[2], z[3]);
 }

@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <vector>
@@ -26,6 +27,7 @@ hipStream_t g_stream = nullptr;
 bool g_prof = false;
 bool g_overlap = true;
 rcp_stats g_stats;
+int g_recompute = 1;      // r of Algorithm 2 (1: Algorithm 1)
 int g_select_limit = 0;   // bounds on the persistent kernels' grids (0: none)
 int g_panel_limit = 0;
 
@@ -154,6 +156,10 @@ int num_cus() {
     if ((x) != hipSuccess) return RCP_EDEVICE; \
   } while (0)
 
+// machine precision of Algorithm 2's thresholds EPS^delta beta (the spacing
+// of doubles at 1)
+constexpr double kEps = 0x1p-52;
+
 // LDS budget of one persistent workgroup's dynamic allocation (gfx950 has
 // 160 KB per CU; the rest is static shared memory and slack)
 constexpr size_t kLdsBudget = 140 * 1024;
@@ -202,6 +208,12 @@ int rcp_set_profiling(int32_t on) {
 
 int rcp_set_overlap(int32_t on) {
   g_overlap = on != 0;
+  return 0;
+}
+
+int rcp_set_recompute(int32_t r) {
+  if (r < 1) return -1;
+  g_recompute = r;
   return 0;
 }
 
@@ -389,6 +401,26 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
     launch_iota64(n, P0, s);
   }
   RCP_TRY(hipGetLastError());
+  // Algorithm 2 (Section 4.5): beta, the largest column norm of the first
+  // sketch; nrec recomputations so far, delta = (nrec + 1) / r
+  const int rr = g_recompute;
+  double beta = 0.0;
+  int nrec = 0;
+  int64_t rank = n;
+  auto sketch_norm = [&](const double* Bp, int Nb) -> double {
+    launch_sketch_colmax(Nb, Bp, lpad, l, ctrl, s);
+    unsigned long long bits = 0;
+    if (hipMemcpyAsync(&bits, &ctrl->sketch_max2, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return -1.0;
+    double v;
+    memcpy(&v, &bits, 8);
+    return std::sqrt(v);
+  };
+  if (rr > 1) {
+    beta = sketch_norm(Bcur, (int)n);
+    if (beta < 0.0) return finish(RCP_EDEVICE);
+  }
 
   int64_t* Pc = P0;
   int64_t* Pn = P1;
@@ -406,9 +438,39 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
     hipMemsetAsync(ex.rec, 0, (size_t)32 * Gmax * sizeof(unsigned long long), s);
     launch_select(Bc, lpad, l, Nb, std::min<int>(b, Nb), posof, win, ex, Gs, s);
   };
+  // is an Algorithm 2 check due at the next block start?
+  auto check_due = [&]() { return rr > 1 && nrec + 1 < rr; };
+  bool stopped = false;
   while (K0 < n) {
     const int N = (int)(n - K0);
     const int bb = std::min<int>(b, N);
+    if (K0 > 0 && check_due()) {
+      double t = sketch_norm(Bc, N);
+      if (t < 0.0) return finish(RCP_EDEVICE);
+      if (t < std::pow(kEps, (double)(nrec + 1) / rr) * beta) {
+        // recompute the sketch of the current Schur complement with a
+        // fresh Omega (stream 1 + nrec): the trailing update must be done
+        if (update_in_flight) RCP_TRY(hipStreamWaitEvent(s, g_side.updated, 0));
+        update_in_flight = false;
+        ++nrec;
+        {
+          Scope sc(KSketch);
+          launch_omega(seed, l, N, OmT, 1, lpad, s, (uint64_t)(1 + nrec));
+          launch_sketch(N, Ac + (size_t)(K0 + K0 * n) * esz, prec, n, OmT, lpad, Bc, partial,
+                        ksplit, s);
+          launch_check_finite(N, Bc, lpad, l, ctrl, s);
+        }
+        RCP_TRY(hipGetLastError());
+        t = sketch_norm(Bc, N);
+        if (t < 0.0) return finish(RCP_EDEVICE);
+        if (t < std::pow(kEps, (double)(nrec + 1) / rr) * beta) {
+          // rank deficient: the Schur complement counts as zero
+          rank = K0;
+          stopped = true;
+          break;
+        }
+      }
+    }
     if (!selected) enqueue_select(N);
     selected = false;
     // the panel reads the trailing matrix: the previous block's update first
@@ -497,7 +559,7 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
     ++nblocks;
     // the next block's selection needs only the updated sketch: it runs
     // while the trailing update proceeds on the second stream
-    if (N2 > 0 && g_overlap) {
+    if (N2 > 0 && g_overlap && !check_due()) {
       enqueue_select(N2);
       selected = true;
     }
@@ -505,7 +567,8 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
   if (update_in_flight) RCP_TRY(hipStreamWaitEvent(s, g_side.updated, 0));
   if (status == 0) {
     Scope sc(KFinal);
-    launch_finalize_L(n, Lwork, Pc, ipiv, L, prec != kPrecF64, s);
+    if (stopped) launch_zero_tail(n, rank, D, ipiv, s);
+    launch_finalize_L(n, Lwork, Pc, ipiv, L, prec != kPrecF64, s, rank);
     launch_max_abs_d(n, D, ipiv, ctrl, s);
     RCP_TRY(hipMemcpyAsync(perm, Pc, n * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
   }
@@ -522,9 +585,12 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
   memcpy(&g_stats.min_margin, &c.min_margin, 8);
   g_stats.near_ties = c.near_ties;
   g_stats.rho_d = g_stats.max_abs_a > 0.0 ? g_stats.max_abs_d / g_stats.max_abs_a : 0.0;
+  g_stats.recomputes = nrec;
+  g_stats.rank = rank;
   if (status != 0) return status;
   if (c.abort_flag) return RCP_EABORT;
   if (c.info != INT_MAX) return c.info;
+  if (stopped) return (int)(rank + 1);   // the first position of the zero Schur complement
   return 0;
 }
 

@@ -162,6 +162,25 @@ __global__ void check_finite_kernel(int64_t n, const double* __restrict__ B, int
   if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(&ctrl->nonfinite, 1);
 }
 
+// ctrl->sketch_max2 <- max over columns j < n of sum_{i<l} B(i, j)^2 (a
+// non-negative double, so its bit pattern orders as an unsigned integer)
+__global__ void sketch_colmax_kernel(int64_t n, const double* __restrict__ B, int lpad, int l,
+                                     Ctrl* ctrl) {
+  double best = 0.0;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const double* col = B + j * lpad;
+    double s = 0.0;
+    for (int i = 0; i < l; ++i) s = fma(col[i], col[i], s);
+    best = fmax(best, s);
+  }
+  for (int off = 32; off > 0; off >>= 1) best = fmax(best, __shfl_xor(best, off));
+  if ((threadIdx.x & 63) == 0)
+    atomicMax(&ctrl->sketch_max2, (unsigned long long)__double_as_longlong(best));
+}
+
+__global__ void clear_sketch_max_kernel(Ctrl* ctrl) { ctrl->sketch_max2 = 0ull; }
+
 __global__ void iota64_kernel(int64_t n, int64_t* P) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -213,6 +232,14 @@ void launch_check_finite(int64_t n, const double* B, int lpad, int l, Ctrl* ctrl
   if (n <= 0) return;
   hipLaunchKernelGGL(check_finite_kernel, dim3(grid1d(n * lpad, 256, 4096)), dim3(256), 0, s, n,
                      B, lpad, l, ctrl);
+}
+
+void launch_sketch_colmax(int64_t n, const double* B, int lpad, int l, Ctrl* ctrl,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(clear_sketch_max_kernel, dim3(1), dim3(1), 0, s, ctrl);
+  if (n <= 0) return;
+  hipLaunchKernelGGL(sketch_colmax_kernel, dim3(grid1d(n, 256, 1024)), dim3(256), 0, s, n, B, lpad,
+                     l, ctrl);
 }
 
 void launch_iota64(int64_t n, int64_t* P, hipStream_t s) {

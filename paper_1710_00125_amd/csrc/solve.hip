@@ -30,7 +30,7 @@ template <typename TL>
 __global__ void __launch_bounds__(256) finalize_L_kernel(int64_t n, const TL* __restrict__ Lwork,
                                                         const int64_t* __restrict__ P,
                                                         const int8_t* __restrict__ ipiv,
-                                                        TL* __restrict__ L) {
+                                                        TL* __restrict__ L, int64_t ncols) {
   __shared__ TL tile[kBlk][kBlk + 1];
   const int64_t nb = (n + kBlk - 1) / kBlk;
   const int64_t I = blockIdx.x % nb, C = blockIdx.x / nb;   // row tile, column tile
@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(256) finalize_L_kernel(int64_t n, const TL* __
       const int ii = e / kBlk, cc = e % kBlk;
       const int64_t i = i0 + ii, c = c0 + cc;
       TL v = 0;
-      if (i < n && c < n && c < i) v = Lwork[P[i] * n + c];
+      if (i < n && c < ncols && c < i) v = Lwork[P[i] * n + c];
       tile[ii][cc] = v;
     }
     __syncthreads();
@@ -422,17 +422,31 @@ unsigned grid1d(int64_t total) {
 
 }  // namespace
 
+__global__ void zero_tail_kernel(int64_t n, int64_t k, double* D, int8_t* ipiv) {
+  for (int64_t i = k + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    D[i] = 0.0;
+    D[n + i] = 0.0;
+    ipiv[i] = 1;
+  }
+}
+
+void launch_zero_tail(int64_t n, int64_t k, double* D, int8_t* ipiv, hipStream_t s) {
+  if (k >= n) return;
+  hipLaunchKernelGGL(zero_tail_kernel, dim3(grid1d(n - k)), dim3(256), 0, s, n, k, D, ipiv);
+}
+
 void launch_finalize_L(int64_t n, const void* Lwork, const int64_t* P, const int8_t* ipiv,
-                       void* L, int l_f32, hipStream_t s) {
+                       void* L, int l_f32, hipStream_t s, int64_t ncols) {
   if (n <= 0) return;
   const int64_t nb = (n + kBlk - 1) / kBlk;
   const dim3 grid((unsigned)(nb * nb));
   if (l_f32)
     hipLaunchKernelGGL(finalize_L_kernel<float>, grid, dim3(256), 0, s, n, (const float*)Lwork, P,
-                       ipiv, (float*)L);
+                       ipiv, (float*)L, ncols);
   else
     hipLaunchKernelGGL(finalize_L_kernel<double>, grid, dim3(256), 0, s, n, (const double*)Lwork,
-                       P, ipiv, (double*)L);
+                       P, ipiv, (double*)L, ncols);
 }
 
 void launch_max_abs_d(int64_t n, const double* D, const int8_t* ipiv, Ctrl* ctrl,
