@@ -87,7 +87,7 @@ EPS = 2.0 ** -52   # machine precision of Algorithm 2 (the spacing of doubles at
 
 
 def factor(A, b, p, seed=0, omega=None, schedule="delayed", record_sketch=False,
-           trace=False, recompute=1):
+           trace=False, recompute=1, q=None):
     """RCP block LDL^T of the symmetric matrix given by the lower triangle of A.
 
     A        n x n array; only A[i, j] with i >= j is read
@@ -101,6 +101,13 @@ def factor(A, b, p, seed=0, omega=None, schedule="delayed", record_sketch=False,
              exact arithmetic, also tracks the element growth factor)
     record_sketch  keep (K0, perm, B(:, K0:)) at every block start
     trace    keep a copy of perm in every decision-log entry (small n only)
+    q        pivots chosen per sketch (Algorithm 1): None or b is the q = b
+             branch (a b-step partial QRCP per block); 1 is the q = 1 branch:
+             before every SBKP step the trailing column of largest sketch norm
+             (ties: smallest position) is interchanged into position k, and
+             after it the sketch is updated by the step's pivot columns,
+             B(:, k+s:n) -= B(:, k:k+s-1) L(k+s:n, k:k+s-1)^T (eq. (3.3);
+             inside a 2x2 block L11 = I).  The sketch then has l = 1 + p rows.
     recompute  r of Algorithm 2 (Section 4.5): with r = 1 this is Algorithm 1.
              With r >= 2, beta is the largest column norm of the first
              sketch and delta = (j+1)/r after j recomputations; while
@@ -120,8 +127,9 @@ def factor(A, b, p, seed=0, omega=None, schedule="delayed", record_sketch=False,
     f = Factorization(n)
     if n == 0:
         return f
+    q1 = q == 1
     if omega is None:
-        Om = omega_mod.omega(seed, b + p, n)
+        Om = omega_mod.omega(seed, (1 if q1 else b) + p, n)
     else:
         Om = np.asarray(omega, dtype=np.float64)
     l = Om.shape[0]
@@ -180,6 +188,18 @@ def factor(A, b, p, seed=0, omega=None, schedule="delayed", record_sketch=False,
             v[0] += np.copysign(np.sqrt(x @ x), x[0])
             vv = v @ v
             R[j:, j + 1:] -= np.outer(v, (2.0 / vv) * (v @ R[j:, j + 1:]))
+
+    def sketch_argmax(k):
+        """q = 1: the trailing column of largest sketch norm goes to k."""
+        nrm2 = np.einsum("ij,ij->j", B[:, k:], B[:, k:])
+        c = int(np.argmax(nrm2))              # first maximum = smallest position
+        best = nrm2[c]
+        others = np.delete(nrm2, c)
+        second = others.max() if others.size else 0.0
+        f.log.append(dict(kind="qrcp", K0=k, j=0, pos=k + c, best=best, second=second))
+        if trace:
+            f.log[-1]["perm"] = perm.copy()
+        interchange(k, k + c)
 
     def sbkp(k, kd):
         """One step of Figure 2 at position k; returns s in {1, 2}."""
@@ -271,17 +291,27 @@ def factor(A, b, p, seed=0, omega=None, schedule="delayed", record_sketch=False,
         f.block_starts.append(K0)
         if record_sketch:
             f.sketch_at_block_start.append((K0, perm.copy(), B[:, K0:].copy()))
-        qrcp(K0, bb)
+        if not q1:
+            qrcp(K0, bb)
         i = 0
         while i < bb and k < n:
+            if q1:
+                sketch_argmax(k)
             s = sbkp(k, K0 if not eager else k)
+            if q1 and k + s < n:
+                # eq. (3.3): the sketch of the new Schur complement
+                t = slice(k, k + s)
+                B[:, k + s:] -= B[:, t] @ L[k + s:, t].T
             if eager and k + s < n:
                 t = slice(k, k + s)
                 S[k + s:, k + s:] -= L[k + s:, t] @ W[k + s:, t].T
                 growth = max(growth, np.max(np.abs(S[k + s:, k + s:])))
             k += s
             i += s
-        if k < n:
+        if k < n and q1:
+            if not eager:
+                S[k:, k:] -= L[k:, K0:k] @ W[k:, K0:k].T
+        elif k < n:
             # sketch update: B(:, k:n) -= B~_1 L11^{-T} L21^T
             L11 = np.tril(L[K0:k, K0:k], -1) + np.eye(k - K0)
             T = solve_triangular(L11, B[:, K0:k].T, lower=True, unit_diagonal=True).T
