@@ -180,7 +180,7 @@ def batched_run(rcp, count, replays):
     return res
 
 
-def _quality(rcp, A, b, p, seed, nrhs_seed):
+def _quality(rcp, A, b, p, seed, nrhs_seed, q=None):
     """One factor + solve of A (device, n x n) with the paper's right-hand
     side b = A x: time, growth factor, backward error (eq. (5.1)), ||L||_1
     and ||L^{-1}||_1 (the quantities of the paper's Section 5 figures)."""
@@ -191,7 +191,7 @@ def _quality(rcp, A, b, p, seed, nrhs_seed):
     rhs = A @ x
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    f = rcp.rcp_factor(A, b, p, seed)
+    f = rcp.rcp_factor(A, b, p, seed) if q is None else rcp.rcp_factor_q(A, b, p, seed, q)
     st = rcp.rcp_get_stats()
     X = rcp.rcp_solve(f, rhs)
     e1.record()
@@ -210,35 +210,82 @@ def _quality(rcp, A, b, p, seed, nrhs_seed):
 
 def stress_run(rcp, sizes, b=64, p=4, seed=10):
     """The paper's matrix types (Section 5) at each order in ``sizes``, block
-    b, oversampling p (the paper's choice p = q + 4 with q = b)."""
+    b, oversampling p = 4: the paper's own setting (q = 1, five sketch rows)
+    and the q = b branch (l = b + 4 rows)."""
     import torch
     from workloads import stress
-    res = {"b": b, "p": p, "seed": seed, "types": {}}
+    res = {"b": b, "p": p, "seed": seed, "q1": {}, "qb": {}}
     for kind in (1, 2, 3, 4, 5, 6, 7, 8, 10):
-        row = {}
+        r1, rb = {}, {}
         for n in sizes:
             A = torch.from_numpy(stress.matrix(kind, n, seed=seed + n)).cuda()
-            row[str(n)] = _quality(rcp, A, b, p, seed + n, seed)
+            r1[str(n)] = _quality(rcp, A, b, p, seed + n, seed, q=1)
+            rb[str(n)] = _quality(rcp, A, b, p, seed + n, seed)
             del A
-        res["types"][str(kind)] = row
+        res["q1"][str(kind)] = r1
+        res["qb"][str(kind)] = rb
         _log(f"bench: stress type {kind}: " + ", ".join(
-            f"n={n} rho={row[str(n)]['rho']:.3g} err={row[str(n)]['err']:.1e}" for n in sizes))
+            f"n={n} rho={r1[str(n)]['rho']:.3g}/{rb[str(n)]['rho']:.3g} "
+            f"err={r1[str(n)]['err']:.1e}/{rb[str(n)]['err']:.1e}" for n in sizes))
     return res
 
 
-def p_sweep_run(rcp, n=4096, b=64, ps=(0, 2, 4, 8, 16, 32, 64), seed=6):
+def p_sweep_run(rcp, n=4096, b=64, ps=(0, 2, 4, 8, 16, 31), seed=6):
     """Type 6 (Gaussian symmetric) at order n: the effect of the oversampling
-    p on time, growth, backward error, ||L||_1 and ||L^{-1}||_1 (the paper's
-    Section 5 study of p)."""
+    p on time, growth, backward error, ||L||_1 and ||L^{-1}||_1 for q = 1 and
+    q = b (the paper's Section 5 study of p and its Section 3.1 comparison of
+    q = 1 with q = b)."""
     import torch
     from workloads import stress
     A = torch.from_numpy(stress.matrix(6, n, seed=seed)).cuda()
-    res = {"type": 6, "n": n, "b": b, "seed": seed, "p": {}}
+    res = {"type": 6, "n": n, "b": b, "seed": seed, "q1": {}, "qb": {}}
     for p in ps:
-        _quality(rcp, A, b, p, seed, seed)            # warm-up of this shape
-        res["p"][str(p)] = _quality(rcp, A, b, p, seed, seed)
-        _log(f"bench: p-sweep p={p}: {res['p'][str(p)]}")
+        for name, q in (("q1", 1), ("qb", None)):
+            _quality(rcp, A, b, p, seed, seed, q=q)            # warm-up of this shape
+            res[name][str(p)] = _quality(rcp, A, b, p, seed, seed, q=q)
+        _log(f"bench: p-sweep p={p}: q=1 {res['q1'][str(p)]['ms']} ms, "
+             f"q=b {res['qb'][str(p)]['ms']} ms")
     return res
+
+
+def q1_run(rcp, A, b, cfg, args, fp64_ms):
+    """The q = 1 branch (the paper's experimental setting: a five-row
+    sketch, p = 4) on the benchmark matrix, factor + solve, timed over the
+    same number of steps as the q = b form."""
+    import torch
+    n = A.shape[0]
+    p = 4
+
+    def step():
+        f = rcp.rcp_factor_q(A, cfg.b, p, cfg.seed, 1)
+        st = rcp.rcp_get_stats()
+        x = rcp.rcp_solve(f, b)
+        return f, x, st
+
+    for w in range(args.warmup):
+        _log(f"bench: q=1 warmup {w + 1}/{args.warmup}")
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    sts = []
+    e0.record()
+    for s in range(args.steps):
+        f, x, st = step()
+        sts.append(st)
+        _log(f"bench: q=1 step {s + 1}/{args.steps}: factor {st['ms_total']:.1f} ms, "
+             f"panel {st['ms_panel']:.1f} ms, update {st['ms_update']:.1f} ms")
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    r = A @ x - b
+    berr = (r.abs().max(dim=0).values /
+            (A.abs().sum(dim=1).max() * x.abs().max(dim=0).values)).max().item()
+    avg = {k: round(sum(s_[k] for s_ in sts) / len(sts), 3)
+           for k in ("ms_total", "ms_panel", "ms_update", "ms_commit", "ms_solve")}
+    return {"q": 1, "b": cfg.b, "p": p, "l": 1 + p, "ms_per_step": round(ms, 3),
+            "value": round((n ** 3 / 3.0) / (ms * 1e-3) / 1e12, 4), "unit": "TFLOP/s",
+            "speedup_vs_q_b": round(fp64_ms / ms, 3), "backward_error": berr,
+            "n2x2": sts[-1]["n2x2"], "sbkp_cases": sts[-1]["ncase"], "kernel_ms": avg}
 
 
 def main():
@@ -259,6 +306,9 @@ def main():
     ap.add_argument("--cond-sweep", action="store_true",
                     help="also time the reduced-precision forms on the cond 1e2/1e6/1e10 "
                          "matrices of the same generator")
+    ap.add_argument("--q1", type=int, default=1,
+                    help="also time the q = 1 branch (five-row sketch) on the benchmark "
+                         "matrix (0 skips it)")
     ap.add_argument("--stress", default="1024,4096",
                     help="orders of the paper's matrix types (Section 5) to factor and "
                          "report growth, backward error, ||L||_1, ||L^-1||_1 (empty skips)")
@@ -388,6 +438,8 @@ def main():
         "kernel_ms": breakdown,
     }
     del f, x
+    if args.q1:
+        out["q1"] = q1_run(rcp, A, b, cfg, args, ms)
     mixed = [m for m in args.mixed.split(",") if m]
     if mixed:
         out["mixed"] = {}

@@ -179,6 +179,20 @@ int rcp_omega(uint64_t seed, int32_t l, int64_t n, double* out);
 int rcp_factor(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p,
                uint64_t seed, int64_t* perm, double* L, double* D, int8_t* ipiv);
 
+/* rcp_factor with the number q of pivots chosen per sketch (Algorithm 1):
+ *   q = b  as rcp_factor (a b-step partial QRCP per block, l = b + p rows);
+ *   q = 1  before every SBKP step the trailing column of largest sketch
+ *          norm (ties: smallest position) is interchanged into the pivot
+ *          position, and after it the sketch is updated by the step's pivot
+ *          columns, B(:, k+s:n) -= B(:, k:k+s-1) L(k+s:n, k:k+s-1)^T
+ *          (eq. (3.3)); the sketch has l = 1 + p rows (the paper's
+ *          experiments: p = 4, i.e. five rows), l <= 32.  The Schur
+ *          complement is still updated once per block of b columns.
+ * With b = 1 both branches are the same algorithm.  Other arguments, the
+ * outputs and the status codes as rcp_factor; -7 if q is neither 1 nor b. */
+int rcp_factor_q(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, uint64_t seed,
+                 int32_t q, int64_t* perm, double* L, double* D, int8_t* ipiv);
+
 /* Solve A X = B with the factors of rcp_factor (Table 1, solution phase):
  * X = P^T L^{-T} D^{-1} L^{-1} P B, 2x2 blocks of D by Cramer's rule in FP64.
  *   L, D, ipiv, perm  as written by rcp_factor for the same n

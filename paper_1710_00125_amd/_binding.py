@@ -73,6 +73,10 @@ _SIGS = {
                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_void_p]),
+    "rcp_factor_q": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                                    ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_void_p]),
     "rcp_solve": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                  ctypes.c_void_p, ctypes.c_int64]),
@@ -257,6 +261,26 @@ def rcp_factor(A, b, p, seed):
                              ctypes.c_uint64(int(seed) & (2**64 - 1)), _ptr(perm), _ptr(Lbuf),
                              _ptr(D), _ptr(ipiv))
     _check("rcp_factor", info, ok_positive=True)
+    return Factors(n, perm, Lbuf.t(), D, ipiv, info)
+
+
+def rcp_factor_q(A, b, p, seed, q):
+    """rcp_factor with q pivots per sketch: q = b as rcp_factor, q = 1 one
+    sketch argmax per step (sketch of 1 + p rows)."""
+    torch = _torch()
+    n = A.shape[0]
+    assert A.dim() == 2 and A.shape[1] == n and A.dtype == torch.float64 and A.is_cuda
+    Acm = _colmajor(A)
+    dev = A.device
+    perm = torch.empty(n, dtype=torch.int64, device=dev)
+    Lbuf = torch.empty((n, n), dtype=torch.float64, device=dev)
+    D = torch.empty(2 * n, dtype=torch.float64, device=dev)
+    ipiv = torch.empty(n, dtype=torch.int8, device=dev)
+    rcp_set_stream()
+    info = load().rcp_factor_q(n, _ptr(Acm), max(1, n), int(b), int(p),
+                               ctypes.c_uint64(int(seed) & (2**64 - 1)), int(q), _ptr(perm),
+                               _ptr(Lbuf), _ptr(D), _ptr(ipiv))
+    _check("rcp_factor_q", info, ok_positive=True)
     return Factors(n, perm, Lbuf.t(), D, ipiv, info)
 
 

@@ -13,7 +13,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librcp.so")
 
-SOURCES = ["omega.hip", "sketch.hip", "select.hip", "panel.hip", "blockops.hip", "update.hip",
+SOURCES = ["omega.hip", "sketch.hip", "select.hip", "panel.hip", "panel_q1.hip", "blockops.hip",
+           "update.hip",
            "solve.hip", "refine.hip", "batched.hip", "rcp_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -113,6 +113,16 @@ struct PanelArgs {
   double* T;          // out: T = B(:, piv) L11^{-T}, lpad x m column-major
 };
 int panel_grid(int N, int ldp, int lpad, int num_cu, size_t* lds_bytes, int* ngr);
+
+// ---- panel_q1.hip  (the q = 1 branch: a sketch argmax before every SBKP
+// step and the sketch update of eq. (3.3) after it, in one launch per block)
+// The sketch has l = 1 + p <= kMaxLQ1 rows.  a.win and a.T are unused; Bq
+// holds N x lpad doubles of scratch; Bnext receives the next block's sketch
+// (column i - m for block position i >= m).
+constexpr int kMaxLQ1 = 32;
+int panel_q1_grid(int N, int ldp, int l, int num_cu, size_t* lds_bytes);
+void launch_panel_q1(const PanelArgs& a, Exchange ex, double* Bq, double* Bnext, int G,
+                     size_t lds_bytes, hipStream_t s);
 void launch_panel(const PanelArgs& a, Exchange ex, int G, int ngr, size_t lds_bytes,
                   hipStream_t s);
 

@@ -287,14 +287,16 @@ namespace {
 // positions in the error codes follow rcp_factor; argument errors of the
 // outputs are reported by the callers.
 int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, uint64_t seed,
-                int prec, int64_t* perm, void* L, double* D, int8_t* ipiv) {
+                int prec, int64_t* perm, void* L, double* D, int8_t* ipiv, bool q1 = false) {
   memset(&g_stats, 0, sizeof(g_stats));
   g_stats.n = n;
   g_stats.min_margin = INFINITY;
   if (n == 0) return 0;
   if (n > INT_MAX / 2) return RCP_EUNSUPPORTED;
 
-  const int l = b + p;
+  // q = b: a b-step partial QRCP per block on l = b + p sketch rows;
+  // q = 1: one sketch argmax per step on l = 1 + p rows
+  const int l = (q1 ? 1 : b) + p;
   const int lpad = (l + 15) / 16 * 16;
   const int ldp = (b + 2) | 1;
   const int ncu = num_cus();
@@ -304,7 +306,14 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
   const int64_t rows_pad_max = (n + 127) / 128 * 128;
 
   // feasibility of the LDS-resident panels for the first (largest) block
-  if (!first_block_shape(n, b, p, ncu).ok) return RCP_EUNSUPPORTED;
+  if (q1) {
+    size_t lds = 0;
+    if (l > kMaxLQ1) return RCP_EUNSUPPORTED;
+    panel_q1_grid((int)n, ldp, l, capped(ncu, g_panel_limit), &lds);
+    if (lds > kLdsBudget) return RCP_EUNSUPPORTED;
+  } else if (!first_block_shape(n, b, p, ncu).ok) {
+    return RCP_EUNSUPPORTED;
+  }
   const int Gmax = ncu;
   const int vec_stride = std::max(lpad, ldp);
 
@@ -471,7 +480,7 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
         }
       }
     }
-    if (!selected) enqueue_select(N);
+    if (!selected && !q1) enqueue_select(N);
     selected = false;
     // the panel reads the trailing matrix: the previous block's update first
     if (update_in_flight) RCP_TRY(hipStreamWaitEvent(s, g_side.updated, 0));
@@ -502,7 +511,15 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
       pa.lpad = lpad;
       pa.T = Tm;
       hipMemsetAsync(ex.rec, 0, (size_t)32 * Gmax * sizeof(unsigned long long), s);
-      launch_panel(pa, ex, Gp, ngr, lds, s);
+      if (q1) {
+        // the sketch argmax, SBKP and the sketch update of every step; the
+        // next block's sketch goes to Bn (`partial` is free scratch here)
+        size_t lq = 0;
+        const int Gq = panel_q1_grid(N, ldp, l, ncu_pan, &lq);
+        launch_panel_q1(pa, ex, partial, Bn, Gq, lq, s);
+      } else {
+        launch_panel(pa, ex, Gp, ngr, lds, s);
+      }
     }
     RCP_TRY(hipGetLastError());
     RCP_TRY(hipMemcpyAsync(g_ctrl_host, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
@@ -522,7 +539,7 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
     }
     const int64_t K1 = K0 + m;
     const int N2 = N - m;
-    if (N2 > 0) {
+    if (N2 > 0 && !q1) {
       Scope sc(KSketchUpd);
       launch_sketch_update(Bc, lpad, l, srcat, m, N, Lpanel, ldp, Tm, Bn, s);
     }
@@ -559,7 +576,7 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
     ++nblocks;
     // the next block's selection needs only the updated sketch: it runs
     // while the trailing update proceeds on the second stream
-    if (N2 > 0 && g_overlap && !check_due()) {
+    if (N2 > 0 && g_overlap && !check_due() && !q1) {
       enqueue_select(N2);
       selected = true;
     }
@@ -731,6 +748,21 @@ int rcp_factor(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, ui
   if (n > 0 && !D) return -9;
   if (n > 0 && !ipiv) return -10;
   return factor_impl(n, A, lda, b, p, seed, kPrecF64, perm, L, D, ipiv);
+}
+
+int rcp_factor_q(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, uint64_t seed,
+                 int32_t q, int64_t* perm, double* L, double* D, int8_t* ipiv) {
+  if (n < 0) return -1;
+  if (!A && n > 0) return -2;
+  if (lda < std::max<int64_t>(1, n)) return -3;
+  if (b < 1 || b > kMaxB) return -4;
+  if (p < 0 || b + p > kMaxL) return -5;
+  if (q != 1 && q != b) return -7;
+  if (n > 0 && !perm) return -8;
+  if (n > 0 && !L) return -9;
+  if (n > 0 && !D) return -10;
+  if (n > 0 && !ipiv) return -11;
+  return factor_impl(n, A, lda, b, p, seed, kPrecF64, perm, L, D, ipiv, q == 1 && b > 1);
 }
 
 int rcp_factor_mp(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, uint64_t seed,
