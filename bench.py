@@ -91,11 +91,12 @@ def mixed_run(rcp, A, b, cfg, name, args, fp64_ms):
     """Reduced-precision factorization + FP64 GMRES refinement to 1e-13,
     timed over the same number of steps as the FP64 form."""
     import torch
-    prec = {"fp32": rcp.RCP_PREC_FP32, "bf16x3": rcp.RCP_PREC_BF16X3}[name]
+    prec = {"fp32": rcp.RCP_PREC_FP32, "bf16x3": rcp.RCP_PREC_BF16X3,
+            "bf16s": rcp.RCP_PREC_BF16S}[name]
     n = A.shape[0]
 
     def step():
-        f = rcp.rcp_factor_mp(A, cfg.b, cfg.p, cfg.seed, prec)
+        f = rcp.rcp_factor_ex(A, cfg.b, cfg.p, cfg.seed, precision=prec)
         st = rcp.rcp_get_stats()
         x, info = rcp.rcp_solve_ir(A, f, b, tol=1e-13, max_outer=10, restart=30,
                                    raise_on_noconv=False)
@@ -123,6 +124,9 @@ def mixed_run(rcp, A, b, cfg, name, args, fp64_ms):
     st, info = runs[-1]
     upd_ms = sum(r_[0]["ms_update"] for r_ in runs) / len(runs)
     peak = PEAK_FP32_MFMA if name == "fp32" else PEAK_BF16_MFMA
+    # matrix-core flops actually issued per algorithmic flop: three BF16
+    # products in the BF16x3 form, 21 slice-pair products in the sliced one
+    issued = {"fp32": 1.0, "bf16x3": 3.0, "bf16s": 21.0}[name]
     achieved = st["flops_update"] / (upd_ms * 1e-3) / 1e12 if upd_ms > 0 else 0.0
     return {
         "ms_per_step": round(ms, 3),
@@ -135,6 +139,8 @@ def mixed_run(rcp, A, b, cfg, name, args, fp64_ms):
         "backward_error": berr, "backward_error_reported": info["berr"],
         "update": {"ms_total": round(upd_ms, 3), "achieved": round(achieved, 3), "peak": peak,
                    "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                   "issued_per_algorithmic_flop": issued,
+                   "frac_issued": round(achieved * issued / peak, 4),
                    "achieved_GBps": round(st["bytes_update"] / (upd_ms * 1e-3) / 1e9, 1)
                    if upd_ms > 0 else 0.0},
         "n2x2": st["n2x2"],
@@ -296,9 +302,9 @@ def main():
     ap.add_argument("--config", default="householder16384")
     ap.add_argument("--cpu-sample", type=int, default=8192,
                     help="order of the oracle sample (0 skips it)")
-    ap.add_argument("--mixed", default="fp32,bf16x3",
+    ap.add_argument("--mixed", default="fp32,bf16x3,bf16s",
                     help="reduced-precision forms to time after the FP64 one "
-                         "(comma list of fp32, bf16x3; empty skips them)")
+                         "(comma list of fp32, bf16x3, bf16s; empty skips them)")
     ap.add_argument("--batched", type=int, default=4096, metavar="COUNT",
                     help="also time the batched form on COUNT systems (0 skips it)")
     ap.add_argument("--replays", type=int, default=50,

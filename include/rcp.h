@@ -47,10 +47,18 @@ extern "C" {
                                     cross-workgroup protocol did not complete);
                                     the outputs are unspecified              */
 
-/* Working precisions of rcp_factor_mp. */
+/* Working precisions of rcp_factor_mp and rcp_factor_ex. */
+#define RCP_PREC_FP64    0  /* the plain method (rcp_factor)                  */
 #define RCP_PREC_FP32    1  /* FP32 trailing matrix, L, sketch and update    */
 #define RCP_PREC_BF16X3  2  /* as FP32, but the update multiplies BF16 splits
                                x = hi + lo: hi*hi + hi*lo + lo*hi, FP32 sums */
+#define RCP_PREC_BF16S   3  /* FP64 trailing matrix and L; the update from
+                               BF16 matrix-core products of six 8-bit slices
+                               of each operand row (x = 2^e sum_a y_a
+                               2^(-8(a+1)), y_a integers), every slice-pair
+                               product exact in FP32 accumulation, pairs
+                               a + b <= 5 formed (about 2^-45 of the row
+                               maxima left out per term)                    */
 
 /* Per-call statistics (filled by every factor / solve call). */
 typedef struct rcp_stats {
@@ -193,6 +201,15 @@ int rcp_factor(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p,
 int rcp_factor_q(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, uint64_t seed,
                  int32_t q, int64_t* perm, double* L, double* D, int8_t* ipiv);
 
+/* The general form: q pivots per sketch (1 or b, as rcp_factor_q) and a
+ * working precision (RCP_PREC_*).  L is double* for RCP_PREC_FP64 and
+ * RCP_PREC_BF16S, float* for RCP_PREC_FP32 and RCP_PREC_BF16X3; the other
+ * arguments as rcp_factor.  Returns as rcp_factor; -7 for q, -8 for an
+ * unknown precision, -9..-12 for NULL perm, L, D, ipiv. */
+int rcp_factor_ex(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, uint64_t seed,
+                  int32_t q, int32_t precision, int64_t* perm, void* L, double* D,
+                  int8_t* ipiv);
+
 /* Solve A X = B with the factors of rcp_factor (Table 1, solution phase):
  * X = P^T L^{-T} D^{-1} L^{-1} P B, 2x2 blocks of D by Cramer's rule in FP64.
  *   L, D, ipiv, perm  as written by rcp_factor for the same n
@@ -275,6 +292,13 @@ int rcp_solve_ir(int64_t n, const double* A, int64_t lda, const float* L, const 
                  const int8_t* ipiv, const int64_t* perm, int64_t nrhs, const double* B,
                  int64_t ldb, double* X, int64_t ldx, double tol, int32_t max_outer,
                  int32_t restart, rcp_ir_result* res);
+
+/* rcp_solve_ir with a double L (the factors of rcp_factor_ex in
+ * RCP_PREC_BF16S, or of rcp_factor); arguments and returns as rcp_solve_ir. */
+int rcp_solve_ir64(int64_t n, const double* A, int64_t lda, const double* L, const double* D,
+                   const int8_t* ipiv, const int64_t* perm, int64_t nrhs, const double* B,
+                   int64_t ldb, double* X, int64_t ldx, double tol, int32_t max_outer,
+                   int32_t restart, rcp_ir_result* res);
 
 /* ---- Batched systems ---------------------------------------------------
  * Many independent small systems (1 <= n <= 512) factored and solved in one

@@ -14,8 +14,10 @@ RCP_ENOMEM = -1002
 RCP_EUNSUPPORTED = -1003
 RCP_ENOCONV = -1004
 RCP_EABORT = -1005
+RCP_PREC_FP64 = 0
 RCP_PREC_FP32 = 1
 RCP_PREC_BF16X3 = 2
+RCP_PREC_BF16S = 3
 RCP_NOALLOC_MAX_N = 16384
 
 
@@ -73,6 +75,16 @@ _SIGS = {
                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_void_p]),
+    "rcp_factor_ex": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "rcp_solve_ir64": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                      ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.POINTER(_IrResult)]),
     "rcp_factor_q": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
                                     ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
@@ -284,6 +296,28 @@ def rcp_factor_q(A, b, p, seed, q):
     return Factors(n, perm, Lbuf.t(), D, ipiv, info)
 
 
+def rcp_factor_ex(A, b, p, seed, q=None, precision=RCP_PREC_FP64):
+    """The general factorization: q pivots per sketch (None = b) in a working
+    precision (RCP_PREC_*); L is float64 for FP64 and BF16S, else float32."""
+    torch = _torch()
+    n = A.shape[0]
+    assert A.dim() == 2 and A.shape[1] == n and A.dtype == torch.float64 and A.is_cuda
+    Acm = _colmajor(A)
+    dev = A.device
+    ldt = torch.float64 if precision in (RCP_PREC_FP64, RCP_PREC_BF16S) else torch.float32
+    perm = torch.empty(n, dtype=torch.int64, device=dev)
+    Lbuf = torch.empty((n, n), dtype=ldt, device=dev)
+    D = torch.empty(2 * n, dtype=torch.float64, device=dev)
+    ipiv = torch.empty(n, dtype=torch.int8, device=dev)
+    rcp_set_stream()
+    info = load().rcp_factor_ex(n, _ptr(Acm), max(1, n), int(b), int(p),
+                                ctypes.c_uint64(int(seed) & (2**64 - 1)),
+                                int(b if q is None else q), int(precision), _ptr(perm),
+                                _ptr(Lbuf), _ptr(D), _ptr(ipiv))
+    _check("rcp_factor_ex", info, ok_positive=True)
+    return Factors(n, perm, Lbuf.t(), D, ipiv, info, int(precision))
+
+
 def rcp_factor_mp(A, b, p, seed, precision=RCP_PREC_FP32):
     """Reduced-precision factorization (FP32 or BF16x3 update); L is float32."""
     torch = _torch()
@@ -318,12 +352,13 @@ def _rhs_cm(B):
 def rcp_solve(f, B):
     """X with A X = B from the factors of rcp_factor or rcp_factor_mp;
     B is (n,) or (n, nrhs), float64."""
+    torch = _torch()
     Bcm, vec = _rhs_cm(B)
     nrhs, n = Bcm.shape
     Lcm = f.L.t()                              # the column-major storage itself
     assert Lcm.is_contiguous()
     rcp_set_stream()
-    fn = "rcp_solve_mp" if f.precision else "rcp_solve"
+    fn = "rcp_solve_mp" if f.L.dtype != torch.float64 else "rcp_solve"
     code = getattr(load(), fn)(n, _ptr(Lcm), _ptr(f.D), _ptr(f.ipiv), _ptr(f.perm), nrhs,
                                _ptr(Bcm), max(1, n))
     _check(fn, code)
@@ -360,7 +395,6 @@ def rcp_solve_ir(A, f, B, tol=1e-13, max_outer=10, restart=30, raise_on_noconv=T
     """FP64 solution of A X = B by GMRES-based refinement preconditioned by the
     reduced-precision factors f.  Returns (X, info dict)."""
     torch = _torch()
-    assert f.precision, "rcp_solve_ir needs the factors of rcp_factor_mp"
     n = A.shape[0]
     Acm = _colmajor(A)
     Bcm, vec = _rhs_cm(B)
@@ -370,13 +404,14 @@ def rcp_solve_ir(A, f, B, tol=1e-13, max_outer=10, restart=30, raise_on_noconv=T
     assert Lcm.is_contiguous()
     res = _IrResult()
     rcp_set_stream()
-    code = load().rcp_solve_ir(n, _ptr(Acm), max(1, n), _ptr(Lcm), _ptr(f.D), _ptr(f.ipiv),
+    fn = "rcp_solve_ir" if f.L.dtype == torch.float32 else "rcp_solve_ir64"
+    code = getattr(load(), fn)(n, _ptr(Acm), max(1, n), _ptr(Lcm), _ptr(f.D), _ptr(f.ipiv),
                                _ptr(f.perm), nrhs, _ptr(Bcm), max(1, n), _ptr(Xcm), max(1, n),
                                float(tol), int(max_outer), int(restart), ctypes.byref(res))
     info = {"outer": res.outer, "inner": res.inner, "berr": res.berr, "ms": res.ms,
             "converged": code == 0}
     if code != RCP_ENOCONV or raise_on_noconv:
-        _check("rcp_solve_ir", code)
+        _check(fn, code)
     X = Xcm.t()
     return (X[:, 0] if vec else X), info
 

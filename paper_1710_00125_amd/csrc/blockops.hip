@@ -228,6 +228,96 @@ __global__ void commit_pack_bf16x3_kernel(const int* __restrict__ srcat, int m, 
     rowsrc[i] = srcat[m + i];
 }
 
+// Sliced packing for the K = 32 BF16 matrix-core steps of the FP64-storage
+// update.  Each row x of L21 and of -W21 is written as
+//   x(t) = 2^e sum_{a < kSlices} y_a(t) 2^(-8 (a + 1)) + remainder,
+// e the row's exponent (every |x(t)| < 2^e), y_0 = rint(x 2^(8 - e)) and
+// y_(a+1) = rint(256 (x 2^(8a - e) - ...)): integers with |y_0| <= 256 and
+// |y_a| <= 128 afterwards, all exact in BF16.  Pass 1: the row exponents
+// (rows past N2 get 0); pass 2: fragment (g, qk) holds kSlices blocks of
+// 64 lanes x 8 BF16, slice a at 64 a (the lane layout of the BF16x3 form).
+__global__ void commit_rowexp_kernel(const int* __restrict__ srcat, int m, int N, int K0,
+                                     int64_t n, const double* __restrict__ Lp, int ldp,
+                                     const double* __restrict__ Dg,
+                                     const int8_t* __restrict__ ipiv, int rows_pad,
+                                     int* __restrict__ eL, int* __restrict__ eW) {
+  const int N2 = N - m;
+  for (int row = blockIdx.x * blockDim.x + threadIdx.x; row < rows_pad;
+       row += gridDim.x * blockDim.x) {
+    double ml = 0.0, mw = 0.0;
+    if (row < N2) {
+      const double* x = Lp + (size_t)srcat[m + row] * ldp;
+      for (int t = 0; t < m; ++t) {
+        ml = fmax(ml, fabs(x[t]));
+        mw = fmax(mw, fabs(w_of_row(x, Dg, ipiv, n, K0, t)));
+      }
+    }
+    int el = 0, ew = 0;
+    frexp(ml, &el);
+    frexp(mw, &ew);
+    eL[row] = el;
+    eW[row] = ew;
+  }
+}
+
+__device__ __forceinline__ void slice8(double x, int e, __bf16* y) {
+  double r = ldexp(x, -e);             // |r| < 1, exact
+#pragma unroll
+  for (int a = 0; a < kSlices; ++a) {
+    r *= 256.0;                        // exact
+    const double v = rint(r);
+    y[a] = (__bf16)(float)v;           // an integer of magnitude <= 256: exact
+    r -= v;                            // exact
+  }
+}
+
+__global__ void commit_pack_bf16s_kernel(const int* __restrict__ srcat, int m, int N, int K0,
+                                         int64_t n, const double* __restrict__ Lp, int ldp,
+                                         const double* __restrict__ Dg,
+                                         const int8_t* __restrict__ ipiv, rcp_bf8* __restrict__ L21p,
+                                         rcp_bf8* __restrict__ W21p, int Qk, int rows_pad,
+                                         const int* __restrict__ eL, const int* __restrict__ eW,
+                                         int* __restrict__ rowsrc) {
+  const int64_t total = (int64_t)(rows_pad / 16) * Qk * 64;
+  const int N2 = N - m;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = (int)(e & 63);
+    const int64_t frag = e >> 6;
+    const int qk = (int)(frag % Qk);
+    const int g = (int)(frag / Qk);
+    const int row = 16 * g + (lane & 15);
+    const double* x = (row < N2) ? Lp + (size_t)srcat[m + row] * ldp : nullptr;
+    const int el = eL[row], ew = eW[row];
+    rcp_bf8 ls[kSlices], ws[kSlices];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = 32 * qk + 8 * (lane >> 4) + u;
+      double lv = 0.0, wv = 0.0;
+      if (x && t < m) {
+        lv = x[t];
+        wv = w_of_row(x, Dg, ipiv, n, K0, t);
+      }
+      __bf16 yl[kSlices], yw[kSlices];
+      slice8(lv, el, yl);
+      slice8(-wv, ew, yw);   // negated, as in the other packings
+#pragma unroll
+      for (int a = 0; a < kSlices; ++a) {
+        ls[a][u] = yl[a];
+        ws[a][u] = yw[a];
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < kSlices; ++a) {
+      L21p[frag * (64 * kSlices) + 64 * a + lane] = ls[a];
+      W21p[frag * (64 * kSlices) + 64 * a + lane] = ws[a];
+    }
+  }
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N2;
+       i += (int64_t)gridDim.x * blockDim.x)
+    rowsrc[i] = srcat[m + i];
+}
+
 template <typename TL>
 __global__ void commit_rows_kernel(const int* __restrict__ srcat, int m, int N, int K0, int64_t n,
                                    const double* __restrict__ Lp, int ldp,
@@ -274,13 +364,20 @@ void launch_sketch_update(const double* B, int lpad, int l, const int* srcat, in
 // k steps of the trailing update, rounded up to an even count (the update
 // walks them in pairs; the packing writes zeros past m)
 int update_k_frags(int prec, int m) {
-  const int q = prec == kPrecBF16x3 ? (m + 31) / 32 : (m + 3) / 4;
+  const int q = (prec == kPrecBF16x3 || prec == kPrecBF16S) ? (m + 31) / 32 : (m + 3) / 4;
   return (q + 1) & ~1;
 }
 
 size_t update_pack_bytes(int prec, int64_t rows_pad, int Qk) {
   if (prec == kPrecBF16x3) return (size_t)(rows_pad / 16) * Qk * 2048;
+  // kSlices blocks of 1 KB per fragment, then the row exponents
+  if (prec == kPrecBF16S) return (size_t)(rows_pad / 16) * Qk * 1024 * kSlices + rows_pad * 4;
   return (size_t)rows_pad * Qk * 4 * prec_elem_bytes(prec);
+}
+
+int* update_row_exponents(void* pack, int prec, int64_t rows_pad, int Qk) {
+  (void)prec;
+  return (int*)((char*)pack + (size_t)(rows_pad / 16) * Qk * 1024 * kSlices);
 }
 
 void launch_commit(const int* srcat, int m, int N, int K0, int64_t n, const double* Lpanel,
@@ -288,8 +385,9 @@ void launch_commit(const int* srcat, int m, int N, int K0, int64_t n, const doub
                    int64_t* Pnext, void* Lwork, int prec, void* L21p, void* W21p, int Qk,
                    int rows_pad, int* rowsrc, hipStream_t s) {
   if (N - m > 0) {
-    const int64_t total = prec == kPrecBF16x3 ? (int64_t)(rows_pad / 16) * Qk * 64
-                                              : (int64_t)rows_pad * Qk * 4;
+    const int64_t total = (prec == kPrecBF16x3 || prec == kPrecBF16S)
+                              ? (int64_t)(rows_pad / 16) * Qk * 64
+                              : (int64_t)rows_pad * Qk * 4;
     const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 8192);
     if (prec == kPrecF64)
       hipLaunchKernelGGL(commit_pack_kernel<double>, dim3(blocks), dim3(256), 0, s, srcat, m, N,
@@ -299,13 +397,22 @@ void launch_commit(const int* srcat, int m, int N, int K0, int64_t n, const doub
       hipLaunchKernelGGL(commit_pack_kernel<float>, dim3(blocks), dim3(256), 0, s, srcat, m, N,
                          K0, n, Lpanel, ldp, Dg, ipiv, (float*)L21p, (float*)W21p, Qk, rows_pad,
                          rowsrc);
-    else
+    else if (prec == kPrecBF16x3)
       hipLaunchKernelGGL(commit_pack_bf16x3_kernel, dim3(blocks), dim3(256), 0, s, srcat, m, N,
                          K0, n, Lpanel, ldp, Dg, ipiv, (rcp_bf8*)L21p, (rcp_bf8*)W21p, Qk,
                          rows_pad, rowsrc);
+    else {
+      int* eL = update_row_exponents(L21p, prec, rows_pad, Qk);
+      int* eW = update_row_exponents(W21p, prec, rows_pad, Qk);
+      hipLaunchKernelGGL(commit_rowexp_kernel, dim3((rows_pad + 255) / 256), dim3(256), 0, s,
+                         srcat, m, N, K0, n, Lpanel, ldp, Dg, ipiv, rows_pad, eL, eW);
+      hipLaunchKernelGGL(commit_pack_bf16s_kernel, dim3(blocks), dim3(256), 0, s, srcat, m, N,
+                         K0, n, Lpanel, ldp, Dg, ipiv, (rcp_bf8*)L21p, (rcp_bf8*)W21p, Qk,
+                         rows_pad, eL, eW, rowsrc);
+    }
   }
   const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(N, 8192));
-  if (prec == kPrecF64)
+  if (prec_f64_storage(prec))
     hipLaunchKernelGGL(commit_rows_kernel<double>, dim3(blocks), dim3(128), 0, s, srcat, m, N, K0,
                        n, Lpanel, ldp, Pcur, Pnext, (double*)Lwork);
   else

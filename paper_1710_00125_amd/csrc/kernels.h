@@ -17,8 +17,15 @@ enum Prec : int {
   kPrecF64 = 0,     // everything FP64 (the plain method)
   kPrecF32 = 1,     // FP32 storage, FP32 matrix-core update and sketch
   kPrecBF16x3 = 2,  // FP32 storage, update as three BF16 products (hi*hi + hi*lo + lo*hi)
+  kPrecBF16S = 3,   // FP64 storage; update from exact BF16 products of 8-bit slices
 };
-inline size_t prec_elem_bytes(int prec) { return prec == kPrecF64 ? 8 : 4; }
+// FP64 trailing matrix and L (the plain method and the sliced update)
+inline bool prec_f64_storage(int prec) { return prec == kPrecF64 || prec == kPrecBF16S; }
+inline size_t prec_elem_bytes(int prec) { return prec_f64_storage(prec) ? 8 : 4; }
+// slices per operand entry of the sliced update: x = 2^e sum_a y_a 2^(-8(a+1))
+// with integers |y_a| <= 256 (exact in BF16); products of slice pairs with
+// a + b < kSlices are formed
+constexpr int kSlices = 6;
 
 // Device-resident control block of one factorization.  The unsigned 64-bit
 // fields hold the bit patterns of non-negative doubles, which order like the
@@ -137,6 +144,8 @@ void launch_sketch_update(const double* B, int lpad, int l, const int* srcat, in
 // Qk = number of k fragments (update_k_frags(prec, m), always even).
 int update_k_frags(int prec, int m);
 size_t update_pack_bytes(int prec, int64_t rows_pad, int Qk);
+// kPrecBF16S: the row exponents (rows_pad ints) after the slices in a pack
+int* update_row_exponents(void* pack, int prec, int64_t rows_pad, int Qk);
 void launch_commit(const int* srcat, int m, int N, int K0, int64_t n, const double* Lpanel,
                    int ldp, const double* Dg, const int8_t* ipiv, const int64_t* Pcur,
                    int64_t* Pnext, void* Lwork, int prec, void* L21p, void* W21p, int Qk,

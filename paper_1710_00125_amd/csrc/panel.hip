@@ -629,7 +629,7 @@ void launch_panel(const PanelArgs& a, Exchange ex, int G, int ntr, size_t lds_by
   p.R = (a.N + G - 1) / G;
   p.ntr = ntr;
   p.ldt = a.ldp;
-  const void* k = a.prec == kPrecF64 ? (const void*)panel_kernel<double>
+  const void* k = prec_f64_storage(a.prec) ? (const void*)panel_kernel<double>
                                      : (const void*)panel_kernel<float>;
   hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
   void* args[] = {&p};

@@ -475,7 +475,7 @@ void launch_panel_q1(const PanelArgs& a, Exchange ex, double* Bq, double* Bnext,
   p.Bnext = Bnext;
   p.G = G;
   p.R = (a.N + G - 1) / G;
-  const void* k = a.prec == kPrecF64 ? (const void*)panel_q1_kernel<double>
+  const void* k = prec_f64_storage(a.prec) ? (const void*)panel_q1_kernel<double>
                                      : (const void*)panel_q1_kernel<float>;
   hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
   void* args[] = {&p};

@@ -585,7 +585,7 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
   if (status == 0) {
     Scope sc(KFinal);
     if (stopped) launch_zero_tail(n, rank, D, ipiv, s);
-    launch_finalize_L(n, Lwork, Pc, ipiv, L, prec != kPrecF64, s, rank);
+    launch_finalize_L(n, Lwork, Pc, ipiv, L, !prec_f64_storage(prec), s, rank);
     launch_max_abs_d(n, D, ipiv, ctrl, s);
     RCP_TRY(hipMemcpyAsync(perm, Pc, n * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
   }
@@ -765,6 +765,30 @@ int rcp_factor_q(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, 
   return factor_impl(n, A, lda, b, p, seed, kPrecF64, perm, L, D, ipiv, q == 1 && b > 1);
 }
 
+int rcp_factor_ex(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, uint64_t seed,
+                  int32_t q, int32_t precision, int64_t* perm, void* L, double* D,
+                  int8_t* ipiv) {
+  if (n < 0) return -1;
+  if (!A && n > 0) return -2;
+  if (lda < std::max<int64_t>(1, n)) return -3;
+  if (b < 1 || b > kMaxB) return -4;
+  if (p < 0 || b + p > kMaxL) return -5;
+  if (q != 1 && q != b) return -7;
+  int prec;
+  switch (precision) {
+    case RCP_PREC_FP64: prec = kPrecF64; break;
+    case RCP_PREC_FP32: prec = kPrecF32; break;
+    case RCP_PREC_BF16X3: prec = kPrecBF16x3; break;
+    case RCP_PREC_BF16S: prec = kPrecBF16S; break;
+    default: return -8;
+  }
+  if (n > 0 && !perm) return -9;
+  if (n > 0 && !L) return -10;
+  if (n > 0 && !D) return -11;
+  if (n > 0 && !ipiv) return -12;
+  return factor_impl(n, A, lda, b, p, seed, prec, perm, L, D, ipiv, q == 1 && b > 1);
+}
+
 int rcp_factor_mp(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, uint64_t seed,
                   int32_t precision, int64_t* perm, float* L, double* D, int8_t* ipiv) {
   if (n < 0) return -1;
@@ -818,10 +842,10 @@ int rcp_solve_noalloc(int64_t n, const double* L, const double* D, const int8_t*
 // can meet its tolerance while the true one stalls when A is ill
 // conditioned.  Up to four right-hand sides run in lockstep, each with its
 // own Krylov space.
-int rcp_solve_ir(int64_t n, const double* A, int64_t lda, const float* L, const double* D,
-                 const int8_t* ipiv, const int64_t* perm, int64_t nrhs, const double* B,
-                 int64_t ldb, double* X, int64_t ldx, double tol, int32_t max_outer,
-                 int32_t restart, rcp_ir_result* res) {
+static int ir_impl(int64_t n, const double* A, int64_t lda, const void* L, int l_f32,
+                   const double* D, const int8_t* ipiv, const int64_t* perm, int64_t nrhs,
+                   const double* B, int64_t ldb, double* X, int64_t ldx, double tol,
+                   int32_t max_outer, int32_t restart, rcp_ir_result* res) {
   if (n < 0) return -1;
   if (n > 0 && !A) return -2;
   if (lda < std::max<int64_t>(1, n)) return -3;
@@ -899,7 +923,7 @@ int rcp_solve_ir(int64_t n, const double* A, int64_t lda, const float* L, const 
   memcpy(&anorm, &mxh[0], 8);
 
   auto precond = [&](double* v, int nr) {   // v <- M^{-1} v, ld n
-    launch_solve(n, L, 1, D, ipiv, perm, nr, v, n, Y, sync, s);
+    launch_solve(n, L, l_f32, D, ipiv, perm, nr, v, n, Y, sync, s);
   };
   std::vector<char> st_host(gmres_state_bytes(NR));
   int status = 0;
@@ -999,6 +1023,22 @@ int rcp_solve_ir(int64_t n, const double* A, int64_t lda, const float* L, const 
   }
   if (abort_word) return RCP_EABORT;
   return status;
+}
+
+int rcp_solve_ir(int64_t n, const double* A, int64_t lda, const float* L, const double* D,
+                 const int8_t* ipiv, const int64_t* perm, int64_t nrhs, const double* B,
+                 int64_t ldb, double* X, int64_t ldx, double tol, int32_t max_outer,
+                 int32_t restart, rcp_ir_result* res) {
+  return ir_impl(n, A, lda, L, 1, D, ipiv, perm, nrhs, B, ldb, X, ldx, tol, max_outer, restart,
+                 res);
+}
+
+int rcp_solve_ir64(int64_t n, const double* A, int64_t lda, const double* L, const double* D,
+                   const int8_t* ipiv, const int64_t* perm, int64_t nrhs, const double* B,
+                   int64_t ldb, double* X, int64_t ldx, double tol, int32_t max_outer,
+                   int32_t restart, rcp_ir_result* res) {
+  return ir_impl(n, A, lda, L, 0, D, ipiv, perm, nrhs, B, ldb, X, ldx, tol, max_outer, restart,
+                 res);
 }
 
 }  // extern "C"

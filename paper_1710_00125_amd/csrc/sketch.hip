@@ -199,7 +199,7 @@ void launch_copy_lower(int64_t n, const double* A, int64_t lda, void* Acur, int 
                        Ctrl* ctrl, hipStream_t s) {
   if (n <= 0) return;
   const dim3 grid((unsigned)std::min<int64_t>(n, 65536));
-  if (prec == kPrecF64)
+  if (prec_f64_storage(prec))
     hipLaunchKernelGGL(copy_lower_kernel<double>, grid, dim3(256), 0, s, n, A, lda,
                        (double*)Acur, ctrl);
   else
@@ -214,7 +214,7 @@ void launch_sketch(int64_t n, const void* Acur, int prec, int64_t ld, const doub
   kchunk = (kchunk + kTK - 1) / kTK * kTK;
   const int ks = (int)((n + kchunk - 1) / kchunk);
   dim3 grid((unsigned)((n + kTJ - 1) / kTJ), (unsigned)ks, (unsigned)((lpad + kTC - 1) / kTC));
-  if (prec == kPrecF64)
+  if (prec_f64_storage(prec))
     hipLaunchKernelGGL(sketch_partial_kernel<double>, grid, dim3(256), 0, s, n,
                        (const double*)Acur, ld, OmT, lpad, ks == 1 ? B : partial, kchunk);
   else

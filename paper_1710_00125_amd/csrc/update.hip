@@ -194,6 +194,109 @@ __global__ void __launch_bounds__(256, 2) update_kernel(const typename P::TA* __
   }
 }
 
+// The FP64-storage update from 8-bit slices (kPrecBF16S).  With the
+// operands packed as x = 2^e sum_a y_a 2^(-8(a+1)) (commit_pack_bf16s_kernel)
+// the product of a row of L21 and a row of -W21 is
+//   2^(eL + eW) sum_d 2^(-8(d+2)) P_d,   P_d = sum_{a+b=d} sum_t y_a(t) z_b(t),
+// and every P_d is an integer: |y_a z_b| <= 2^15 (2^16 for a = b = 0) and at
+// most 128 terms t per pass, so |P_d| <= 2^24 for d < kSlices and each P_d
+// is exact in FP32 accumulation, whatever the order of the sums.  Per group
+// d and per 128 columns of k the wave accumulates P_d on the BF16 matrix
+// cores and adds 2^(eL + eW - 8(d+2)) P_d (an exact scaling) to its FP64
+// entries.  Pairs with a + b >= kSlices are left out: relative to the row
+// maxima their sum is below about 2^-45 per term.
+__global__ void __launch_bounds__(256, 1) update_bf16s_kernel(
+    const double* __restrict__ Acur, double* __restrict__ Anext, int64_t ld,
+    const int* __restrict__ rowsrc, int N2, const rcp_bf8* __restrict__ L21p,
+    const rcp_bf8* __restrict__ W21p, const int* __restrict__ eL, const int* __restrict__ eW,
+    int Qk, int64_t ntiles) {
+  const int64_t b = blockIdx.x;
+  const int64_t per = (ntiles + kXcd - 1) / kXcd;
+  const int64_t xcd = b % kXcd, nx = gridDim.x / kXcd;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wy = w >> 1, wx = w & 1;
+  constexpr int FE = 64 * kSlices;   // rcp_bf8 per fragment (all slices)
+  for (int64_t t = b / kXcd; t < per; t += nx) {
+    const int64_t id = xcd * per + t;
+    if (id >= ntiles) break;
+    int I, J;
+    tile_of(id, I, J);
+    if (I == J && wx > wy) continue;
+    const int r0 = I * kTile + wy * 64;
+    const int c0 = J * kTile + wx * 64;
+    if (r0 >= N2 || c0 >= N2) continue;
+    const int src_r = rowsrc[min(r0 + lane, N2 - 1)];
+    const int src_c = rowsrc[min(c0 + lane, N2 - 1)];
+    const int g0 = r0 / 16, h0 = c0 / 16;
+    const rcp_bf8* pa = L21p + ((int64_t)g0 * Qk) * FE + lane;
+    const rcp_bf8* pb = W21p + ((int64_t)h0 * Qk) * FE + lane;
+    const int64_t gstride = (int64_t)Qk * FE;
+    // C[x][y][v]: row i = r0 + 16x + lane % 16, column j = c0 + 16y +
+    // acc_row_f32(lane, v) (the layout of the FP32 accumulators)
+    double C[4][4][4];
+    int ei[4], ej[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      const int i = r0 + 16 * x + acc_col(lane);
+      ei[x] = eL[i];
+      const int64_t s_i = __shfl(src_r, 16 * x + acc_col(lane));
+#pragma unroll
+      for (int y = 0; y < 4; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int jj = 16 * y + acc_row_f32(lane, v);
+          const int64_t s_j = __shfl(src_c, jj);
+          C[x][y][v] = Acur[(s_i >= s_j) ? s_i + s_j * ld : s_j + s_i * ld];
+          if (x == 0) ej[y][v] = eW[c0 + jj];
+        }
+    }
+    for (int d = 0; d < kSlices; ++d) {
+      for (int q0 = 0; q0 < Qk; q0 += 4) {
+        const int q1 = min(q0 + 4, Qk);
+        rcp_f4 acc[4][4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) acc[x][y] = rcp_f4{0.f, 0.f, 0.f, 0.f};
+        for (int q = q0; q < q1; ++q) {
+          for (int a = 0; a <= d; ++a) {
+            const int bs = d - a;
+            rcp_bf8 fa[4], fb[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+              fa[x] = pa[x * gstride + q * FE + 64 * a];
+              fb[x] = pb[x * gstride + q * FE + 64 * bs];
+            }
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+              for (int y = 0; y < 4; ++y) acc[x][y] = mfma16x16x32(fb[y], fa[x], acc[x][y]);
+          }
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              C[x][y][v] += ldexp((double)acc[x][y][v], ei[x] + ej[y][v] - 8 * (d + 2));
+      }
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      const int i = r0 + 16 * x + acc_col(lane);
+#pragma unroll
+      for (int y = 0; y < 4; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int j = c0 + 16 * y + acc_row_f32(lane, v);
+          if (i < N2 && j < N2) Anext[i + (int64_t)j * ld] = C[x][y][v];
+        }
+    }
+  }
+}
+
 }  // namespace
 
 void launch_update(const void* Acur, void* Anext, int64_t ld, const int* rowsrc, int N2,
@@ -207,7 +310,7 @@ void launch_update(const void* Acur, void* Anext, int64_t ld, const int* rowsrc,
   // concurrent register-resident selection kernel (about 140 registers):
   // two of the FP64 and FP32 forms (at most 184), one of the BF16x3 form
   // (about 210); never more than the tiles need
-  const int wpc = prec == kPrecBF16x3 ? 1 : 2;
+  const int wpc = (prec == kPrecBF16x3 || prec == kPrecBF16S) ? 1 : 2;
   const int64_t nwg = std::min<int64_t>((int64_t)wpc * num_cu / kXcd, per) * kXcd;
   const dim3 grid((unsigned)std::max<int64_t>(kXcd, nwg));
   if (prec == kPrecF64)
@@ -218,10 +321,18 @@ void launch_update(const void* Acur, void* Anext, int64_t ld, const int* rowsrc,
     hipLaunchKernelGGL(update_kernel<PackF32>, grid, dim3(256), 0, s, (const float*)Acur,
                        (float*)Anext, ld, rowsrc, N2, (const float*)L21p, (const float*)W21p, Qk,
                        ntiles);
-  else
+  else if (prec == kPrecBF16x3)
     hipLaunchKernelGGL(update_kernel<PackBF16x3>, grid, dim3(256), 0, s, (const float*)Acur,
                        (float*)Anext, ld, rowsrc, N2, (const rcp_bf8*)L21p, (const rcp_bf8*)W21p,
                        Qk, ntiles);
+  else {
+    const int64_t rows_pad = (N2 + kTile - 1) / kTile * kTile;
+    const int* eL = update_row_exponents(const_cast<void*>(L21p), prec, rows_pad, Qk);
+    const int* eW = update_row_exponents(const_cast<void*>(W21p), prec, rows_pad, Qk);
+    hipLaunchKernelGGL(update_bf16s_kernel, grid, dim3(256), 0, s, (const double*)Acur,
+                       (double*)Anext, ld, rowsrc, N2, (const rcp_bf8*)L21p,
+                       (const rcp_bf8*)W21p, eL, eW, Qk, ntiles);
+  }
 }
 
 }  // namespace rcp
