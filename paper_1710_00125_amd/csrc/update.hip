@@ -205,7 +205,7 @@ __global__ void __launch_bounds__(256, 2) update_kernel(const typename P::TA* __
 // cores and adds 2^(eL + eW - 8(d+2)) P_d (an exact scaling) to its FP64
 // entries.  Pairs with a + b >= kSlices are left out: relative to the row
 // maxima their sum is below about 2^-45 per term.
-__global__ void __launch_bounds__(256, 1) update_bf16s_kernel(
+__global__ void __launch_bounds__(256, 2) update_bf16s_kernel(
     const double* __restrict__ Acur, double* __restrict__ Anext, int64_t ld,
     const int* __restrict__ rowsrc, int N2, const rcp_bf8* __restrict__ L21p,
     const rcp_bf8* __restrict__ W21p, const int* __restrict__ eL, const int* __restrict__ eW,
@@ -224,75 +224,92 @@ __global__ void __launch_bounds__(256, 1) update_bf16s_kernel(
     tile_of(id, I, J);
     if (I == J && wx > wy) continue;
     const int r0 = I * kTile + wy * 64;
-    const int c0 = J * kTile + wx * 64;
-    if (r0 >= N2 || c0 >= N2) continue;
+    const int c0w = J * kTile + wx * 64;
+    if (r0 >= N2 || c0w >= N2) continue;
     const int src_r = rowsrc[min(r0 + lane, N2 - 1)];
-    const int src_c = rowsrc[min(c0 + lane, N2 - 1)];
-    const int g0 = r0 / 16, h0 = c0 / 16;
+    const int src_c = rowsrc[min(c0w + lane, N2 - 1)];
+    const int g0 = r0 / 16;
     const rcp_bf8* pa = L21p + ((int64_t)g0 * Qk) * FE + lane;
-    const rcp_bf8* pb = W21p + ((int64_t)h0 * Qk) * FE + lane;
     const int64_t gstride = (int64_t)Qk * FE;
-    // C[x][y][v]: row i = r0 + 16x + lane % 16, column j = c0 + 16y +
-    // acc_row_f32(lane, v) (the layout of the FP32 accumulators)
-    double C[4][4][4];
-    int ei[4], ej[4][4];
+    int ei[4];
 #pragma unroll
-    for (int x = 0; x < 4; ++x) {
-      const int i = r0 + 16 * x + acc_col(lane);
-      ei[x] = eL[i];
-      const int64_t s_i = __shfl(src_r, 16 * x + acc_col(lane));
+    for (int x = 0; x < 4; ++x) ei[x] = eL[r0 + 16 * x + acc_col(lane)];
+    // the wave's 64 x 64 in two passes of 64 x 32 (fewer registers per pass)
+    for (int hh = 0; hh < 2; ++hh) {
+      const int c0 = c0w + 32 * hh;
+      if (c0 >= N2) break;
+      const rcp_bf8* pb = W21p + ((int64_t)(c0 / 16) * Qk) * FE + lane;
+      // C[x][y][v]: row i = r0 + 16x + lane % 16, column j = c0 + 16y +
+      // acc_row_f32(lane, v) (the layout of the FP32 accumulators)
+      double C[4][2][4];
+      int ej[2][4];
 #pragma unroll
-      for (int y = 0; y < 4; ++y)
+      for (int x = 0; x < 4; ++x) {
+        const int64_t s_i = __shfl(src_r, 16 * x + acc_col(lane));
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int jj = 16 * y + acc_row_f32(lane, v);
-          const int64_t s_j = __shfl(src_c, jj);
-          C[x][y][v] = Acur[(s_i >= s_j) ? s_i + s_j * ld : s_j + s_i * ld];
-          if (x == 0) ej[y][v] = eW[c0 + jj];
-        }
-    }
-    for (int d = 0; d < kSlices; ++d) {
-      for (int q0 = 0; q0 < Qk; q0 += 4) {
-        const int q1 = min(q0 + 4, Qk);
-        rcp_f4 acc[4][4];
+        for (int y = 0; y < 2; ++y)
 #pragma unroll
-        for (int x = 0; x < 4; ++x)
+          for (int v = 0; v < 4; ++v) {
+            const int jj = 32 * hh + 16 * y + acc_row_f32(lane, v);
+            const int64_t s_j = __shfl(src_c, jj);
+            C[x][y][v] = Acur[(s_i >= s_j) ? s_i + s_j * ld : s_j + s_i * ld];
+            if (x == 0) ej[y][v] = eW[c0w + jj];
+          }
+      }
+      for (int d = 0; d < kSlices; ++d) {
+        for (int q0 = 0; q0 < Qk; q0 += 4) {
+          const int q1 = min(q0 + 4, Qk);
+          rcp_f4 acc[4][2];
 #pragma unroll
-          for (int y = 0; y < 4; ++y) acc[x][y] = rcp_f4{0.f, 0.f, 0.f, 0.f};
-        for (int q = q0; q < q1; ++q) {
-          for (int a = 0; a <= d; ++a) {
-            const int bs = d - a;
-            rcp_bf8 fa[4], fb[4];
+          for (int x = 0; x < 4; ++x)
 #pragma unroll
-            for (int x = 0; x < 4; ++x) {
-              fa[x] = pa[x * gstride + q * FE + 64 * a];
-              fb[x] = pb[x * gstride + q * FE + 64 * bs];
-            }
+            for (int y = 0; y < 2; ++y) acc[x][y] = rcp_f4{0.f, 0.f, 0.f, 0.f};
+          // the (k step, slice pair) products of this group and chunk in one
+          // sequence, the operands of the next pair loaded while the matrix
+          // cores work on the current one
+          const int np = (q1 - q0) * (d + 1);
+          auto load_pair = [&](int idx, rcp_bf8* fa, rcp_bf8* fb) {
+            const int q = q0 + idx / (d + 1), a = idx % (d + 1);
+#pragma unroll
+            for (int x = 0; x < 4; ++x) fa[x] = pa[x * gstride + q * FE + 64 * a];
+#pragma unroll
+            for (int y = 0; y < 2; ++y) fb[y] = pb[y * gstride + q * FE + 64 * (d - a)];
+          };
+          rcp_bf8 fa0[4], fb0[2], fa1[4], fb1[2];
+          load_pair(0, fa0, fb0);
+          for (int idx = 0; idx < np; idx += 2) {
+            if (idx + 1 < np) load_pair(idx + 1, fa1, fb1);
 #pragma unroll
             for (int x = 0; x < 4; ++x)
 #pragma unroll
-              for (int y = 0; y < 4; ++y) acc[x][y] = mfma16x16x32(fb[y], fa[x], acc[x][y]);
+              for (int y = 0; y < 2; ++y) acc[x][y] = mfma16x16x32(fb0[y], fa0[x], acc[x][y]);
+            if (idx + 1 >= np) break;
+            if (idx + 2 < np) load_pair(idx + 2, fa0, fb0);
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+              for (int y = 0; y < 2; ++y) acc[x][y] = mfma16x16x32(fb1[y], fa1[x], acc[x][y]);
           }
+#pragma unroll
+          for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+#pragma unroll
+              for (int v = 0; v < 4; ++v)
+                C[x][y][v] += ldexp((double)acc[x][y][v], ei[x] + ej[y][v] - 8 * (d + 2));
         }
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-          for (int y = 0; y < 4; ++y)
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-              C[x][y][v] += ldexp((double)acc[x][y][v], ei[x] + ej[y][v] - 8 * (d + 2));
       }
-    }
 #pragma unroll
-    for (int x = 0; x < 4; ++x) {
-      const int i = r0 + 16 * x + acc_col(lane);
+      for (int x = 0; x < 4; ++x) {
+        const int i = r0 + 16 * x + acc_col(lane);
 #pragma unroll
-      for (int y = 0; y < 4; ++y)
+        for (int y = 0; y < 2; ++y)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int j = c0 + 16 * y + acc_row_f32(lane, v);
-          if (i < N2 && j < N2) Anext[i + (int64_t)j * ld] = C[x][y][v];
-        }
+          for (int v = 0; v < 4; ++v) {
+            const int j = c0 + 16 * y + acc_row_f32(lane, v);
+            if (i < N2 && j < N2) Anext[i + (int64_t)j * ld] = C[x][y][v];
+          }
+      }
     }
   }
 }
@@ -309,7 +326,10 @@ void launch_update(const void* Acur, void* Anext, int64_t ld, const int* rowsrc,
   // workgroups per CU: as many as leave room in the register file for the
   // concurrent register-resident selection kernel (about 140 registers):
   // two of the FP64 and FP32 forms (at most 184), one of the BF16x3 form
-  // (about 210); never more than the tiles need
+  // (about 210) and of the sliced form (254; with two per CU it ran 78 ms
+  // instead of 125 ms over the n = 16384 factorization, but the selection
+  // then waited for it: 316 ms instead of 287 ms); never more than the
+  // tiles need
   const int wpc = (prec == kPrecBF16x3 || prec == kPrecBF16S) ? 1 : 2;
   const int64_t nwg = std::min<int64_t>((int64_t)wpc * num_cu / kXcd, per) * kXcd;
   const dim3 grid((unsigned)std::max<int64_t>(kXcd, nwg));
