@@ -52,6 +52,31 @@ def measured_traffic():
     return None
 
 
+def oracle_solution(name):
+    """The CPU oracle's stored solution for a benchmark matrix (written by the
+    scripts in tests/golden, which call only the oracle), or None."""
+    gold = os.path.join(ROOT, "tests", "golden")
+    try:
+        if name == "householder16384":
+            return np.load(os.path.join(gold, "householder16384_oracle.npz"))["x"]
+        if name.startswith("householder16384_cond"):
+            key = name[len("householder16384_cond"):].replace("+", "")
+            return np.load(os.path.join(gold, "householder16384_cond_oracle.npz"))[f"x_{key}"]
+    except (OSError, KeyError):
+        return None
+    return None
+
+
+def forward_error(x, x_ref):
+    """||x - x_oracle||_inf / ||x_oracle||_inf (None without a stored oracle
+    solution)."""
+    if x_ref is None:
+        return None
+    xh = x.reshape(len(x_ref), -1).cpu().numpy()
+    xr = np.asarray(x_ref).reshape(xh.shape)
+    return float(np.max(np.abs(xh - xr)) / np.max(np.abs(xr)))
+
+
 def cpu_baseline(cfg_name, n_sample):
     """The oracle as it stands, factor + solve, on a smaller instance of the
     same family (host cores)."""
@@ -76,8 +101,11 @@ def cpu_baseline(cfg_name, n_sample):
 
 
 def fp64_time(rcp, A, b, cfg):
-    """one FP64 factor + solve, ms (events around the two calls)"""
+    """one FP64 factor + solve, ms (events around the two calls, after one
+    untimed run of the same shape)"""
     import torch
+    rcp.rcp_solve(rcp.rcp_factor(A, cfg.b, cfg.p, cfg.seed), b)
+    torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     f = rcp.rcp_factor(A, cfg.b, cfg.p, cfg.seed)
@@ -122,6 +150,7 @@ def mixed_run(rcp, A, b, cfg, name, args, fp64_ms):
     anorm = A.abs().sum(dim=1).max()
     berr = (r.abs().max(dim=0).values / (anorm * x.reshape(n, -1).abs().max(dim=0).values)).max().item()
     st, info = runs[-1]
+    ferr = forward_error(x, oracle_solution(cfg.name))
     upd_ms = sum(r_[0]["ms_update"] for r_ in runs) / len(runs)
     peak = PEAK_FP32_MFMA if name == "fp32" else PEAK_BF16_MFMA
     # matrix-core flops actually issued per algorithmic flop: three BF16
@@ -137,6 +166,7 @@ def mixed_run(rcp, A, b, cfg, name, args, fp64_ms):
         "ms_refine": round(sum(r_[1]["ms"] for r_ in runs) / len(runs), 3),
         "ir_outer": info["outer"], "ir_inner": info["inner"], "converged": info["converged"],
         "backward_error": berr, "backward_error_reported": info["berr"],
+        "forward_error_vs_oracle": ferr,
         "update": {"ms_total": round(upd_ms, 3), "achieved": round(achieved, 3), "peak": peak,
                    "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                    "issued_per_algorithmic_flop": issued,
@@ -291,6 +321,7 @@ def q1_run(rcp, A, b, cfg, args, fp64_ms):
     return {"q": 1, "b": cfg.b, "p": p, "l": 1 + p, "ms_per_step": round(ms, 3),
             "value": round((n ** 3 / 3.0) / (ms * 1e-3) / 1e12, 4), "unit": "TFLOP/s",
             "speedup_vs_q_b": round(fp64_ms / ms, 3), "backward_error": berr,
+            "forward_error_vs_oracle": forward_error(x, oracle_solution(cfg.name)),
             "n2x2": sts[-1]["n2x2"], "sbkp_cases": sts[-1]["ncase"], "kernel_ms": avg}
 
 
@@ -309,9 +340,9 @@ def main():
                     help="also time the batched form on COUNT systems (0 skips it)")
     ap.add_argument("--replays", type=int, default=50,
                     help="graph replays of the batched plan for the latency percentiles")
-    ap.add_argument("--cond-sweep", action="store_true",
-                    help="also time the reduced-precision forms on the cond 1e2/1e6/1e10 "
-                         "matrices of the same generator")
+    ap.add_argument("--cond-sweep", type=int, default=1,
+                    help="also time the reduced-precision forms and FP64 on the cond "
+                         "1e2/1e6/1e10 matrices of the same generator, seeds 41-43 (0 skips)")
     ap.add_argument("--q1", type=int, default=1,
                     help="also time the q = 1 branch (five-row sketch) on the benchmark "
                          "matrix (0 skips it)")
@@ -439,6 +470,7 @@ def main():
                      "isolated_frac": round(upd_flops / (iso_ms * 1e-3) / 1e12 / PEAK_FP64_MFMA, 4)
                      if iso_ms > 0 else None},
         "backward_error": berr,
+        "forward_error_vs_oracle": forward_error(x, oracle_solution(cfg.name)),
         "n2x2": stats[-1]["n2x2"],
         "sbkp_cases": stats[-1]["ncase"],
         "kernel_ms": breakdown,
@@ -459,9 +491,9 @@ def main():
                 _log(f"bench: generating {ccfg.name}")
                 Ac = torch.from_numpy(ccfg.matrix()).to(dev)
                 bc = torch.from_numpy(ccfg.rhs()).to(dev)
-                out["cond_sweep"][ccfg.name] = {
-                    name: mixed_run(rcp, Ac, bc, ccfg, name, args, None) for name in mixed}
                 fp = fp64_time(rcp, Ac, bc, ccfg)
+                out["cond_sweep"][ccfg.name] = {
+                    name: mixed_run(rcp, Ac, bc, ccfg, name, args, fp) for name in mixed}
                 out["cond_sweep"][ccfg.name]["fp64_ms"] = fp
                 del Ac, bc
     if args.batched > 0:
