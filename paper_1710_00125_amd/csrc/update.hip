@@ -19,8 +19,12 @@
 // double-buffered across the k loop.  The accumulators are loaded with the
 // old entries before the k loop (W21 arrives negated), so the epilogue only
 // stores.  The launch is persistent (two workgroups per CU) and each XCD
-// (which receives every 8th workgroup) walks a contiguous stretch of the
-// tile order, reusing the same rows of L21 in its own L2.
+// (which receives every 8th workgroup) walks a contiguous stretch of a
+// banded tile order: bands of eight tile rows, column by column inside a
+// band.  The 64 tiles an XCD has in flight then span about 8 x 8 tiles and
+// share their L21 and W21 rows (2 MB in FP64) in that XCD's L2; in plain
+// row-major order they would span 64 tile columns, whose W21 rows (8 MB)
+// do not fit and are fetched again for every tile row.
 #include "common.h"
 #include "kernels.h"
 #include "mfma.h"
@@ -31,13 +35,35 @@ namespace {
 constexpr int kTile = 128;
 constexpr int kXcd = 8;
 
-__device__ __forceinline__ void tile_of(int64_t id, int& I, int& J) {
-  // id -> (I, J) with I >= J, row-major over the lower triangle of tiles
-  int64_t i = (int64_t)((sqrt(8.0 * (double)id + 1.0) - 1.0) * 0.5);
-  while ((i + 1) * (i + 2) / 2 <= id) ++i;
-  while (i * (i + 1) / 2 > id) --i;
-  I = (int)i;
-  J = (int)(id - i * (i + 1) / 2);
+constexpr int kBand = 8;   // tile rows per band of the walk order
+
+// id -> (I, J), I >= J, in the banded order over the lower triangle of
+// T x T tiles.  Band s holds tile rows [8s, 8s + 8) (the last one may hold
+// fewer, rr); inside it, column J in turn, rows ascending: first the full
+// columns J < 8s (rr tiles each), then the band's own triangle.  Full bands
+// before band s hold (64 s^2 + 8 s) / 2 tiles.
+__device__ __forceinline__ void tile_of(int64_t id, int64_t T, int& I, int& J) {
+  const int64_t B = kBand, full = T / B;
+  auto before = [&](int64_t x) { return (B * B * x * x + B * x) / 2; };
+  int64_t s = (int64_t)((sqrt((double)(B * B / 4) + 2.0 * (double)(B * B) * (double)id) -
+                         (double)(B / 2)) / (double)(B * B));
+  while (s > 0 && before(s) > id) --s;
+  while (s < full && before(s + 1) <= id) ++s;
+  const int64_t rr = (s < full) ? B : T - full * B;
+  int64_t o = id - before(s);
+  if (o < s * B * rr) {
+    J = (int)(o / rr);
+    I = (int)(s * B + o % rr);
+    return;
+  }
+  o -= s * B * rr;
+  int64_t j = 0;
+  while (o >= rr - j) {
+    o -= rr - j;
+    ++j;
+  }
+  J = (int)(s * B + j);
+  I = (int)(J + o);
 }
 
 // Operand packings (one fragment = one 16-row group at one k step):
@@ -99,9 +125,11 @@ __global__ void __launch_bounds__(256, 2) update_kernel(const typename P::TA* __
   typedef typename P::Frag Frag;
   typedef typename P::Acc Acc;
   // Persistent: the grid (a multiple of 8) loops over the tiles.  Hardware
-  // block b runs on XCD b % 8; XCD x walks the contiguous tile range
-  // [x per, (x + 1) per), so the rows of L21 a range touches stay in one L2.
+  // block b runs on XCD b % 8; XCD x walks the contiguous range
+  // [x per, (x + 1) per) of the banded order, so the operand rows its tiles
+  // share stay in one L2.
   const int64_t b = blockIdx.x;
+  const int64_t T = (N2 + kTile - 1) / kTile;
   const int64_t per = (ntiles + kXcd - 1) / kXcd;
   const int64_t xcd = b % kXcd, nx = gridDim.x / kXcd;
   const int lane = threadIdx.x & 63;
@@ -113,7 +141,7 @@ __global__ void __launch_bounds__(256, 2) update_kernel(const typename P::TA* __
   const int64_t id = xcd * per + t;
   if (id >= ntiles) break;
   int I, J;
-  tile_of(id, I, J);
+  tile_of(id, T, I, J);
   if (I == J && wx > wy) continue;   // strictly upper quarter of a diagonal tile
   const int r0 = I * kTile + wy * 64;   // first row of my 64 x 64
   const int c0 = J * kTile + wx * 64;   // first column
@@ -211,6 +239,7 @@ __global__ void __launch_bounds__(256, 2) update_bf16s_kernel(
     const rcp_bf8* __restrict__ W21p, const int* __restrict__ eL, const int* __restrict__ eW,
     int Qk, int64_t ntiles) {
   const int64_t b = blockIdx.x;
+  const int64_t T = (N2 + kTile - 1) / kTile;
   const int64_t per = (ntiles + kXcd - 1) / kXcd;
   const int64_t xcd = b % kXcd, nx = gridDim.x / kXcd;
   const int lane = threadIdx.x & 63;
@@ -221,7 +250,7 @@ __global__ void __launch_bounds__(256, 2) update_bf16s_kernel(
     const int64_t id = xcd * per + t;
     if (id >= ntiles) break;
     int I, J;
-    tile_of(id, I, J);
+    tile_of(id, T, I, J);
     if (I == J && wx > wy) continue;
     const int r0 = I * kTile + wy * 64;
     const int c0w = J * kTile + wx * 64;
