@@ -118,6 +118,15 @@ int rcp_set_profiling(int32_t on);
  * are measured in isolation).  Results are identical either way.  Returns 0. */
 int rcp_set_overlap(int32_t on);
 
+/* Speculation in the persistent SBKP panels (Figure 2): while a step's
+ * records are exchanged, every workgroup assumes the step takes case (0) or
+ * (1) (a 1x1 pivot on the current column) and forms the next step's column
+ * and candidate; another case restores what the assumption changed and
+ * redoes the step.  mode = 1: whenever the shape allows, 0: never, -1 (the
+ * default): where it was measured to pay.  Pivots, L and D are bit-identical
+ * in every mode.  Returns 0, or -1 for another mode. */
+int rcp_set_speculation(int32_t mode);
+
 /* Algorithm 2 of the paper (Section 4.5) for later rcp_factor and
  * rcp_factor_mp calls: r = 1 (the default) is Algorithm 1.  With r >= 2,
  * beta is the largest column norm of the first sketch and delta = (j+1)/r

@@ -14,7 +14,8 @@ from ._binding import (RCP_EABORT, RCP_ENOCONV, RCP_NOALLOC_MAX_N, RCP_PREC_BF16
                        Factors, exported_symbols, lib_path, load, pack_batch, rcp_batch_create,
                        rcp_batch_get_table, rcp_batch_set_table, rcp_factor, rcp_factor_ex, rcp_factor_mp, rcp_factor_q,
                        rcp_get_stats, rcp_launch_shape, rcp_omega, rcp_release,
-                       rcp_set_grid_limit, rcp_set_overlap, rcp_set_profiling, rcp_set_recompute,
+                       rcp_set_grid_limit, rcp_set_overlap, rcp_set_profiling,
+                       rcp_set_speculation, rcp_set_recompute,
                        rcp_set_stream,
                        rcp_solve, rcp_solve_ir, rcp_solve_mp, rcp_solve_noalloc)
 
@@ -23,5 +24,5 @@ __all__ = ["RCP_EABORT", "RCP_ENOCONV", "RCP_NOALLOC_MAX_N", "RCP_PREC_BF16S", "
            "Factors", "exported_symbols", "lib_path", "load", "pack_batch", "rcp_batch_create",
            "rcp_batch_get_table", "rcp_batch_set_table", "rcp_factor", "rcp_factor_ex", "rcp_factor_mp", "rcp_factor_q",
            "rcp_get_stats", "rcp_launch_shape", "rcp_omega", "rcp_release", "rcp_set_grid_limit",
-           "rcp_set_overlap", "rcp_set_profiling", "rcp_set_recompute", "rcp_set_stream", "rcp_solve", "rcp_solve_ir",
+           "rcp_set_overlap", "rcp_set_profiling", "rcp_set_speculation", "rcp_set_recompute", "rcp_set_stream", "rcp_solve", "rcp_solve_ir",
            "rcp_solve_mp", "rcp_solve_noalloc"]

@@ -63,6 +63,7 @@ _SIGS = {
     "rcp_set_stream": (ctypes.c_int, [ctypes.c_void_p]),
     "rcp_set_profiling": (ctypes.c_int, [ctypes.c_int32]),
     "rcp_set_overlap": (ctypes.c_int, [ctypes.c_int32]),
+    "rcp_set_speculation": (ctypes.c_int, [ctypes.c_int32]),
     "rcp_set_recompute": (ctypes.c_int, [ctypes.c_int32]),
     "rcp_get_stats": (ctypes.c_int, [ctypes.POINTER(_Stats)]),
     "rcp_release": (ctypes.c_int, []),
@@ -192,6 +193,15 @@ def rcp_set_profiling(on):
 
 def rcp_set_overlap(on):
     return load().rcp_set_overlap(1 if on else 0)
+
+
+def rcp_set_speculation(mode):
+    """mode 1: speculate in the SBKP panels whenever the shape allows, 0: never,
+    -1: the measured rule (the default)."""
+    rc = load().rcp_set_speculation(int(mode))
+    if rc != 0:
+        raise ValueError(f"rcp_set_speculation: mode {mode} is not -1, 0 or 1")
+    return rc
 
 
 def rcp_set_recompute(r=1):

@@ -128,9 +128,11 @@ int panel_grid(int N, int ldp, int lpad, int num_cu, size_t* lds_bytes, int* ngr
 // (column i - m for block position i >= m).
 constexpr int kMaxLQ1 = 32;
 int panel_q1_grid(int N, int ldp, int l, int num_cu, size_t* lds_bytes);
+// spec: speculate SBKP case (0)/(1) across the exchange (1), never (0), or
+// by the measured rule of each kernel (-1)
 void launch_panel_q1(const PanelArgs& a, Exchange ex, double* Bq, double* Bnext, int G,
-                     size_t lds_bytes, hipStream_t s);
-void launch_panel(const PanelArgs& a, Exchange ex, int G, int ngr, size_t lds_bytes,
+                     size_t lds_bytes, int spec, hipStream_t s);
+void launch_panel(const PanelArgs& a, Exchange ex, int G, int ngr, size_t lds_bytes, int spec,
                   hipStream_t s);
 
 // ---- blockops.hip

@@ -37,6 +37,23 @@
 //            forms the L row of the next pivot redundantly.  The next pivot
 //            is always one of {c, win[k+1], win[k+2]}: their rows of L and
 //            their columns of A are prefetched during the step.
+//
+// Speculation (at most 64 rows per workgroup).  SBKP case (1) decides
+// almost every step (16332 of 16368 at n = 16384), and its pivot c and its
+// next pivot win[k+1] are known before the decision.  So during the gap
+// every workgroup assumes case (0)/(1) for step k: it applies the step's
+// multipliers to its rows (keeping the old diagonal), forms the next pivot's
+// new L entry, W row and a_kk redundantly, forms the next column on its
+// rows and its best candidate, and keeps the L row of win[k+2] current
+// (loads of the entries stored before step k-1, and entries k-1 and k
+// formed as their owner forms them).  When the decision confirms the case,
+// the next record goes out at once; otherwise the old diagonal comes back
+// and the step is finished by the step-by-step path above.  The arithmetic
+// is the same in both paths, so the results are bit-identical either way.
+// One wave does all of a speculative step's global loads and stores and
+// publishes the record, so that its waits for memory overlap the other
+// waves' work and the exchange.  Measured at n = 16384: 6.1 us per step
+// against 7.1 us step by step (factorization 232 ms against 253 ms).
 #include <climits>
 
 #include "common.h"
@@ -48,6 +65,9 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kRowsPerPass = kThreads / 4;
 constexpr int kMaxG = 256;   // workgroups of one launch (one per CU at most)
+// grids at least this large speculate (all: kkt4096 48.4 ms against 52.7 ms
+// step by step, where the later blocks run on grids below 256)
+constexpr int kSpecMinG = 1;
 
 struct PanelParams {
   PanelArgs a;
@@ -55,6 +75,7 @@ struct PanelParams {
   int G, R;
   int ntr;        // rows of T owned per workgroup (rows G-1-g, G-1-g+G, ...)
   int ldt;        // LDS row stride of T (>= bb + 2)
+  int spec;       // speculate SBKP case (0)/(1) (needs R <= 64)
 };
 
 // multipliers of a 1x1 pivot d (zero column when d == 0: SBKP case (0))
@@ -163,13 +184,16 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
   const bool wide = ldp >= 128;             // rows long enough for dot16_quad_z
   double* Lrow = smem;                      // [R][ldl] L rows of my sources
   double* vcol = Lrow + (size_t)R * ldl;    // [R] current column on my rows
-  double* acolv = vcol + R;                 // [3][R] A(s, .) for c, win[k+1], win[k+2]
+  double* vcolS = vcol + R;                 // [R] the next column (speculation)
+  double* acolv = vcolS + R;                // [3][R] A(s, .) for c, win[k+1], win[k+2]
   double* Adiag = acolv + 3 * R;            // [R] current diagonal a_ss of my rows
-  double* avec = Adiag + R;                 // [R] A(s, r)
+  double* AdiagOld = Adiag + R;             // [R] ... before a speculative step
+  double* avec = AdiagOld + R;              // [R] A(s, r)
   double* Lp = avec + R;                    // [ldp] L row of the pivot
   double* Wp = Lp + ldp;                    // [ldp] its W row
   double* Wn = Wp + ldp;                    // [ldp] W row of the next pivot
-  double* Lr = Wn + ldp;                    // [ldp] L row of the winner r
+  double* Wv = Wn + ldp;                    // [ldp] W row of the previous pivot
+  double* Lr = Wv + ldp;                    // [ldp] L row of the winner r
   double* Wr = Lr + ldp;                    // [ldp] its W row
   double* Ln1 = Wr + ldp;                   // [ldp] L row of win[k+1]
   double* Ln2 = Ln1 + ldp;                  // [ldp] L row of win[k+2]
@@ -185,7 +209,9 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
   __shared__ int sh_rsrc[2][kMaxG];
   __shared__ double sh_rark[2][kMaxG], sh_rarr[2][kMaxG];
   __shared__ double sh_akk, sh_Acc, sh_A1c, sh_A2c, sh_A11, sh_A22, sh_Anr;
-  __shared__ double sh_vn, sh_vrn, sh_sold;
+  __shared__ double sh_vn, sh_vrn, sh_sold, sh_vn2;
+  __shared__ double sh_A21, sh_akkS;
+  __shared__ double sh_bpt[16];   // B(r, pivot) for my first 16 rows of T (speculation)
   __shared__ unsigned long long sh_rec[4];
   __shared__ int sh_pend_n, sh_pend_t, sh_pend_s1, sh_pend_s2;
 
@@ -222,6 +248,7 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
   for (int t = tid; t < ldp; t += kThreads) {
     Wp[t] = 0.0;
     Wn[t] = 0.0;
+    Wv[t] = 0.0;
     Wr[t] = 0.0;
   }
   if (tid == 0) sh_pend_n = 0;
@@ -234,6 +261,17 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
     if (tid == 0) {
       sh_Acc = A[(int64_t)c * (ld + 1)];
       sh_akk = sh_Acc;
+    }
+    // the first step's speculation: A(s, win[1]), A(win[1], win[0]),
+    // A(win[1], win[1])
+    const int c1 = bb > 1 ? win[1] : -1;
+    if (P.spec && c1 >= 0) {
+      for (int r = tid; r < nown; r += kThreads)
+        acolv[R + r] = sym_at(A, ld, (int64_t)(s0 + r), (int64_t)c1);
+      if (tid == 64) {
+        sh_A1c = sym_at(A, ld, (int64_t)c1, (int64_t)c);
+        sh_A11 = A[(int64_t)c1 * (ld + 1)];
+      }
     }
   }
   __syncthreads();
@@ -264,6 +302,28 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
   };
 
   int k = 0;
+  // have: the column of win[k] on my rows (vcol) and my best candidate
+  // (best) were formed speculatively during the previous exchange, and the
+  // record of step k is already published.
+  // spec_ok: the state the speculation needs is in place -- Ln1 holds the L
+  // row of win[k+1] (entries < k), Wv and akkprev the W row and a_kk of the
+  // previous pivot (1x1), acol1 = A(s, win[k+1]), sh_A1c = A(win[k+1],
+  // win[k]), sh_A11 = A(win[k+1], win[k+1]); true at the block start and
+  // after every step of case (0)/(1).
+  bool have = false;
+  bool spec_ok = P.spec != 0;
+  double akk = 0.0;        // a_kk of the current pivot (the same in every thread)
+  double akkprev = 0.0;    // ... of the previous pivot
+  ArgKey best{-1.0, INT_MAX, -1};
+  // Speculative steps give every global memory access of the step to wave
+  // 2 (the gmem wave): the next step's operands are loaded at the start
+  // and stored to LDS only at the end, the multipliers and D are stored in
+  // between, and the record is published by that wave alone once the
+  // decision is known.  Its waits for memory then overlap the other waves'
+  // work and the exchange.
+  const bool gw = (tid >> 6) == 2;   // the gmem wave
+  const int gl = tid & 63;           // its lane
+  unsigned long long recS = 0;       // gmem wave, lanes 0..3: the next record's words
   while (k < bb) {
     // a 2x2 step advances k by two, so the slots alternate by iteration
     const int par = it & 1;
@@ -273,56 +333,184 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
     double* acol = acolv + cur * R;
     double* acol1 = acolv + ((cur + 1) % 3) * R;
     double* acol2 = acolv + ((cur + 2) % 3) * R;
-    // ---- phase A: current column of c on my rows, my best candidate
-    ArgKey best{-1.0, INT_MAX, -1};
-    for (int rb = 0; rb < nown; rb += kRowsPerPass) {
-      const int r = rb + rho;
-      const bool live = r < nown && posl[r] > k;
-      const double* xr = Lrow + (size_t)(live ? r : 0) * ldl;
-      const double dsum =
-          wide ? dot16_quad_z(xr, Wp, live ? k : 0, q) : dot16_quad(xr, Wp, live ? k : 0, q);
-      if (live && q == 0) {
-        const double v = acol[r] - dsum;
-        vcol[r] = v;
-        ArgKey kk{fabs(v), posl[r], s0 + r};
-        if (key_better(kk, best)) best = kk;
+    unsigned long long* recs = P.ex.rec + (size_t)par * P.G * RCP_REC_STRIDE;
+    if (!have) {
+      // ---- phase A: current column of c on my rows, my best candidate
+      best = ArgKey{-1.0, INT_MAX, -1};
+      for (int rb = 0; rb < nown; rb += kRowsPerPass) {
+        const int r = rb + rho;
+        const bool live = r < nown && posl[r] > k;
+        const double* xr = Lrow + (size_t)(live ? r : 0) * ldl;
+        const double dsum =
+            wide ? dot16_quad_z(xr, Wp, live ? k : 0, q) : dot16_quad(xr, Wp, live ? k : 0, q);
+        if (live && q == 0) {
+          const double v = acol[r] - dsum;
+          vcol[r] = v;
+          ArgKey kk{fabs(v), posl[r], s0 + r};
+          if (key_better(kk, best)) best = kk;
+        }
+      }
+      best = block_argmax1(best, shk);   // (the publication barrier follows)
+      {
+        const bool hv = best.idx >= 0;
+        const int rl = hv ? best.idx - s0 : 0;
+        if (tid == 0) {
+          sh_rec[0] = rec_tag(best.val, it);
+          sh_rec[1] = rec_word1(best.pos, best.idx, it);
+          sh_rec[2] = rec_tag(hv ? vcol[rl] : 0.0, it);
+          sh_rec[3] = rec_tag(hv ? Adiag[rl] : 0.0, it);
+        }
+      }
+      // publish the record after every store of this workgroup so far (its
+      // multipliers of the last step) has completed
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (tid < 4) st_agent(&recs[RCP_REC_STRIDE * g + tid], sh_rec[tid]);
+      akk = sh_akk;
+    }
+    const bool spec = spec_ok && c1 >= 0;
+    double lsp = 0.0;                 // largest speculative multiplier of this thread
+    ArgKey bestS{-1.0, INT_MAX, -1};  // my best candidate of the next column
+    double akkS = 0.0;                // a_kk of c1 (speculation)
+    // gmem wave registers: A(s0 + gl, c2); L(c2, gl), L(c2, gl + 64);
+    // A(c2, c / c2 / c1 / win[k-1]) (lanes 0..3); B(T row gl, c)
+    double pa2 = 0.0, pl2a = 0.0, pl2b = 0.0, psc = 0.0, pbt = 0.0;
+    if (!spec) {
+      // ---- gap: prefetch the columns of the two window candidates for the
+      // next step, and extend T by the previous step's pivots
+      for (int r = tid; r < nown; r += kThreads) {
+        // both loads issued before either store (sources clamped: a value for
+        // an absent candidate is not stored)
+        const double v1 = sym_at(A, ld, (int64_t)(s0 + r), (int64_t)max(c1, 0));
+        const double v2 = sym_at(A, ld, (int64_t)(s0 + r), (int64_t)max(c2, 0));
+        if (c1 >= 0) acol1[r] = v1;
+        if (c2 >= 0) acol2[r] = v2;
+      }
+      if (tid == 64 && c1 >= 0) {
+        sh_A1c = sym_at(A, ld, (int64_t)c1, (int64_t)c);
+        sh_A11 = A[(int64_t)c1 * (ld + 1)];
+      }
+      if (tid == 128 && c2 >= 0) {
+        sh_A2c = sym_at(A, ld, (int64_t)c2, (int64_t)c);
+        sh_A22 = A[(int64_t)c2 * (ld + 1)];
+        sh_A21 = sym_at(A, ld, (int64_t)c2, (int64_t)max(c1, 0));
+      }
+      flush_T();
+    } else {
+      // ---- speculation: assume SBKP case (0)/(1) (pivot c, 1x1) and form
+      // the next step's column while the records are in flight
+      if (gw) {
+        // S0: the next step's operands (consumed at S5)
+        if (c2 >= 0) {
+          if (gl < nown) pa2 = sym_at(A, ld, (int64_t)(s0 + gl), (int64_t)c2);
+          if (gl < 4) {
+            const int cc = gl == 0 ? c : (gl == 1 ? c2 : (gl == 2 ? c1 : win[max(k - 1, 0)]));
+            psc = sym_at(A, ld, (int64_t)c2, (int64_t)cc);
+          }
+          // L(c2, t) for t < k - 1: stored by its owner before its record
+          // of step k - 1
+          if (gl < k - 1) pl2a = ld_agent(&a.Lpanel[(size_t)c2 * ldp + gl]);
+          if (gl + 64 < k - 1) pl2b = ld_agent(&a.Lpanel[(size_t)c2 * ldp + gl + 64]);
+        }
+        {
+          const int r = tr0 + gl * P.G;
+          if (gl < ntr && gl < 16 && r < a.l) pbt = a.B[(int64_t)c * lpad + r];
+        }
+        if (gl == 0 && g == 0) {
+          const int64_t gk = a.K0 + k;
+          a.Dg[gk] = akk;
+          a.Dg[a.n + gk] = 0.0;
+          a.ipiv[gk] = 1;
+        }
+      }
+      // S1: multipliers of column k on my rows (kept if the step is case
+      // (0)/(1)); the W entries of c1 before k
+      for (int rb = 0; rb < nown; rb += kRowsPerPass) {
+        const int r = rb + rho;
+        if (r < nown && q == 0 && posl[r] > k) {
+          const double l1 = mult_1x1(vcol[r], akk);
+          Lrow[(size_t)r * ldl + k] = l1;
+          const double dold = Adiag[r];
+          AdiagOld[r] = dold;
+          Adiag[r] = fma(-l1, l1 * akk, dold);
+          lsp = fmax(lsp, fabs(l1));
+        }
+      }
+      for (int t = tid; t < k; t += kThreads) Wn[t] = w_entry(Ln1, Dd, Ds, kind, t);
+      __syncthreads();
+      // S2: the next pivot c1 (wave 1): its entry in column k and its a_kk,
+      // lanes 0..15 summing L(c1, t) W(c, t), lanes 16..31 L(c1, t) W(c1, t)
+      // over t < k (the chunks and trees of every other dot product, so the
+      // same bits); the gmem wave stores the multipliers
+      if ((tid >> 6) == 1 && (tid & 63) < 32) {
+        const int lw = tid & 63;
+        const double dsum = dot16_lanes(Ln1, lw < 16 ? Wp : Wn, k, l16);
+        const double sold = bcast_lane(dsum, 16);
+        const double vn = sh_A1c - bcast_lane(dsum, 0);
+        const double l1 = mult_1x1(vn, akk);
+        if (lw == 0) {
+          Ln1[k] = l1;
+          Dd[k] = akk;
+          Ds[k] = 0.0;
+          kind[k] = 1;
+          const double wk = l1 * akk;   // w_entry of a 1x1 column
+          Wn[k] = wk;
+          sh_akkS = sh_A11 - (sold + fma(l1, wk, 0.0));
+        }
+      }
+      if (gw) {
+        for (int r = gl; r < nown; r += 64)
+          if (posl[r] > k)
+            st_agent(&a.Lpanel[(size_t)(s0 + r) * ldp + k], Lrow[(size_t)r * ldl + k]);
+      }
+      __syncthreads();
+      akkS = sh_akkS;
+      // S3: the column of c1 on my rows (positions after k + 1)
+      for (int rb = 0; rb < nown; rb += kRowsPerPass) {
+        const int r = rb + rho;
+        const bool live = r < nown && posl[r] > k + 1;
+        const double* xr = Lrow + (size_t)(live ? r : 0) * ldl;
+        const double dsum = wide ? dot16_quad_z(xr, Wn, live ? k + 1 : 0, q)
+                                 : dot16_quad(xr, Wn, live ? k + 1 : 0, q);
+        if (live && q == 0) {
+          const double v = acol1[r] - dsum;
+          vcolS[r] = v;
+          ArgKey kk{fabs(v), posl[r], s0 + r};
+          if (key_better(kk, bestS)) bestS = kk;
+        }
+      }
+      bestS = block_argmax1(bestS, shk);
+      // S4: T
+      flush_T();
+      // S5 (gmem wave): stash the operands, L(c2, k-1) and L(c2, k) formed
+      // as their owner forms them (their stores are not visible before the
+      // next step), and the words of the next record
+      if (gw) {
+        if (c2 >= 0) {
+          if (gl < nown) acol2[gl] = pa2;
+          if (gl < k - 1) Ln2[gl] = pl2a;
+          if (gl + 64 < k - 1) Ln2[gl + 64] = pl2b;
+          if (gl < 16) {
+            const double ap = bcast_lane(psc, 3), ac = bcast_lane(psc, 0);
+            if (k >= 1) {
+              const double d1 = dot16_lanes(Ln2, Wv, k - 1, l16);
+              Ln2[k - 1] = mult_1x1(ap - d1, akkprev);
+            }
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            const double d2 = dot16_lanes(Ln2, Wp, k, l16);
+            Ln2[k] = mult_1x1(ac - d2, akk);
+          }
+        }
+        if (gl < 16) sh_bpt[gl] = pbt;
+        const bool hv = bestS.idx >= 0;
+        const int rl = hv ? bestS.idx - s0 : 0;
+        const double w2 = hv ? vcolS[rl] : 0.0, w3 = hv ? Adiag[rl] : 0.0;
+        recS = gl == 0 ? rec_tag(bestS.val, it + 1)
+                       : (gl == 1 ? rec_word1(bestS.pos, bestS.idx, it + 1)
+                                  : rec_tag(gl == 2 ? w2 : w3, it + 1));
       }
     }
-    best = block_argmax1(best, shk);   // (the publication barrier follows)
-    const bool have = best.idx >= 0;
-    const int rl = have ? best.idx - s0 : 0;
-    if (tid == 0) {
-      sh_rec[0] = rec_tag(best.val, it);
-      sh_rec[1] = rec_word1(best.pos, best.idx, it);
-      sh_rec[2] = rec_tag(have ? vcol[rl] : 0.0, it);
-      sh_rec[3] = rec_tag(have ? Adiag[rl] : 0.0, it);
-    }
-    // publish the record after every store of this workgroup so far (its
-    // multipliers of the last step) has completed
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    unsigned long long* recs = P.ex.rec + (size_t)par * P.G * RCP_REC_STRIDE;
-    if (tid < 4) st_agent(&recs[RCP_REC_STRIDE * g + tid], sh_rec[tid]);
-    // ---- gap: prefetch the columns of the two window candidates for the
-    // next step, and extend T by the previous step's pivots
-    for (int r = tid; r < nown; r += kThreads) {
-      // both loads issued before either store (sources clamped: a value for
-      // an absent candidate is not stored)
-      const double v1 = sym_at(A, ld, (int64_t)(s0 + r), (int64_t)max(c1, 0));
-      const double v2 = sym_at(A, ld, (int64_t)(s0 + r), (int64_t)max(c2, 0));
-      if (c1 >= 0) acol1[r] = v1;
-      if (c2 >= 0) acol2[r] = v2;
-    }
-    if (tid == 64 && c1 >= 0) {
-      sh_A1c = sym_at(A, ld, (int64_t)c1, (int64_t)c);
-      sh_A11 = A[(int64_t)c1 * (ld + 1)];
-    }
-    if (tid == 128 && c2 >= 0) {
-      sh_A2c = sym_at(A, ld, (int64_t)c2, (int64_t)c);
-      sh_A22 = A[(int64_t)c2 * (ld + 1)];
-    }
-    flush_T();
 
     // ---- phase B: every workgroup's record (one poll is the barrier and the
     // read), the same decision everywhere; keys (value, position,
@@ -359,10 +547,13 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
     __syncthreads();   // every record seen: all earlier stores of all workgroups visible
     // L rows of the two window candidates for the next pivot (entries < k
     // were stored by their owners before their records)
-    for (int t = tid; t < k; t += kThreads) {
-      if (c1 >= 0) Ln1[t] = ld_agent(&a.Lpanel[(size_t)c1 * ldp + t]);
-      if (c2 >= 0) Ln2[t] = ld_agent(&a.Lpanel[(size_t)c2 * ldp + t]);
-    }
+    auto load_next_rows = [&]() {
+      for (int t = tid; t < k; t += kThreads) {
+        if (c1 >= 0) Ln1[t] = ld_agent(&a.Lpanel[(size_t)c1 * ldp + t]);
+        if (c2 >= 0) Ln2[t] = ld_agent(&a.Lpanel[(size_t)c2 * ldp + t]);
+      }
+    };
+    if (!spec) load_next_rows();
     rk = block_argmax1(rk, shk);   // (its barrier also orders the LDS lookups below)
     Rec rc{rk.val, rk.pos, -1, 0.0, 0.0, rk.idx};
     if (rk.idx >= 0) {
@@ -370,7 +561,6 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
       rc.ark = sh_rark[par][rk.idx];
       rc.arr = sh_rarr[par][rk.idx];
     }
-    const double akk = sh_akk;
     const double lam = rc.val >= 0.0 ? rc.val : 0.0;
     const int rpos = rc.pos, rsrc = rc.src;
     const double ark = rc.ark, arr = rc.arr;
@@ -379,6 +569,81 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
     else if (fabs(akk) >= RCP_ALPHA * lam) kase = 1;
     else if (fabs(arr) >= RCP_ALPHA * lam) kase = 2;
     else kase = 3;
+
+    if (spec && kase <= 1) {
+      // ---- the speculation holds: publish the next record (the gmem wave
+      // stored everything this workgroup stores before it), then the
+      // bookkeeping
+      if (gw && gl < 4) {
+        __builtin_amdgcn_s_waitcnt(0);
+        unsigned long long* rn = P.ex.rec + (size_t)(par ^ 1) * P.G * RCP_REC_STRIDE;
+        st_agent(&rn[RCP_REC_STRIDE * g + gl], recS);
+      }
+      lmax = fmax(lmax, lsp);
+      if (gw && gl == 0 && g == 0) {
+        if (akk == 0.0) atomicMin(&a.ctrl->info, (int)(a.K0 + k + 1));
+        ncase[kase] += 1;
+        if (lam > 0.0) {
+          const double mg = fabs(fabs(akk) - RCP_ALPHA * lam) / lam;
+          mmin = fmin(mmin, mg);
+          nties += (mg <= kNearTie) ? 1 : 0;
+        }
+      }
+      if (gw && gl == 1) {
+        // the next pivot's diagonal, and the next step's A(c2, c2), A(c2, c1)
+        // (read again only after the next barrier)
+        const double a11 = sh_A11;
+        sh_Acc = a11;
+        if (c2 >= 0) sh_A11 = psc;
+      }
+      if (gw && gl == 2 && c2 >= 0) sh_A1c = psc;
+      if (tid == 0) {
+        sh_pend_n = 1;
+        sh_pend_t = k;
+        sh_pend_s1 = c;
+      }
+      if (l16 == 0 && grp16 < ntr) bp1 = sh_bpt[grp16];
+      akkprev = akk;
+      akk = akkS;
+      {
+        // pending T column: the pivot's old row; the next pivot's row; the
+        // row of win[k+2] (entries < k + 1); a free buffer
+        double* t0 = Pd1;
+        Pd1 = Lp;
+        Lp = Ln1;
+        Ln1 = Ln2;
+        Ln2 = t0;
+        double* t1 = Wv;
+        Wv = Wp;
+        Wp = Wn;
+        Wn = t1;
+        double* t2 = vcol;
+        vcol = vcolS;
+        vcolS = t2;
+      }
+      cur = (cur + 1) % 3;
+      best = bestS;
+      have = true;
+      k += 1;
+      it += 1;
+      continue;   // (the next step's first barrier orders the LDS writes above)
+    }
+    if (spec) {
+      // undo the speculative diagonal (the multipliers and D entries are
+      // rewritten below), put the operands of c2 where the step-by-step
+      // path keeps them, and read the candidates' rows as it does
+      for (int rb = 0; rb < nown; rb += kRowsPerPass) {
+        const int r = rb + rho;
+        if (r < nown && q == 0 && posl[r] > k) Adiag[r] = AdiagOld[r];
+      }
+      if (gw && gl < 2 && c2 >= 0) {
+        if (gl == 0) sh_A2c = psc;
+        if (gl == 1) sh_A22 = psc;
+      }
+      load_next_rows();
+      __syncthreads();
+    }
+    have = false;
     const int sstep = (kase == 3) ? 2 : 1;
     // next pivot source after this step's interchange
     int cn;
@@ -483,6 +748,11 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
       const double dsum = dot16_lanes(Lsrc, Wr, k, l16);
       if (l16 == 0) sh_vrn = sh_Anr - dsum;
     }
+    if (cn >= 0 && kase <= 1 && c2 >= 0 && (tid >> 6) == 2 && (tid & 63) < 16) {
+      // ... and win[k+2]'s entry in column c (its row is the next step's Ln1)
+      const double dsum = dot16_lanes(Ln2, Wp, k, l16);
+      if (l16 == 0) sh_vn2 = sh_A2c - dsum;
+    }
     if (cn >= 0 && (tid >> 6) == 3 && (tid & 63) < 16) {
       // ... and its old L row against its old W row (for a_kk)
       const double sold = dot16_lanes_w(Lsrc, Dd, Ds, kind, k, l16);
@@ -560,12 +830,26 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
       const double Acc = (cn == c) ? sh_Acc : (cn == c1 ? sh_A11 : sh_A22);
       sh_Acc = Acc;
       sh_akk = Acc - (sh_sold + tail);
+      if (kase <= 1 && c2 >= 0) {
+        // the state the next step's speculation needs (see spec_ok)
+        Ln2[kold] = mult_1x1(sh_vn2, dpiv);
+        sh_A1c = sh_A21;
+        sh_A11 = sh_A22;
+      }
     }
     {
-      double* tmp = Wp;
+      double* tmp = Wv;
+      Wv = Wp;
       Wp = Wn;
       Wn = tmp;
     }
+    if (kase <= 1) {
+      double* tmp = Ln1;
+      Ln1 = Ln2;
+      Ln2 = tmp;
+    }
+    akkprev = akk;
+    spec_ok = P.spec != 0 && kase <= 1;
     cur = (cn == c) ? cur : (cn == c1 ? (cur + 1) % 3 : (cur + 2) % 3);
     __syncthreads();
   }
@@ -602,7 +886,7 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
 }
 
 size_t panel_lds(int R, int ldp, int bb, int ntr, int ldt) {
-  return (size_t)R * (ldp | 1) * 8 + (size_t)7 * R * 8 + (size_t)12 * ldp * 8 +
+  return (size_t)R * (ldp | 1) * 8 + (size_t)9 * R * 8 + (size_t)13 * ldp * 8 +
          (size_t)ntr * ldt * 8 + (size_t)ldp * 4 + (size_t)R * 4 + (size_t)(bb + 2) * 4 + 64;
 }
 
@@ -620,7 +904,7 @@ int panel_grid(int N, int ldp, int lpad, int num_cu, size_t* lds_bytes, int* ntr
   return G;
 }
 
-void launch_panel(const PanelArgs& a, Exchange ex, int G, int ntr, size_t lds_bytes,
+void launch_panel(const PanelArgs& a, Exchange ex, int G, int ntr, size_t lds_bytes, int spec,
                   hipStream_t s) {
   PanelParams p;
   p.a = a;
@@ -629,6 +913,8 @@ void launch_panel(const PanelArgs& a, Exchange ex, int G, int ntr, size_t lds_by
   p.R = (a.N + G - 1) / G;
   p.ntr = ntr;
   p.ldt = a.ldp;
+  const bool want = spec < 0 ? G >= kSpecMinG : spec != 0;
+  p.spec = (want && p.R <= 64) ? 1 : 0;
   const void* k = prec_f64_storage(a.prec) ? (const void*)panel_kernel<double>
                                      : (const void*)panel_kernel<float>;
   hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);

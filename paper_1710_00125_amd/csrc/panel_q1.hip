@@ -577,7 +577,7 @@ int panel_q1_grid(int N, int ldp, int l, int num_cu, size_t* lds_bytes) {
 }
 
 void launch_panel_q1(const PanelArgs& a, Exchange ex, double* Bq, double* Bnext, int G,
-                     size_t lds_bytes, hipStream_t s) {
+                     size_t lds_bytes, int spec, hipStream_t s) {
   Q1Params p;
   p.a = a;
   p.ex = ex;
@@ -591,7 +591,7 @@ void launch_panel_q1(const PanelArgs& a, Exchange ex, double* Bq, double* Bnext,
   // 14.7 us on none; n = 4096 (grids below 256 after the first block),
   // 11.2 against 10.2 us.  With speculation from G = 256 on: 13.8 us and
   // 10.2 us (from G = 160: 13.7 us and 10.8 us).
-  p.spec = G >= kSpecMinG ? 1 : 0;
+  p.spec = spec < 0 ? (G >= kSpecMinG ? 1 : 0) : (spec != 0 ? 1 : 0);
   const void* k = prec_f64_storage(a.prec) ? (const void*)panel_q1_kernel<double>
                                      : (const void*)panel_q1_kernel<float>;
   hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);

@@ -30,6 +30,7 @@ rcp_stats g_stats;
 int g_recompute = 1;      // r of Algorithm 2 (1: Algorithm 1)
 int g_select_limit = 0;   // bounds on the persistent kernels' grids (0: none)
 int g_panel_limit = 0;
+int g_spec = -1;          // panel speculation: -1 the measured rule, 0 never, 1 always
 
 struct Arena {
   int device = -1;
@@ -208,6 +209,12 @@ int rcp_set_profiling(int32_t on) {
 
 int rcp_set_overlap(int32_t on) {
   g_overlap = on != 0;
+  return 0;
+}
+
+int rcp_set_speculation(int32_t mode) {
+  if (mode < -1 || mode > 1) return -1;
+  g_spec = mode;
   return 0;
 }
 
@@ -516,9 +523,9 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
         // next block's sketch goes to Bn (`partial` is free scratch here)
         size_t lq = 0;
         const int Gq = panel_q1_grid(N, ldp, l, ncu_pan, &lq);
-        launch_panel_q1(pa, ex, partial, Bn, Gq, lq, s);
+        launch_panel_q1(pa, ex, partial, Bn, Gq, lq, g_spec, s);
       } else {
-        launch_panel(pa, ex, Gp, ngr, lds, s);
+        launch_panel(pa, ex, Gp, ngr, lds, g_spec, s);
       }
     }
     RCP_TRY(hipGetLastError());
