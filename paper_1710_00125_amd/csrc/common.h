@@ -144,6 +144,34 @@ __device__ __forceinline__ bool key_better(const ArgKey& a, const ArgKey& b) {
   return a.pos < b.pos;
 }
 
+// Rows of 16 lanes combined into lane 63 with the gfx9 DPP row broadcasts
+// (row_bcast:15 feeds rows 1 and 3 from lane 15 of rows 0 and 2, then
+// row_bcast:31 feeds rows 2 and 3 from lane 31), for a value that is
+// already uniform within each row; read back through a scalar register.
+// Two DPP moves per 32 bits instead of the permlane swaps of xchg<16/32>.
+template <typename Op>
+__device__ __forceinline__ double rows_to_wave(double m, Op op) {
+  unsigned long long u = (unsigned long long)__double_as_longlong(m);
+  int lo = (int)(unsigned)u, hi = (int)(unsigned)(u >> 32);
+  lo = __builtin_amdgcn_update_dpp(lo, lo, 0x142, 0xa, 0xf, false);
+  hi = __builtin_amdgcn_update_dpp(hi, hi, 0x142, 0xa, 0xf, false);
+  m = op(m, __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                             (unsigned long long)(unsigned)lo)));
+  u = (unsigned long long)__double_as_longlong(m);
+  lo = (int)(unsigned)u;
+  hi = (int)(unsigned)(u >> 32);
+  lo = __builtin_amdgcn_update_dpp(lo, lo, 0x143, 0xc, 0xf, false);
+  hi = __builtin_amdgcn_update_dpp(hi, hi, 0x143, 0xc, 0xf, false);
+  m = op(m, __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                             (unsigned long long)(unsigned)lo)));
+  return bcast_lane(m, 63);
+}
+__device__ __forceinline__ int rows_to_wave_min(int p) {
+  p = min(p, __builtin_amdgcn_update_dpp(p, p, 0x142, 0xa, 0xf, false));
+  p = min(p, __builtin_amdgcn_update_dpp(p, p, 0x143, 0xc, 0xf, false));
+  return __builtin_amdgcn_readlane(p, 63);
+}
+
 // argmax over the 64 lanes of a wave; the result is in every lane
 // (in three cheaper passes than a butterfly over whole keys: the maximum
 // value, then the smallest position among the lanes holding it, then the
@@ -154,15 +182,13 @@ __device__ __forceinline__ ArgKey wave_argmax(ArgKey k) {
   m = fmax(m, xchg<2>(m));
   m = fmax(m, xchg<4>(m));
   m = fmax(m, xchg<8>(m));
-  m = fmax(m, xchg<16>(m));
-  m = fmax(m, xchg<32>(m));
+  m = rows_to_wave(m, [](double x, double y) { return fmax(x, y); });
   int p = (k.val == m) ? k.pos : INT_MAX;
   p = min(p, xchg_i<1>(p));
   p = min(p, xchg_i<2>(p));
   p = min(p, xchg_i<4>(p));
   p = min(p, xchg_i<8>(p));
-  p = min(p, xchg_i<16>(p));
-  p = min(p, xchg_i<32>(p));
+  p = rows_to_wave_min(p);
   const unsigned long long who = __ballot(k.val == m && k.pos == p);
   const int src = __ffsll((long long)who) - 1;
   ArgKey r;
