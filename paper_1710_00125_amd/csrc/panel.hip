@@ -174,7 +174,9 @@ __device__ __forceinline__ bool rec_better(const Rec& a, const Rec& b) {
 
 // TA: element type of the stored trailing matrix (double, or float in the
 // reduced-precision modes; values are widened to FP64 on load)
-template <typename TA>
+// SPEC: compiled with the speculative path (otherwise the step-by-step
+// path alone, with the registers of that path only)
+template <typename TA, bool SPEC>
 __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
   __builtin_amdgcn_s_setprio(3);
   const PanelArgs& a = P.a;
@@ -265,7 +267,7 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
     // the first step's speculation: A(s, win[1]), A(win[1], win[0]),
     // A(win[1], win[1])
     const int c1 = bb > 1 ? win[1] : -1;
-    if (P.spec && c1 >= 0) {
+    if (SPEC && P.spec && c1 >= 0) {
       for (int r = tid; r < nown; r += kThreads)
         acolv[R + r] = sym_at(A, ld, (int64_t)(s0 + r), (int64_t)c1);
       if (tid == 64) {
@@ -311,7 +313,11 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
   // win[k]), sh_A11 = A(win[k+1], win[k+1]); true at the block start and
   // after every step of case (0)/(1).
   bool have = false;
-  bool spec_ok = P.spec != 0;
+  bool spec_ok = SPEC && P.spec != 0;
+  // the last eight decisions, 1 for case (0)/(1): a failed speculation costs
+  // about 2.5 times what a kept one saves, so a step speculates only while
+  // at least seven of them kept it (the same in every workgroup)
+  unsigned hist = 0xFFu;
   double akk = 0.0;        // a_kk of the current pivot (the same in every thread)
   double akkprev = 0.0;    // ... of the previous pivot
   ArgKey best{-1.0, INT_MAX, -1};
@@ -369,7 +375,10 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
       if (tid < 4) st_agent(&recs[RCP_REC_STRIDE * g + tid], sh_rec[tid]);
       akk = sh_akk;
     }
-    const bool spec = spec_ok && c1 >= 0;
+    const bool spec = SPEC && spec_ok && c1 >= 0;
+    // the step after this one may speculate only if this one keeps the gate
+    // open (see hist); otherwise the step-by-step path skips its preparation
+    const bool may_spec = SPEC && P.spec != 0 && __builtin_popcount(((hist << 1) | 1u) & 0xFFu) >= 7;
     double lsp = 0.0;                 // largest speculative multiplier of this thread
     ArgKey bestS{-1.0, INT_MAX, -1};  // my best candidate of the next column
     double akkS = 0.0;                // a_kk of c1 (speculation)
@@ -394,7 +403,7 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
       if (tid == 128 && c2 >= 0) {
         sh_A2c = sym_at(A, ld, (int64_t)c2, (int64_t)c);
         sh_A22 = A[(int64_t)c2 * (ld + 1)];
-        sh_A21 = sym_at(A, ld, (int64_t)c2, (int64_t)max(c1, 0));
+        if (may_spec) sh_A21 = sym_at(A, ld, (int64_t)c2, (int64_t)max(c1, 0));
       }
       flush_T();
     } else {
@@ -621,6 +630,7 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
         vcol = vcolS;
         vcolS = t2;
       }
+      hist = ((hist << 1) | 1u) & 0xFFu;
       cur = (cur + 1) % 3;
       best = bestS;
       have = true;
@@ -748,7 +758,7 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
       const double dsum = dot16_lanes(Lsrc, Wr, k, l16);
       if (l16 == 0) sh_vrn = sh_Anr - dsum;
     }
-    if (cn >= 0 && kase <= 1 && c2 >= 0 && (tid >> 6) == 2 && (tid & 63) < 16) {
+    if (cn >= 0 && kase <= 1 && c2 >= 0 && may_spec && (tid >> 6) == 2 && (tid & 63) < 16) {
       // ... and win[k+2]'s entry in column c (its row is the next step's Ln1)
       const double dsum = dot16_lanes(Ln2, Wp, k, l16);
       if (l16 == 0) sh_vn2 = sh_A2c - dsum;
@@ -830,7 +840,7 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
       const double Acc = (cn == c) ? sh_Acc : (cn == c1 ? sh_A11 : sh_A22);
       sh_Acc = Acc;
       sh_akk = Acc - (sh_sold + tail);
-      if (kase <= 1 && c2 >= 0) {
+      if (kase <= 1 && c2 >= 0 && may_spec) {
         // the state the next step's speculation needs (see spec_ok)
         Ln2[kold] = mult_1x1(sh_vn2, dpiv);
         sh_A1c = sh_A21;
@@ -849,7 +859,8 @@ __global__ void __launch_bounds__(kThreads) panel_kernel(PanelParams P) {
       Ln2 = tmp;
     }
     akkprev = akk;
-    spec_ok = P.spec != 0 && kase <= 1;
+    hist = ((hist << 1) | (kase <= 1 ? 1u : 0u)) & 0xFFu;
+    spec_ok = SPEC && P.spec != 0 && kase <= 1 && __builtin_popcount(hist) >= 7;
     cur = (cn == c) ? cur : (cn == c1 ? (cur + 1) % 3 : (cur + 2) % 3);
     __syncthreads();
   }
@@ -915,8 +926,11 @@ void launch_panel(const PanelArgs& a, Exchange ex, int G, int ntr, size_t lds_by
   p.ldt = a.ldp;
   const bool want = spec < 0 ? G >= kSpecMinG : spec != 0;
   p.spec = (want && p.R <= 64) ? 1 : 0;
-  const void* k = prec_f64_storage(a.prec) ? (const void*)panel_kernel<double>
-                                     : (const void*)panel_kernel<float>;
+  const bool f64 = prec_f64_storage(a.prec);
+  const void* k = p.spec ? (f64 ? (const void*)panel_kernel<double, true>
+                                : (const void*)panel_kernel<float, true>)
+                         : (f64 ? (const void*)panel_kernel<double, false>
+                                : (const void*)panel_kernel<float, false>);
   hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
   void* args[] = {&p};
   hipLaunchCooperativeKernel(k, dim3(G), dim3(kThreads), args, lds_bytes, s);

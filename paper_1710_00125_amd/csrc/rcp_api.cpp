@@ -448,6 +448,8 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
   int status = 0;
   bool update_in_flight = false;
   bool selected = false;   // the selection of the current block is enqueued
+  bool spec_next = true;   // speculate in the next panel (rcp_set_speculation(-1))
+  long long seen_c23 = 0, seen_tot = 0;   // SBKP decision counts so far
   auto enqueue_select = [&](int Nb) {
     Scope sc(KSelect);
     const int Gs = select_grid(Nb, lpad, ncu_sel);
@@ -525,7 +527,7 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
         const int Gq = panel_q1_grid(N, ldp, l, ncu_pan, &lq);
         launch_panel_q1(pa, ex, partial, Bn, Gq, lq, g_spec, s);
       } else {
-        launch_panel(pa, ex, Gp, ngr, lds, g_spec, s);
+        launch_panel(pa, ex, Gp, ngr, lds, g_spec >= 0 ? g_spec : (spec_next ? 1 : 0), s);
       }
     }
     RCP_TRY(hipGetLastError());
@@ -543,6 +545,18 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
     if (m < 1 || m > bb + 1 || K0 + m > n) {
       status = RCP_EABORT;
       break;
+    }
+    {
+      // the rule for the next block's panel (speculation left to the
+      // measured rule): speculate unless more than one decision in eight of
+      // this block took SBKP case (2) or (3), where a failed speculation
+      // costs more than the kept ones save; the same results either way
+      const long long c23 = g_ctrl_host->ncase[2] + g_ctrl_host->ncase[3];
+      const long long tot = c23 + g_ctrl_host->ncase[0] + g_ctrl_host->ncase[1];
+      const long long dc = c23 - seen_c23, dt = tot - seen_tot;
+      spec_next = 8 * dc <= dt;
+      seen_c23 = c23;
+      seen_tot = tot;
     }
     const int64_t K1 = K0 + m;
     const int N2 = N - m;

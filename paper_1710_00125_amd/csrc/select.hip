@@ -92,6 +92,7 @@ __global__ void __launch_bounds__(kThreads) select_kernel(SelectParams a) {
   __syncthreads();
 
   const int nsteps = min(min(a.bb, l), a.N);
+  const bool idx_first = a.G >= 256;   // poll the index word alone while waiting
   for (int j = 0; j < nsteps; ++j) {
     const int par = j & 1;
     // ---- my best untaken column (position >= j) by squared residual norm
@@ -126,13 +127,16 @@ __global__ void __launch_bounds__(kThreads) select_kernel(SelectParams a) {
       unsigned long long w0 = 0, w1 = 0;
       unsigned int spins = 0;
       for (;;) {
-        // the index word alone until it is current (the writer stores it
-        // last), then the value word: one load per probe while waiting.
-        // Halving the probes' traffic made the selection 3 % faster beside
-        // the trailing update, and the update 10 % faster beside it.
+        // on the full grid, the index word alone until it is current (the
+        // writer stores it last), then the value word: one load per probe
+        // while waiting.  Halving the probes' traffic there made the
+        // selection 3 % faster beside the trailing update (and the update
+        // 10 % faster beside it); on smaller grids the extra round trip
+        // costs more than it saves.
         w1 = ld_agent(&rec[kRecStride * w + 1]);
+        if (!idx_first) w0 = ld_agent(&rec[kRecStride * w]);
         if (rec_index_current(w1, j)) {
-          w0 = ld_agent(&rec[kRecStride * w]);
+          if (idx_first) w0 = ld_agent(&rec[kRecStride * w]);
           if (rec_tag_current(w0, j)) break;
         }
         if ((++spins & 1023u) == 0) {
@@ -323,6 +327,7 @@ __global__ void __launch_bounds__(kThreads) select_reg_kernel(SelectParams a) {
   __syncthreads();
 
   const int nsteps = min(min(a.bb, l), a.N);
+  const bool idx_first = a.G >= 256;   // poll the index word alone while waiting
   for (int j = 0; j < nsteps; ++j) {
     const int par = j & 1;
     // ---- my best untaken column (position >= j) by squared residual norm
@@ -359,11 +364,11 @@ __global__ void __launch_bounds__(kThreads) select_reg_kernel(SelectParams a) {
       unsigned long long w0 = 0, w1 = 0;
       unsigned int spins = 0;
       for (;;) {
-        // the index word alone until it is current (the writer stores it
-        // last), then the value word: one load per probe while waiting
+        // (index word first on the full grid: see select_kernel)
         w1 = ld_agent(&rec[kRecStride * w + 1]);
+        if (!idx_first) w0 = ld_agent(&rec[kRecStride * w]);
         if (rec_index_current(w1, j)) {
-          w0 = ld_agent(&rec[kRecStride * w]);
+          if (idx_first) w0 = ld_agent(&rec[kRecStride * w]);
           if (rec_tag_current(w0, j)) break;
         }
         if ((++spins & 1023u) == 0) {
