@@ -29,6 +29,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kColsPerPass = 64;   // a quad of lanes per column
 constexpr int kRecStride = RCP_REC_STRIDE;
+constexpr int kIdxFirstG = 256;   // grids at least this large poll index-first
 
 struct SelectParams {
   const double* B;
@@ -45,6 +46,9 @@ __device__ __forceinline__ double quad_sum(double v) {
   return v;
 }
 
+// IDX_FIRST: poll a record's index word alone until it is current (the
+// full grid); a compile-time choice, so that each loop stays branch-free
+template <bool IDX_FIRST>
 __global__ void __launch_bounds__(kThreads) select_kernel(SelectParams a) {
   // issue priority over the trailing update's waves that share the CU
   __builtin_amdgcn_s_setprio(3);
@@ -92,7 +96,6 @@ __global__ void __launch_bounds__(kThreads) select_kernel(SelectParams a) {
   __syncthreads();
 
   const int nsteps = min(min(a.bb, l), a.N);
-  const bool idx_first = a.G >= 256;   // poll the index word alone while waiting
   for (int j = 0; j < nsteps; ++j) {
     const int par = j & 1;
     // ---- my best untaken column (position >= j) by squared residual norm
@@ -134,9 +137,9 @@ __global__ void __launch_bounds__(kThreads) select_kernel(SelectParams a) {
         // 10 % faster beside it); on smaller grids the extra round trip
         // costs more than it saves.
         w1 = ld_agent(&rec[kRecStride * w + 1]);
-        if (!idx_first) w0 = ld_agent(&rec[kRecStride * w]);
+        if (!IDX_FIRST) w0 = ld_agent(&rec[kRecStride * w]);
         if (rec_index_current(w1, j)) {
-          if (idx_first) w0 = ld_agent(&rec[kRecStride * w]);
+          if (IDX_FIRST) w0 = ld_agent(&rec[kRecStride * w]);
           if (rec_tag_current(w0, j)) break;
         }
         if ((++spins & 1023u) == 0) {
@@ -280,6 +283,7 @@ __device__ __forceinline__ void sum16_cols(double (&x)[kRegCols]) {
   for (int e = 0; e < kRegCols; ++e) x[e] += y[e];
 }
 
+template <bool IDX_FIRST>
 __global__ void __launch_bounds__(kThreads) select_reg_kernel(SelectParams a) {
   __builtin_amdgcn_s_setprio(3);
   extern __shared__ int win[];   // [bb + 2]
@@ -327,7 +331,6 @@ __global__ void __launch_bounds__(kThreads) select_reg_kernel(SelectParams a) {
   __syncthreads();
 
   const int nsteps = min(min(a.bb, l), a.N);
-  const bool idx_first = a.G >= 256;   // poll the index word alone while waiting
   for (int j = 0; j < nsteps; ++j) {
     const int par = j & 1;
     // ---- my best untaken column (position >= j) by squared residual norm
@@ -366,9 +369,9 @@ __global__ void __launch_bounds__(kThreads) select_reg_kernel(SelectParams a) {
       for (;;) {
         // (index word first on the full grid: see select_kernel)
         w1 = ld_agent(&rec[kRecStride * w + 1]);
-        if (!idx_first) w0 = ld_agent(&rec[kRecStride * w]);
+        if (!IDX_FIRST) w0 = ld_agent(&rec[kRecStride * w]);
         if (rec_index_current(w1, j)) {
-          if (idx_first) w0 = ld_agent(&rec[kRecStride * w]);
+          if (IDX_FIRST) w0 = ld_agent(&rec[kRecStride * w]);
           if (rec_tag_current(w0, j)) break;
         }
         if ((++spins & 1023u) == 0) {
@@ -501,16 +504,18 @@ void launch_select(const double* B, int lpad, int l, int N, int bb, int* posof, 
   p.win = win;
   p.ex = ex;
   void* args[] = {&p};
+  const bool idx_first = G >= kIdxFirstG;
   if (select_uses_registers(l, p.R, G)) {
     const size_t lds = select_lds_bytes(l, lpad, p.R, bb, true);
-    hipLaunchCooperativeKernel((const void*)select_reg_kernel, dim3(G), dim3(kThreads), args, lds,
-                               s);
+    const void* k = idx_first ? (const void*)select_reg_kernel<true>
+                              : (const void*)select_reg_kernel<false>;
+    hipLaunchCooperativeKernel(k, dim3(G), dim3(kThreads), args, lds, s);
     return;
   }
   const size_t lds = select_lds_bytes(l, lpad, p.R, bb, false);
-  hipFuncSetAttribute((const void*)select_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)lds);
-  hipLaunchCooperativeKernel((const void*)select_kernel, dim3(G), dim3(kThreads), args, lds, s);
+  const void* k = idx_first ? (const void*)select_kernel<true> : (const void*)select_kernel<false>;
+  hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchCooperativeKernel(k, dim3(G), dim3(kThreads), args, lds, s);
 }
 
 }  // namespace rcp
