@@ -309,15 +309,20 @@ def q1_run(rcp, A, b, cfg, args, fp64_ms):
         f, x, st = step()
         sts.append(st)
         _log(f"bench: q=1 step {s + 1}/{args.steps}: factor {st['ms_total']:.1f} ms, "
-             f"panel {st['ms_panel']:.1f} ms, update {st['ms_update']:.1f} ms")
+             f"update {st['ms_update']:.1f} ms")
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
     r = A @ x - b
     berr = (r.abs().max(dim=0).values /
             (A.abs().sum(dim=1).max() * x.abs().max(dim=0).values)).max().item()
-    avg = {k: round(sum(s_[k] for s_ in sts) / len(sts), 3)
-           for k in ("ms_total", "ms_panel", "ms_update", "ms_commit", "ms_solve")}
+    del f
+    rcp.rcp_set_profiling(1)   # the breakdown: one extra, fully profiled step
+    _, _, pst = step()
+    rcp.rcp_set_profiling(2)
+    avg = {k: round(pst[k], 3) for k in ("ms_total", "ms_panel", "ms_update", "ms_commit",
+                                         "ms_solve")}
+    avg["note"] = "one extra factor + solve after the timed steps, every launch timed"
     return {"q": 1, "b": cfg.b, "p": p, "l": 1 + p, "ms_per_step": round(ms, 3),
             "value": round((n ** 3 / 3.0) / (ms * 1e-3) / 1e12, 4), "unit": "TFLOP/s",
             "speedup_vs_q_b": round(fp64_ms / ms, 3), "backward_error": berr,
@@ -387,7 +392,11 @@ def main():
     b = torch.from_numpy(rhs_host).to(dev)
     del A_host
     rcp.load()
-    rcp.rcp_set_profiling(True)
+    # events around the trailing update's launches only (on its own stream):
+    # the roofline's kernel time, measured live, with the critical path left
+    # as it is; the per-class breakdown comes from one extra, fully profiled
+    # factorization after the timed region (those events cost about 2 %)
+    rcp.rcp_set_profiling(2)
 
     def step():
         f = rcp.rcp_factor(A, cfg.b, cfg.p, cfg.seed)
@@ -407,8 +416,7 @@ def main():
         f, x, st = step()
         stats.append(st)
         _log(f"bench: step {s + 1}/{args.steps}: factor {st['ms_total']:.1f} ms, "
-             f"update {st['ms_update']:.1f} ms, panel {st['ms_panel']:.1f} ms, "
-             f"select {st['ms_select']:.1f} ms")
+             f"update {st['ms_update']:.1f} ms")
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
@@ -433,10 +441,15 @@ def main():
     iso_ms = rcp.rcp_get_stats()["ms_update"]
     rcp.rcp_set_overlap(True)
     traffic = measured_traffic() if args.config == "householder16384" else None
-    breakdown = {k: round(sum(s[k] for s in stats) / len(stats), 3)
+    _log("bench: one extra factor + solve with every launch timed (kernel_ms)")
+    rcp.rcp_set_profiling(1)
+    _, _, pst = step()
+    rcp.rcp_set_profiling(2)
+    breakdown = {k: round(pst[k], 3)
                  for k in ("ms_total", "ms_omega", "ms_sketch", "ms_select", "ms_panel",
                            "ms_sketch_update", "ms_commit", "ms_update", "ms_finalize",
                            "ms_solve")}
+    breakdown["note"] = "one extra factor + solve after the timed steps, every launch timed"
     out = {
         "metric": "RCP factor+solve TFLOP/s at n=16384: FP64 vs FP32/BF16+IR at 1e-13 bwd error",
         "value": round(value, 4),

@@ -108,9 +108,14 @@ typedef struct rcp_launch_info {
  * NULL selects the null stream.  Returns 0. */
 int rcp_set_stream(void* hip_stream);
 
-/* Bracket every kernel launch with HIP events and report per-kernel times
- * in rcp_stats (on = 1) or not (on = 0, the default).  Returns 0. */
-int rcp_set_profiling(int32_t on);
+/* Per-kernel times in rcp_stats.  mode = 1: every kernel launch of a
+ * factorization is bracketed with HIP events (each pair leaves a short gap
+ * between launches: about 2 % on a factorization of n = 16384); 2: only the
+ * trailing-update launches, on the stream they run on (ms_update alone; the
+ * critical path is left as it is); 0 (the default): none.  In modes 1 and 2
+ * a solve is timed as a whole (ms_solve).  ms_total is always measured.
+ * Returns 0, or -1 for another mode. */
+int rcp_set_profiling(int32_t mode);
 
 /* Run the trailing update of block j on a second stream, concurrently with
  * the pivot selection of block j+1 (on = 1, the default), or strictly after

@@ -187,8 +187,13 @@ def rcp_set_stream(stream=None):
     return load().rcp_set_stream(ctypes.c_void_p(handle))
 
 
-def rcp_set_profiling(on):
-    return load().rcp_set_profiling(1 if on else 0)
+def rcp_set_profiling(mode):
+    """mode 1 (or True): time every kernel launch, 2: the trailing update's
+    launches only, 0 (or False): none."""
+    rc = load().rcp_set_profiling(int(mode))
+    if rc != 0:
+        raise ValueError(f"rcp_set_profiling: mode {mode} is not 0, 1 or 2")
+    return rc
 
 
 def rcp_set_overlap(on):

@@ -24,7 +24,7 @@ using namespace rcp;
 namespace {
 
 hipStream_t g_stream = nullptr;
-bool g_prof = false;
+int g_prof = 0;            // 0 off, 1 every kernel class, 2 the trailing update only
 bool g_overlap = true;
 rcp_stats g_stats;
 int g_recompute = 1;      // r of Algorithm 2 (1: Algorithm 1)
@@ -93,14 +93,16 @@ struct Scope {
   int cls;
   int e0 = -1;
   hipStream_t st;
-  explicit Scope(int c, hipStream_t stream = nullptr) : cls(c), st(stream ? stream : g_stream) {
-    if (g_prof) {
+  bool on;
+  explicit Scope(int c, hipStream_t stream = nullptr)
+      : cls(c), st(stream ? stream : g_stream), on(g_prof == 1 || (g_prof == 2 && c == KUpdate)) {
+    if (on) {
       e0 = (int)g_profiler.used;
       hipEventRecord(g_profiler.get(), st);
     }
   }
   ~Scope() {
-    if (g_prof) {
+    if (on) {
       const int e1 = (int)g_profiler.used;
       hipEventRecord(g_profiler.get(), st);
       g_profiler.marks.push_back({cls, {e0, e1}});
@@ -202,8 +204,9 @@ int rcp_set_stream(void* hip_stream) {
   return 0;
 }
 
-int rcp_set_profiling(int32_t on) {
-  g_prof = on != 0;
+int rcp_set_profiling(int32_t mode) {
+  if (mode < 0 || mode > 2) return -1;
+  g_prof = mode;
   return 0;
 }
 
@@ -722,7 +725,7 @@ int solve_impl(int64_t n, const void* L, int l_f32, const double* D, const int8_
   double* Y = g_solve.take<double>(solve_work_doubles(n, nrhs));
   unsigned int* sync = g_solve.take<unsigned int>(words);
   int* zp = g_solve.take<int>(16);
-  return solve_core(n, L, l_f32, D, ipiv, perm, nrhs, B, ldb, Y, sync, zp, g_prof);
+  return solve_core(n, L, l_f32, D, ipiv, perm, nrhs, B, ldb, Y, sync, zp, g_prof != 0);
 }
 
 // ---- the solve without device allocation (rcp_solve_noalloc)

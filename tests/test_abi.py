@@ -180,3 +180,23 @@ def test_release_without_device_work():
         pytest.skip("librcp.so not built")
     assert pkg.rcp_release() == 0
     assert pkg.rcp_release() == 0
+
+
+def test_mode_setters_validate_without_gpu():
+    # pure setters: no device call; an unknown mode is refused and changes
+    # nothing
+    import paper_1710_00125_amd as pkg
+    if not os.path.exists(pkg.lib_path()):
+        pytest.skip("librcp.so not built")
+    lib = pkg.load()
+    for bad in (-1, 3):
+        assert lib.rcp_set_profiling(bad) == -1
+    for good in (1, 2, 0):
+        assert lib.rcp_set_profiling(good) == 0
+    for bad in (-2, 2):
+        assert lib.rcp_set_speculation(bad) == -1
+    for good in (0, 1, -1):
+        assert lib.rcp_set_speculation(good) == 0
+    with pytest.raises(ValueError):
+        pkg.rcp_set_profiling(5)
+    pkg.rcp_set_profiling(False)
