@@ -20,97 +20,97 @@ namespace {
 
 // ---------------------------------------------------------------------------
 // Bnext(:, i - m) = B(:, srcat[i]) - T L(srcat[i], 0:m)^T for i in [m, N).
-// A workgroup owns 64 output columns i and every sketch row; the product is
-// formed transposed, C(i, r) = sum_t L(i, t) T(r, t), so that the 16 lanes
-// of an accumulator column hold 16 consecutive sketch rows and the stores
-// are contiguous.  Both operands go through LDS in chunks of 32 k values:
-// L rows (64 x 32, negated) and T columns (lpad x 32).  Wave w owns columns
-// 16 w .. 16 w + 15 and all row fragments; its accumulators start from the
-// old sketch columns.
+// A workgroup owns 64 output columns i (blockIdx.x) and FR row fragments of
+// 16 sketch rows (blockIdx.y: fragments FR y .. FR y + FR - 1).  The product
+// is formed transposed, C(i, r) = sum_t L(i, t) T(r, t), so that the 16
+// lanes of an accumulator column hold 16 consecutive sketch rows and the
+// stores are contiguous.  Both operands go through LDS in chunks of 32 k
+// values: L rows (64 x 32, negated) and the group's T columns (16 FR x 32).
+// Wave w owns columns 16 w .. 16 w + 15; its accumulators start from the
+// old sketch columns.  Splitting the rows over workgroups keeps the grid
+// (and every CU's matrix cores) busy at every trailing size, and the small
+// accumulator sets let several workgroups share a CU.
 // ---------------------------------------------------------------------------
 constexpr int kSuCols = 64;
 constexpr int kSuK = 32;
-constexpr int kSuMaxRowFrags = (kMaxL + 15) / 16;   // 32
+constexpr int kSuMaxFR = 4;   // row fragments per workgroup at most
 
-template <int NRF>
+template <int FR>
 __global__ void __launch_bounds__(256) sketch_update_kernel(
     const double* __restrict__ B, int lpad, int l, const int* __restrict__ srcat, int m, int N,
     const double* __restrict__ Lp, int ldp, const double* __restrict__ T,
     double* __restrict__ Bnext) {
-  extern __shared__ double smem[];
-  double* Ls = smem;                          // [64][kSuK + 1]   L(i, t)
-  double* Ts = Ls + kSuCols * (kSuK + 1);     // [kSuK][lpad + 1] T(r, t) by t
-  const int ldt = lpad + 1;
+  constexpr int kRows = 16 * FR;            // sketch rows of the group
+  constexpr int kLdt = kRows + 1;           // LDS row stride of T
+  constexpr int kTP = kSuK * kRows / 256;   // T elements per thread per chunk (2 FR)
+  __shared__ double Ls[kSuCols * (kSuK + 1)];   // L(i, t), negated
+  __shared__ double Ts[kSuK * kLdt];            // T(r, t) by t
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int i0 = m + blockIdx.x * kSuCols;
+  const int f0 = FR * blockIdx.y;           // the group's first fragment
+  const int rb = 16 * f0;                   // ... and first sketch row
   const int nrf = lpad / 16;
-  // the accumulators start from the old sketch columns B(:, srcat[i]) (all
-  // reads issued before the k loop) and the staged L is negated, so the
-  // epilogue only stores; acc[f]: lane l, element v = (column
-  // 16 w + acc_row(l, v), row 16 f + l%16)
-  rcp_d4 acc[NRF];
-  {
-    int sv[4];
+  // acc[f]: lane l, element v = (column 16 w + acc_row(l, v), row
+  // rb + 16 f + l%16)
+  rcp_d4 acc[FR];
+  int sv[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) sv[v] = srcat[min(i0 + 16 * w + acc_row(lane, v), N - 1)];
-#pragma unroll
-    for (int f = 0; f < NRF; ++f) {
-      const int r = 16 * f + acc_col(lane);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const double x = B[(size_t)sv[v] * lpad + min(r, l - 1)];
-        acc[f][v] = (f < nrf && r < l) ? x : 0.0;
-      }
-    }
-  }
-  // staging: every thread issues all its loads of a chunk before its first
-  // LDS store.  L: thread tid takes column tid / 4 (its source read once)
-  // and 8 consecutive k values; T: 8 elements per thread per pass.
+  for (int v = 0; v < 4; ++v) sv[v] = srcat[min(i0 + 16 * w + acc_row(lane, v), N - 1)];
   const int cc = tid >> 2, t8 = (tid & 3) * 8;
   const int isrc = srcat[min(i0 + cc, N - 1)];
   const bool col_ok = i0 + cc < N;
-  for (int k0 = 0; k0 < m; k0 += kSuK) {
+  // The loads have clamped addresses and no condition (a branch around a
+  // load would be waited for at its end, a round trip per element); the
+  // masks are applied when the values are stored to LDS.  Fragments past
+  // nrf take no products and are not stored, and rows r >= l are stored as
+  // zeros whatever they hold (every output element is its own sum).
+  double lv[8], tv[kTP];
+  auto fetch = [&](int k0) {
     const int kn = min(kSuK, m - k0);
-    double lv[8];
     const double* lrow = Lp + (size_t)isrc * ldp + k0;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int t = t8 + u;
-      const double x = lrow[min(t, kn - 1)];
-      lv[u] = (col_ok && t < kn) ? -x : 0.0;
+    for (int u = 0; u < 8; ++u) lv[u] = lrow[min(t8 + u, kn - 1)];
+#pragma unroll
+    for (int u = 0; u < kTP; ++u) {
+      const int e = tid + 256 * u;          // chunk row t, group row rr
+      const int t = e / kRows, rr = e - t * kRows;
+      tv[u] = T[(size_t)(k0 + min(t, kn - 1)) * lpad + min(rb + rr, lpad - 1)];
     }
+  };
+  auto stage = [&](int k0) {
+    const int kn = min(kSuK, m - k0);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      Ls[cc * (kSuK + 1) + t8 + u] = (col_ok && t8 + u < kn) ? -lv[u] : 0.0;
+#pragma unroll
+    for (int u = 0; u < kTP; ++u) {
+      const int e = tid + 256 * u;
+      const int t = e / kRows, rr = e - t * kRows;
+      Ts[t * kLdt + rr] = (t < kn) ? tv[u] : 0.0;
+    }
+  };
+  // the first chunk's loads go out with the accumulators', one round trip
+  fetch(0);
+#pragma unroll
+  for (int f = 0; f < FR; ++f) {
+    const int r = rb + 16 * f + acc_col(lane);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[f][v] = B[(size_t)sv[v] * lpad + min(r, l - 1)];
+  }
+  for (int k0 = 0; k0 < m; k0 += kSuK) {
     __syncthreads();   // the previous chunk's products are done with Ls, Ts
-#pragma unroll
-    for (int u = 0; u < 8; ++u) Ls[cc * (kSuK + 1) + t8 + u] = lv[u];
-    const int tot = kSuK * lpad;
-    for (int e0 = 0; e0 < tot; e0 += 256 * 8) {
-      double tv[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = min(e0 + tid + 256 * u, tot - 1);
-        const int t = e / lpad, r = e - t * lpad;
-        const double x = T[(size_t)(k0 + min(t, kn - 1)) * lpad + r];
-        tv[u] = (t < kn) ? x : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + tid + 256 * u;
-        if (e < tot) {
-          const int t = e / lpad, r = e - t * lpad;
-          Ts[t * ldt + r] = tv[u];
-        }
-      }
-    }
+    stage(k0);
     __syncthreads();
+    if (k0 + kSuK < m) fetch(k0 + kSuK);   // in flight during the products
 #pragma unroll
     for (int q = 0; q < kSuK / 4; ++q) {
       const int t = 4 * q + frag_k(lane);
-      // A operand: L(column 16 w + l%16, t); B operand: T(row 16 f + l%16, t)
+      // A operand: L(column 16 w + l%16, t); B operand: T(row rb + 16 f + l%16, t)
       const double av = Ls[(16 * w + frag_row(lane)) * (kSuK + 1) + t];
 #pragma unroll
-      for (int f = 0; f < NRF; ++f) {
-        if (f < nrf) {
-          const double bv = Ts[t * ldt + 16 * f + frag_col(lane)];
+      for (int f = 0; f < FR; ++f) {
+        if (f0 + f < nrf) {
+          const double bv = Ts[t * kLdt + 16 * f + frag_col(lane)];
           acc[f] = mfma16x16x4(av, bv, acc[f]);
         }
       }
@@ -121,9 +121,9 @@ __global__ void __launch_bounds__(256) sketch_update_kernel(
     const int i = i0 + 16 * w + acc_row(lane, v);
     if (i >= N) continue;
 #pragma unroll
-    for (int f = 0; f < NRF; ++f) {
-      if (f < nrf) {
-        const int r = 16 * f + acc_col(lane);
+    for (int f = 0; f < FR; ++f) {
+      if (f0 + f < nrf) {
+        const int r = rb + 16 * f + acc_col(lane);
         Bnext[(size_t)(i - m) * lpad + r] = (r < l) ? acc[f][v] : 0.0;
       }
     }
@@ -345,20 +345,19 @@ void launch_sketch_update(const double* B, int lpad, int l, const int* srcat, in
                           hipStream_t s) {
   const int N2 = N - m;
   if (N2 <= 0) return;
-  const size_t lds = ((size_t)kSuCols * (kSuK + 1) + (size_t)kSuK * (lpad + 1)) * 8;
-  const dim3 grid((N2 + kSuCols - 1) / kSuCols);
+  // row groups of at most kSuMaxFR fragments, as even as the count allows
+  const int nrf = lpad / 16;
+  const int groups = (nrf + kSuMaxFR - 1) / kSuMaxFR;
+  const int fr = (nrf + groups - 1) / groups;
+  const dim3 grid((N2 + kSuCols - 1) / kSuCols, groups);
   auto go = [&](auto kern) {
-    hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, B, lpad, l, srcat, m, N, Lpanel, ldp, T,
+    hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, B, lpad, l, srcat, m, N, Lpanel, ldp, T,
                        Bnext);
   };
-  // accumulators sized for the sketch height (lpad / 16 fragments)
-  const int nrf = lpad / 16;
-  if (nrf <= 4) go(sketch_update_kernel<4>);
-  else if (nrf <= 8) go(sketch_update_kernel<8>);
-  else if (nrf <= 12) go(sketch_update_kernel<12>);
-  else if (nrf <= 16) go(sketch_update_kernel<16>);
-  else go(sketch_update_kernel<kSuMaxRowFrags>);
+  if (fr == 1) go(sketch_update_kernel<1>);
+  else if (fr == 2) go(sketch_update_kernel<2>);
+  else if (fr == 3) go(sketch_update_kernel<3>);
+  else go(sketch_update_kernel<4>);
 }
 
 // k steps of the trailing update, rounded up to an even count (the update
