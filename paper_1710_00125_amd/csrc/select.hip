@@ -304,7 +304,11 @@ __global__ void __launch_bounds__(kThreads) select_reg_kernel(SelectParams a) {
   const int s0 = g * a.R;
   const int nown = max(0, min(a.R, a.N - s0));
 
-  // my columns' rows
+  // my columns' rows: every load issued before any is waited for.  The
+  // condition is a factor of 1 or 0 rather than a choice (a choice lets the
+  // compiler branch around each load and wait for it at the branch's end, a
+  // round trip per element); a zero factor leaves a signed zero, which no
+  // norm, reflection or comparison below tells from +0.
   double d[kRegRows][kRegCols];
   if (tid < 16 * kRegCols) posl[tid] = (tid < nown) ? s0 + tid : -1;
 #pragma unroll
@@ -315,7 +319,7 @@ __global__ void __launch_bounds__(kThreads) select_reg_kernel(SelectParams a) {
     for (int u = 0; u < kRegRows; ++u) {
       const int i = rq + 16 * u;
       const double bv = col[min(i, l - 1)];
-      d[u][e] = (c < nown && i < l) ? bv : 0.0;
+      d[u][e] = bv * ((c < nown && i < l) ? 1.0 : 0.0);
     }
   }
   for (int t = tid; t <= a.bb; t += kThreads) win[t] = t;
