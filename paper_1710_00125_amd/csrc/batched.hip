@@ -123,9 +123,11 @@ __device__ __forceinline__ void swp(T& a, T& b) {
   b = t;
 }
 
+// (the address is chosen, then loaded: one load with no branch around it)
 template <typename TA>
 __device__ __forceinline__ double symw(const TA* W, int n, int i, int j) {
-  return (double)((i >= j) ? W[i + (int64_t)j * n] : W[j + (int64_t)i * n]);
+  const int64_t e = (i >= j) ? i + (int64_t)j * n : j + (int64_t)i * n;
+  return (double)W[e];
 }
 
 template <typename TA>
@@ -249,17 +251,21 @@ __device__ void swap_positions(Sys<TA>& S, int p, int q, int kc, int kk) {
 }
 
 // W row (L D) of position c over the block's first kk columns, into dst
+// (every operand any kind of column needs is loaded, from clamped
+// addresses, together with the kind: one round trip, then the choice)
 template <typename TA>
 __device__ void w_row(const Sys<TA>& S, int c, int kk, double* dst) {
   const int K0 = S.K0, n = S.n;
   const double* x = S.Lp + c * kBldp;
   for (int t = threadIdx.x; t < kk; t += kBT) {
+    const int tp = max(t - 1, 0), tn = min(t + 1, kk - 1);
     const int kd = S.ipiv[K0 + t];
-    double w;
-    if (kd == 1) w = x[t] * S.D[K0 + t];
-    else if (kd == 2) w = fma(x[t], S.D[K0 + t], x[t + 1] * S.D[n + K0 + t]);
-    else w = fma(x[t - 1], S.D[n + K0 + t - 1], x[t] * S.D[K0 + t]);
-    dst[t] = w;
+    const double x0 = x[t], xn = x[tn], xp = x[tp];
+    const double d0 = S.D[K0 + t], dn = S.D[n + K0 + t], dp = S.D[n + K0 + tp];
+    // all three forms computed, then chosen (a choice between computed
+    // values leaves no load to sink into a branch)
+    const double w1 = x0 * d0, w2 = fma(x0, d0, xn * dn), w3 = fma(xp, dp, x0 * d0);
+    dst[t] = (kd == 1) ? w1 : ((kd == 2) ? w2 : w3);
   }
 }
 
@@ -818,17 +824,19 @@ __global__ void __launch_bounds__(kBT) batched_kernel(KernelArgs a) {
     const double anorm = rs_max;
     for (;;) {
       // r = b - A x, in FP64 from the input matrix
-      // (all right-hand sides share each load of A; the loads of eight
+      // (all right-hand sides share each load of A; the loads of four
       // consecutive j are issued together)
       static_assert(kBatchMaxRhs <= 4, "residual accumulators");
       for (int i = tid; i < n; i += kBT) {
         double s[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 8
+#pragma unroll 4
         for (int j = 0; j < n; ++j) {
           const double av = A[(j <= i) ? i + (int64_t)j * n : j + (int64_t)i * n];
+          // every slot from a clamped column (slots c >= nrhs are not
+          // stored): no branch around the loads
 #pragma unroll
           for (int c = 0; c < 4; ++c)
-            if (c < nrhs) s[c] = fma(av, S.x[j + (int64_t)c * n], s[c]);
+            s[c] = fma(av, S.x[j + (int64_t)min(c, nrhs - 1) * n], s[c]);
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c)
@@ -929,11 +937,14 @@ __device__ void blocked_solve(Sys<TA>& S, int nrhs, double* yv, Shared& sh) {
     }
     __syncthreads();
     for (int i = j0 + jn + tid; i < n; i += kBT) {
+      // four slots whatever nrhs (slots c >= nrhs are not stored), so that
+      // the loads of consecutive t are not separated by a loop
       double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 8
       for (int t = 0; t < jn; ++t) {
         const double lv = (double)S.Lw[i + (int64_t)(j0 + t) * n];
-        for (int c = 0; c < nrhs; ++c) acc[c] = fma(lv, sh.s.yb[c][t], acc[c]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] = fma(lv, sh.s.yb[min(c, nrhs - 1)][t], acc[c]);
       }
       for (int c = 0; c < nrhs; ++c) tmp[i + (int64_t)c * n] -= acc[c];
     }
@@ -968,7 +979,10 @@ __device__ void blocked_solve(Sys<TA>& S, int nrhs, double* yv, Shared& sh) {
 #pragma unroll 8
         for (int i = j0 + jn + qtr; i < n; i += 4) {
           const double lv = (double)S.Lw[i + (int64_t)(j0 + t) * n];
-          for (int c = 0; c < nrhs; ++c) acc[c] = fma(lv, tmp[i + (int64_t)c * n], acc[c]);
+          // four slots from clamped columns (as in the forward update)
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            acc[c] = fma(lv, tmp[i + (int64_t)min(c, nrhs - 1) * n], acc[c]);
         }
       for (int c = 0; c < nrhs; ++c) sh.s.part[qtr][c][t] = acc[c];
     }
