@@ -249,7 +249,10 @@ __global__ void __launch_bounds__(256) trsv_chain_kernel(int64_t n, int nrhs,
 
   const int64_t ntile = lower ? K : nb - 1 - K;   // tiles before K in solve order
   auto tile_j0 = [&](int64_t q) { return (lower ? q : nb - 1 - q) * kBlk; };
-  // my 16 L values of tile q: zero outside the matrix, addresses clamped in
+  // my 16 L values of tile q: zero outside the matrix, addresses clamped in.
+  // The bounds enter as a factor of 1 or 0, not as a choice: a choice on
+  // the wave-uniform column bound lets the compiler branch around each load
+  // and wait for it there, which would serialize the tile's loads.
   auto load_l = [&](int64_t q, TL (&lv)[16]) {
     const int64_t j0 = tile_j0(q);
     const int jn = (int)std::min<int64_t>(kBlk, n - j0);
@@ -260,7 +263,7 @@ __global__ void __launch_bounds__(256) trsv_chain_kernel(int64_t n, int nrhs,
     for (int u = 0; u < 16; ++u) {
       const int col = grp + 4 * u;
       const TL v = L[row + (c0 + min(col, cn - 1)) * n];
-      lv[u] = (lane < rn && col < cn) ? v : (TL)0;
+      lv[u] = v * ((lane < rn && col < cn) ? (TL)1 : (TL)0);
     }
   };
   // the Z entries of tile q, one row per lane (rows past the end repeat the
