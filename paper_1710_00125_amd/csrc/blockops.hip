@@ -133,6 +133,8 @@ __global__ void __launch_bounds__(256) sketch_update_kernel(
 // ---------------------------------------------------------------------------
 // Commit of one block.
 // ---------------------------------------------------------------------------
+// Entry t of the W row (L D) of the L row x: the loads the pivot kind
+// needs, after the kind's (for one entry per thread, the fewest loads).
 __device__ __forceinline__ double w_of_row(const double* __restrict__ x, const double* __restrict__ Dg,
                                            const int8_t* __restrict__ ipiv, int64_t n, int K0,
                                            int t) {
@@ -141,6 +143,23 @@ __device__ __forceinline__ double w_of_row(const double* __restrict__ x, const d
   if (kd == 1) return x[t] * Dg[gt];
   if (kd == 2) return fma(x[t], Dg[gt], x[t + 1] * Dg[n + gt]);
   return fma(x[t - 1], Dg[n + gt - 1], x[t] * Dg[gt]);
+}
+
+// The same entry with every operand that any pivot kind needs loaded with
+// the kind (x[t + 1] lies in the row: t < m <= b + 1 < ldp) and all three
+// forms computed before the choice: no load waits behind the kind's, so a
+// thread's entries can be loaded together.
+__device__ __forceinline__ double w_of_row_all(const double* __restrict__ x,
+                                               const double* __restrict__ Dg,
+                                               const int8_t* __restrict__ ipiv, int64_t n, int K0,
+                                               int t) {
+  const int64_t gt = K0 + t;
+  const int tp = max(t - 1, 0);
+  const int kd = ipiv[gt];
+  const double x0 = x[t], xn = x[t + 1], xp = x[tp];
+  const double d0 = Dg[gt], dn = Dg[n + gt], dp = Dg[n + K0 + tp];
+  const double w1 = x0 * d0, w2 = fma(x0, d0, xn * dn), w3 = fma(xp, dp, x0 * d0);
+  return (kd == 1) ? w1 : ((kd == 2) ? w2 : w3);
 }
 
 // FP64 / FP32 packing for the K = 4 matrix-core steps: element e of the
@@ -201,15 +220,15 @@ __global__ void commit_pack_bf16x3_kernel(const int* __restrict__ srcat, int m, 
     const int g = (int)(frag / Qk);
     const int row = 16 * g + (lane & 15);
     rcp_bf8 lh, ll, wh, wl;
-    const double* x = (row < N2) ? Lp + (size_t)srcat[m + row] * ldp : nullptr;
+    // a clamped row and k, the bounds applied as a factor of 1 or 0: the
+    // eight entries' loads go out together instead of one branch each
+    const double* x = Lp + (size_t)srcat[m + min(row, N2 - 1)] * ldp;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int t = 32 * qk + 8 * (lane >> 4) + u;
-      double lv = 0.0, wv = 0.0;
-      if (x && t < m) {
-        lv = x[t];
-        wv = w_of_row(x, Dg, ipiv, n, K0, t);
-      }
+      const double keep = (row < N2 && t < m) ? 1.0 : 0.0;
+      const int tc = min(t, m - 1);
+      const double lv = x[tc] * keep, wv = w_of_row_all(x, Dg, ipiv, n, K0, tc) * keep;
       __bf16 h, lo;
       split_bf16(lv, h, lo);
       lh[u] = h;
@@ -247,9 +266,21 @@ __global__ void commit_rowexp_kernel(const int* __restrict__ srcat, int m, int N
     double ml = 0.0, mw = 0.0;
     if (row < N2) {
       const double* x = Lp + (size_t)srcat[m + row] * ldp;
-      for (int t = 0; t < m; ++t) {
-        ml = fmax(ml, fabs(x[t]));
-        mw = fmax(mw, fabs(w_of_row(x, Dg, ipiv, n, K0, t)));
+      // eight entries per round of loads (clamped k, bounds as a factor)
+      for (int t0 = 0; t0 < m; t0 += 8) {
+        double lv[8], wv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int tc = min(t0 + u, m - 1);
+          lv[u] = x[tc];
+          wv[u] = w_of_row_all(x, Dg, ipiv, n, K0, tc);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const double keep = (t0 + u < m) ? 1.0 : 0.0;
+          ml = fmax(ml, fabs(lv[u]) * keep);
+          mw = fmax(mw, fabs(wv[u]) * keep);
+        }
       }
     }
     int el = 0, ew = 0;
@@ -287,17 +318,16 @@ __global__ void commit_pack_bf16s_kernel(const int* __restrict__ srcat, int m, i
     const int qk = (int)(frag % Qk);
     const int g = (int)(frag / Qk);
     const int row = 16 * g + (lane & 15);
-    const double* x = (row < N2) ? Lp + (size_t)srcat[m + row] * ldp : nullptr;
+    // (clamped row and k with the bounds as a factor, as in the BF16x3 form)
+    const double* x = Lp + (size_t)srcat[m + min(row, N2 - 1)] * ldp;
     const int el = eL[row], ew = eW[row];
     rcp_bf8 ls[kSlices], ws[kSlices];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int t = 32 * qk + 8 * (lane >> 4) + u;
-      double lv = 0.0, wv = 0.0;
-      if (x && t < m) {
-        lv = x[t];
-        wv = w_of_row(x, Dg, ipiv, n, K0, t);
-      }
+      const double keep = (row < N2 && t < m) ? 1.0 : 0.0;
+      const int tc = min(t, m - 1);
+      const double lv = x[tc] * keep, wv = w_of_row_all(x, Dg, ipiv, n, K0, tc) * keep;
       __bf16 yl[kSlices], yw[kSlices];
       slice8(lv, el, yl);
       slice8(-wv, ew, yw);   // negated, as in the other packings
