@@ -269,12 +269,25 @@ __global__ void __launch_bounds__(kThreads) panel_q1_kernel(Q1Params P) {
       else if (s0 + r == ck && c != ck) posl[r] = pc;
     }
     const int src_k1 = (pc == k + 1) ? ck : ck1;   // source at k+1 after it
-    // the pivot's L row, sketch column, A column on my rows and diagonal
-    for (int t = tid; t < k; t += kThreads) Lp[t] = ld_agent(&a.Lpanel[(size_t)c * ldp + t]);
-    if (tid < l) Bp1[tid] = ld_agent(&Bqc[(int64_t)c * lpad + tid]);
-    for (int r = tid; r < nown; r += kThreads)
+    // the pivot's L row, sketch column, A column on my rows and diagonal:
+    // a thread's first four loads go out together (clamped addresses, the
+    // stores under their conditions afterwards), one round trip instead of
+    // one per condition; entries past the first kThreads follow in loops
+    {
+      const double vL = ld_agent(&a.Lpanel[(size_t)c * ldp + min(tid, max(k - 1, 0))]);
+      const double vB = ld_agent(&Bqc[(int64_t)c * lpad + min(tid, l - 1)]);
+      const int64_t ra = nown > 0 ? (int64_t)(s0 + min(tid, nown - 1)) : (int64_t)c;
+      const double vA = (double)sym_at(A, ld, ra, (int64_t)c);
+      const double vD = (double)A[(int64_t)c * (ld + 1)];
+      if (tid < k) Lp[tid] = vL;
+      if (tid < l) Bp1[tid] = vB;
+      if (tid < nown) acol[tid] = vA;
+      if (tid == 0) sh_Acc = vD;
+    }
+    for (int t = tid + kThreads; t < k; t += kThreads)
+      Lp[t] = ld_agent(&a.Lpanel[(size_t)c * ldp + t]);
+    for (int r = tid + kThreads; r < nown; r += kThreads)
       acol[r] = (double)sym_at(A, ld, (int64_t)(s0 + r), (int64_t)c);
-    if (tid == 0) sh_Acc = (double)A[(int64_t)c * (ld + 1)];
     __syncthreads();
     for (int t = tid; t < k; t += kThreads) Wp[t] = w_of(Lp, Dd, Ds, kind, t);
     __syncthreads();
