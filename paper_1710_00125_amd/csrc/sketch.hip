@@ -74,10 +74,26 @@ __global__ void __launch_bounds__(256) sketch_partial_kernel(int64_t n, const TA
       const int ii = all_upper ? e % kTK : e / kTJ;
       As[jj][ii] = (j0 + jj < n && i0 + ii < kend) ? ra[q] : (TA)0;
     }
-    for (int e = tid; e < kTK * ncols; e += 256) {
-      const int ii = e / ncols, cc = e - ii * ncols;
-      const int64_t i = i0 + ii;
-      Bs[ii][cc] = (i < kend) ? (TA)OmT[i * lpad + c0 + cc] : (TA)0;
+    // four entries per round of loads (clamped addresses, every load of a
+    // group issued before its first store): a quarter of the round trips of
+    // one load per entry, with few registers live beside the accumulators
+    const int nb = kTK * ncols;
+    for (int e0 = tid; e0 < nb; e0 += 4 * 256) {
+      double rb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = min(e0 + 256 * u, nb - 1);
+        const int ii = e / ncols, cc = e - ii * ncols;
+        rb[u] = OmT[min(i0 + ii, kend - 1) * lpad + c0 + cc];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + 256 * u;
+        if (e < nb) {
+          const int ii = e / ncols, cc = e - ii * ncols;
+          Bs[ii][cc] = (i0 + ii < kend) ? (TA)rb[u] : (TA)0;
+        }
+      }
     }
   };
 
