@@ -148,12 +148,21 @@ __global__ void copy_lower_kernel(int64_t n, const double* __restrict__ A, int64
                                   TA* __restrict__ Acur, Ctrl* ctrl) {
   // one workgroup per column, rows j..n-1; the largest magnitude read goes
   // to ctrl->max_abs_a (one atomic per wave)
+  // (four loads per thread in flight: rows past the end are clamped to row
+  // n - 1, a real entry of the lower triangle, so the maximum needs no
+  // mask; only rows inside the column are stored)
   double mx = 0.0;
   for (int64_t j = blockIdx.x; j < n; j += gridDim.x) {
-    for (int64_t i = j + threadIdx.x; i < n; i += blockDim.x) {
-      const double v = A[i + j * lda];
-      Acur[i + j * n] = (TA)v;
-      mx = fmax(mx, fabs(v));   // fmax drops a NaN; non-finite input is caught by the sketch check
+    for (int64_t i0 = j + threadIdx.x; i0 < n; i0 += 4 * blockDim.x) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = A[std::min<int64_t>(i0 + u * blockDim.x, n - 1) + j * lda];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t i = i0 + u * blockDim.x;
+        if (i < n) Acur[i + j * n] = (TA)v[u];
+        mx = fmax(mx, fabs(v[u]));   // fmax drops a NaN; non-finite input is caught by the sketch check
+      }
     }
   }
   mx = fmax(mx, xchg<1>(mx));

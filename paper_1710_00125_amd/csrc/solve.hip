@@ -37,14 +37,22 @@ __global__ void __launch_bounds__(256) finalize_L_kernel(int64_t n, const TL* __
   const int64_t i0 = I * kBlk, c0 = C * kBlk;
   const int tid = threadIdx.x;
   if (I >= C) {
-    // read: thread -> (row ii, column run cc), contiguous along c in Lwork
-    for (int e = tid; e < kBlk * kBlk; e += 256) {
-      const int ii = e / kBlk, cc = e % kBlk;
-      const int64_t i = i0 + ii, c = c0 + cc;
-      TL v = 0;
-      if (i < n && c < ncols && c < i) v = Lwork[P[i] * n + c];
-      tile[ii][cc] = v;
-    }
+    // read: thread -> (rows (tid / 64) + 4 k, column cc = tid % 64),
+    // contiguous along c in Lwork.  All 16 row indices, then all 16
+    // entries, are loaded from clamped addresses before any is used (two
+    // round trips, not two per entry); the write below uses an entry only
+    // strictly below the diagonal and left of ncols.
+    constexpr int kPer = kBlk * kBlk / 256;
+    const int cc = tid % kBlk;
+    const int64_t c = std::min<int64_t>(c0 + cc, n - 1);
+    int64_t pr[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) pr[k] = P[std::min<int64_t>(i0 + tid / kBlk + 4 * k, n - 1)];
+    TL v[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) v[k] = Lwork[pr[k] * n + c];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) tile[tid / kBlk + 4 * k][cc] = v[k];
     __syncthreads();
   }
   for (int e = tid; e < kBlk * kBlk; e += 256) {
@@ -54,6 +62,7 @@ __global__ void __launch_bounds__(256) finalize_L_kernel(int64_t n, const TL* __
     TL v;
     if (c > i) v = 0;
     else if (c == i) v = 1;
+    else if (c >= ncols) v = 0;   // past the factored columns
     else if (i == c + 1 && ipiv[c] == 2) v = 0;
     else v = tile[ii][cc];
     L[i + c * n] = v;
