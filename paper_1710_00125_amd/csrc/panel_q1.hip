@@ -439,10 +439,20 @@ __global__ void __launch_bounds__(kThreads) panel_q1_kernel(Q1Params P) {
         for (int i = 0; i < l; ++i) x[i] = xo[i];
       }
       if (kase >= 2) {
-        // r's L row, sketch column and A column on my rows
-        for (int t = tid; t < k; t += kThreads) Lr[t] = ld_agent(&a.Lpanel[(size_t)rsrc * ldp + t]);
-        if (tid < l) Bp2[tid] = ld_agent(&Bq1[(int64_t)rsrc * lpad + tid]);
-        for (int r = tid; r < nown; r += kThreads)
+        // r's L row, sketch column and A column on my rows (a thread's first
+        // three loads together from clamped addresses, as for the pivot)
+        {
+          const double vL = ld_agent(&a.Lpanel[(size_t)rsrc * ldp + min(tid, max(k - 1, 0))]);
+          const double vB = ld_agent(&Bq1[(int64_t)rsrc * lpad + min(tid, l - 1)]);
+          const int64_t ra = nown > 0 ? (int64_t)(s0 + min(tid, nown - 1)) : (int64_t)rsrc;
+          const double vA = (double)sym_at(A, ld, ra, (int64_t)rsrc);
+          if (tid < k) Lr[tid] = vL;
+          if (tid < l) Bp2[tid] = vB;
+          if (tid < nown) avec[tid] = vA;
+        }
+        for (int t = tid + kThreads; t < k; t += kThreads)
+          Lr[t] = ld_agent(&a.Lpanel[(size_t)rsrc * ldp + t]);
+        for (int r = tid + kThreads; r < nown; r += kThreads)
           avec[r] = (double)sym_at(A, ld, (int64_t)(s0 + r), (int64_t)rsrc);
         __syncthreads();
         for (int t = tid; t < k; t += kThreads) Wr[t] = w_of(Lr, Dd, Ds, kind, t);
