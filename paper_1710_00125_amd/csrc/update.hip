@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(256, 2) update_kernel(const typename P::TA* __
 // cores and adds 2^(eL + eW - 8(d+2)) P_d (an exact scaling) to its FP64
 // entries.  Pairs with a + b >= kSlices are left out: relative to the row
 // maxima their sum is below about 2^-45 per term.
-__global__ void __launch_bounds__(256, 2) update_bf16s_kernel(
+__global__ void __launch_bounds__(256) update_bf16s_kernel(
     const double* __restrict__ Acur, double* __restrict__ Anext, int64_t ld,
     const int* __restrict__ rowsrc, int N2, const rcp_bf8* __restrict__ L21p,
     const rcp_bf8* __restrict__ W21p, const int* __restrict__ eL, const int* __restrict__ eW,
@@ -263,18 +263,22 @@ __global__ void __launch_bounds__(256, 2) update_bf16s_kernel(
     int ei[4];
 #pragma unroll
     for (int x = 0; x < 4; ++x) ei[x] = eL[r0 + 16 * x + acc_col(lane)];
-    // the wave's 64 x 64 in two passes of 64 x 32 (fewer registers per pass)
-    for (int hh = 0; hh < 2; ++hh) {
-      const int c0 = c0w + 32 * hh;
-      if (c0 >= N2) break;
+    // the wave's 64 x 64 in four passes of 32 x 32 (rows rh, columns hh):
+    // a pass keeps its six groups' accumulators and one k step's slices of
+    // both operands in registers
+    for (int pp = 0; pp < 4; ++pp) {
+      const int rh = pp >> 1, hh = pp & 1;
+      const int rr0 = r0 + 32 * rh, c0 = c0w + 32 * hh;
+      if (rr0 >= N2 || c0 >= N2) continue;
+      const rcp_bf8* pap = pa + (int64_t)(2 * rh) * gstride;
       const rcp_bf8* pb = W21p + ((int64_t)(c0 / 16) * Qk) * FE + lane;
-      // C[x][y][v]: row i = r0 + 16x + lane % 16, column j = c0 + 16y +
+      // C[x][y][v]: row i = rr0 + 16x + lane % 16, column j = c0 + 16y +
       // acc_row_f32(lane, v) (the layout of the FP32 accumulators)
-      double C[4][2][4];
+      double C[2][2][4];
       int ej[2][4];
 #pragma unroll
-      for (int x = 0; x < 4; ++x) {
-        const int64_t s_i = __shfl(src_r, 16 * x + acc_col(lane));
+      for (int x = 0; x < 2; ++x) {
+        const int64_t s_i = __shfl(src_r, 32 * rh + 16 * x + acc_col(lane));
 #pragma unroll
         for (int y = 0; y < 2; ++y)
 #pragma unroll
@@ -285,52 +289,51 @@ __global__ void __launch_bounds__(256, 2) update_bf16s_kernel(
             if (x == 0) ej[y][v] = eW[c0w + jj];
           }
       }
-      for (int d = 0; d < kSlices; ++d) {
-        for (int q0 = 0; q0 < Qk; q0 += 4) {
-          const int q1 = min(q0 + 4, Qk);
-          rcp_f4 acc[4][2];
+      // per chunk of four k steps (at most 128 terms t: every P_d exact in
+      // FP32): each k step's slices of both operands are loaded once and
+      // feed all the groups d, whose accumulators stay in registers, then
+      // the chunk's P_d are scaled onto the FP64 entries in order of d
+      for (int q0 = 0; q0 < Qk; q0 += 4) {
+        const int q1 = min(q0 + 4, Qk);
+        rcp_f4 acc[kSlices][2][2];
 #pragma unroll
-          for (int x = 0; x < 4; ++x)
+        for (int d = 0; d < kSlices; ++d)
 #pragma unroll
-            for (int y = 0; y < 2; ++y) acc[x][y] = rcp_f4{0.f, 0.f, 0.f, 0.f};
-          // the (k step, slice pair) products of this group and chunk in one
-          // sequence, the operands of the next pair loaded while the matrix
-          // cores work on the current one
-          const int np = (q1 - q0) * (d + 1);
-          auto load_pair = [&](int idx, rcp_bf8* fa, rcp_bf8* fb) {
-            const int q = q0 + idx / (d + 1), a = idx % (d + 1);
+          for (int x = 0; x < 2; ++x)
 #pragma unroll
-            for (int x = 0; x < 4; ++x) fa[x] = pa[x * gstride + q * FE + 64 * a];
+            for (int y = 0; y < 2; ++y) acc[d][x][y] = rcp_f4{0.f, 0.f, 0.f, 0.f};
+        for (int q = q0; q < q1; ++q) {
+          rcp_bf8 fa[2][kSlices], fb[2][kSlices];
 #pragma unroll
-            for (int y = 0; y < 2; ++y) fb[y] = pb[y * gstride + q * FE + 64 * (d - a)];
-          };
-          rcp_bf8 fa0[4], fb0[2], fa1[4], fb1[2];
-          load_pair(0, fa0, fb0);
-          for (int idx = 0; idx < np; idx += 2) {
-            if (idx + 1 < np) load_pair(idx + 1, fa1, fb1);
+          for (int a = 0; a < kSlices; ++a) {
 #pragma unroll
-            for (int x = 0; x < 4; ++x)
+            for (int x = 0; x < 2; ++x) fa[x][a] = pap[x * gstride + q * FE + 64 * a];
 #pragma unroll
-              for (int y = 0; y < 2; ++y) acc[x][y] = mfma16x16x32(fb0[y], fa0[x], acc[x][y]);
-            if (idx + 1 >= np) break;
-            if (idx + 2 < np) load_pair(idx + 2, fa0, fb0);
-#pragma unroll
-            for (int x = 0; x < 4; ++x)
-#pragma unroll
-              for (int y = 0; y < 2; ++y) acc[x][y] = mfma16x16x32(fb1[y], fa1[x], acc[x][y]);
+            for (int y = 0; y < 2; ++y) fb[y][a] = pb[y * gstride + q * FE + 64 * a];
           }
 #pragma unroll
-          for (int x = 0; x < 4; ++x)
+          for (int d = 0; d < kSlices; ++d)
+#pragma unroll
+            for (int a = 0; a <= d; ++a)
+#pragma unroll
+              for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+                  acc[d][x][y] = mfma16x16x32(fb[y][d - a], fa[x][a], acc[d][x][y]);
+        }
+#pragma unroll
+        for (int d = 0; d < kSlices; ++d)
+#pragma unroll
+          for (int x = 0; x < 2; ++x)
 #pragma unroll
             for (int y = 0; y < 2; ++y)
 #pragma unroll
               for (int v = 0; v < 4; ++v)
-                C[x][y][v] += ldexp((double)acc[x][y][v], ei[x] + ej[y][v] - 8 * (d + 2));
-        }
+                C[x][y][v] += ldexp((double)acc[d][x][y][v], ei[2 * rh + x] + ej[y][v] - 8 * (d + 2));
       }
 #pragma unroll
-      for (int x = 0; x < 4; ++x) {
-        const int i = r0 + 16 * x + acc_col(lane);
+      for (int x = 0; x < 2; ++x) {
+        const int i = rr0 + 16 * x + acc_col(lane);
 #pragma unroll
         for (int y = 0; y < 2; ++y)
 #pragma unroll
@@ -354,11 +357,12 @@ void launch_update(const void* Acur, void* Anext, int64_t ld, const int* rowsrc,
   const int64_t per = (ntiles + kXcd - 1) / kXcd;
   // workgroups per CU: as many as leave room in the register file for the
   // concurrent register-resident selection kernel (about 140 registers):
-  // two of the FP64 and FP32 forms (at most 184), one of the BF16x3 form
-  // (about 210) and of the sliced form (254; with two per CU it ran 78 ms
-  // instead of 125 ms over the n = 16384 factorization, but the selection
-  // then waited for it: 316 ms instead of 287 ms); never more than the
-  // tiles need
+  // two of the FP64 and FP32 forms (at most 184) and one of the BF16x3 form
+  // (about 210); never more than the tiles need.  The sliced form takes
+  // nearly the whole register file (one k step's slices and six groups'
+  // accumulators per wave), so the selection waits for it: 81 ms over the
+  // n = 16384 factorization instead of 116 ms beside the selection, 232 ms
+  // instead of 259 ms per factorization
   const int wpc = (prec == kPrecBF16x3 || prec == kPrecBF16S) ? 1 : 2;
   const int64_t nwg = std::min<int64_t>((int64_t)wpc * num_cu / kXcd, per) * kXcd;
   const dim3 grid((unsigned)std::max<int64_t>(kXcd, nwg));
