@@ -130,10 +130,10 @@ int rcp_set_overlap(int32_t on);
  * redoes the step.  A speculating q = b panel does so at a step only while
  * seven of its last eight decisions took case (0)/(1).  mode = 1: every
  * panel whose workgroups own at most 64 rows speculates; 0: none does; -1
- * (the default): for q = b, a block's panel speculates unless more than one
- * decision in eight of the previous block took case (2) or (3); for q = 1,
- * a panel speculates when its grid has 256 workgroups.  Pivots, L and D
- * are bit-identical in every mode.  Returns 0, or -1 for another mode. */
+ * (the default): a block's panel (q = b or q = 1) speculates unless more
+ * than one decision in eight of the previous block took case (2) or (3).
+ * Pivots, L and D are bit-identical in every mode.  Returns 0, or -1 for
+ * another mode. */
 int rcp_set_speculation(int32_t mode);
 
 /* Algorithm 2 of the paper (Section 4.5) for later rcp_factor and

@@ -933,6 +933,9 @@ size_t panel_lds(int R, int ldp, int bb, int ntr, int ldt) {
 }  // namespace
 
 int panel_grid(int N, int ldp, int lpad, int num_cu, size_t* lds_bytes, int* ntr_out) {
+  // 16 rows per workgroup where the grid allows: more rows (64) made the
+  // exchange cheaper but the speculating step's row work dearer (n = 16384:
+  // 98.8 ms instead of 98.1 ms; n = 4096: 23.3 ms instead of 22.2 ms)
   int G = std::max(1, std::min(num_cu, (N + 15) / 16));
   auto lds_of = [&](int gg) {
     const int ntr = (lpad + gg - 1) / gg;

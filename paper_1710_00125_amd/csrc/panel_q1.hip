@@ -593,7 +593,10 @@ size_t q1_lds(int R, int ldp, int l) {
 }  // namespace
 
 int panel_q1_grid(int N, int ldp, int l, int num_cu, size_t* lds_bytes) {
-  int G = std::max(1, std::min(std::min(num_cu, kMaxG), (N + 15) / 16));
+  // 64 rows per workgroup where the grid allows: one pass of the row loops,
+  // as for fewer rows, and fewer workgroups in each exchange (n = 16384:
+  // 199 ms instead of 217 ms; n = 4096: 12-15 % faster on the stress types)
+  int G = std::max(1, std::min(std::min(num_cu, kMaxG), (N + 63) / 64));
   while (G < std::min(num_cu, kMaxG) && q1_lds((N + G - 1) / G, ldp, l) > 140 * 1024) ++G;
   *lds_bytes = q1_lds((N + G - 1) / G, ldp, l);
   return G;
@@ -609,11 +612,13 @@ void launch_panel_q1(const PanelArgs& a, Exchange ex, double* Bq, double* Bnext,
   p.G = G;
   p.R = (a.N + G - 1) / G;
   // the speculation saves the E1 exchange but adds its own barriers and
-  // copies; it pays where an exchange is dearest, on the largest grids.
-  // Measured per step: n = 16384, 13.3 us speculating on every grid against
-  // 14.7 us on none; n = 4096 (grids below 256 after the first block),
-  // 11.2 against 10.2 us.  With speculation from G = 256 on: 13.8 us and
-  // 10.2 us (from G = 160: 13.7 us and 10.8 us).
+  // copies, and a failed one redoes its step.  The factorization passes its
+  // per-block rule (0 after a block with more than one case (2)/(3)
+  // decision in eight, else 1).  Measured with 64 rows per workgroup:
+  // n = 16384, 225 ms speculating against 247 ms not; stress type 7
+  // (n = 4096), 41.1 against 45.9 ms; the 2x2-heavy type 6, 39.1 against
+  // 35.3 ms, where the rule keeps it off.  spec < 0 (no rule from the
+  // caller) speculates on full grids only.
   p.spec = spec < 0 ? (G >= kSpecMinG ? 1 : 0) : (spec != 0 ? 1 : 0);
   const void* k = prec_f64_storage(a.prec) ? (const void*)panel_q1_kernel<double>
                                      : (const void*)panel_q1_kernel<float>;

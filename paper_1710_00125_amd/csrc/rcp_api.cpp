@@ -528,7 +528,8 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
         // next block's sketch goes to Bn (`partial` is free scratch here)
         size_t lq = 0;
         const int Gq = panel_q1_grid(N, ldp, l, ncu_pan, &lq);
-        launch_panel_q1(pa, ex, partial, Bn, Gq, lq, g_spec, s);
+        launch_panel_q1(pa, ex, partial, Bn, Gq, lq, g_spec >= 0 ? g_spec : (spec_next ? 1 : 0),
+                        s);
       } else {
         launch_panel(pa, ex, Gp, ngr, lds, g_spec >= 0 ? g_spec : (spec_next ? 1 : 0), s);
       }
@@ -550,10 +551,11 @@ int factor_impl(int64_t n, const double* A, int64_t lda, int32_t b, int32_t p, u
       break;
     }
     {
-      // the rule for the next block's panel (speculation left to the
-      // measured rule): speculate unless more than one decision in eight of
-      // this block took SBKP case (2) or (3), where a failed speculation
-      // costs more than the kept ones save; the same results either way
+      // the rule for the next block's panel, q = b and q = 1 alike
+      // (speculation left to the measured rule): speculate unless more than
+      // one decision in eight of this block took SBKP case (2) or (3), where
+      // a failed speculation costs more than the kept ones save; the same
+      // results either way
       const long long c23 = g_ctrl_host->ncase[2] + g_ctrl_host->ncase[3];
       const long long tot = c23 + g_ctrl_host->ncase[0] + g_ctrl_host->ncase[1];
       const long long dc = c23 - seen_c23, dt = tot - seen_tot;

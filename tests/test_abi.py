@@ -140,8 +140,15 @@ def test_launch_shape_dispatch_without_gpu():
     sh = pkg.rcp_launch_shape(16384, 128, 16, 256)
     assert (sh["select_grid"], sh["select_cols"], sh["select_regs"]) == (256, 64, 1)
     assert (sh["panel_grid"], sh["panel_rows"], sh["supported"]) == (256, 64, 1)
-    # 33..64 columns per workgroup for every trailing order in (8192, 16384]
-    assert pkg.rcp_launch_shape(9000, 128, 16, 256)["select_cols"] == 36
+    # the selection takes 64 columns per workgroup wherever the grid allows:
+    # 9000 gives 141 workgroups of 64 (the last one 40), 2000 gives 32 of 63
+    # (the last 47)
+    sh = pkg.rcp_launch_shape(9000, 128, 16, 256)
+    assert (sh["select_grid"], sh["select_cols"], sh["select_regs"]) == (141, 64, 1)
+    sh = pkg.rcp_launch_shape(2000, 128, 16, 256)
+    assert (sh["select_grid"], sh["select_cols"]) == (32, 63)
+    # the q = b panel keeps 16 rows per workgroup below the full grid
+    assert (sh["panel_grid"], sh["panel_rows"]) == (125, 16)
     # one more column than the register slab holds, or a taller sketch: LDS
     assert pkg.rcp_launch_shape(16385, 128, 16, 256)["select_regs"] == 0
     assert pkg.rcp_launch_shape(1300, 128, 24, 256)["select_regs"] == 0

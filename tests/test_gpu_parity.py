@@ -211,14 +211,16 @@ def test_nonfinite_input(rcp, bad):
 
 # The persistent kernels' other shapes at sizes the oracle checks in
 # seconds.  The selection keeps up to 64 sketch columns per workgroup in
-# registers (l <= 144) and more, or taller sketches, in LDS; at full size
-# (n = 16384, b = 128, p = 16) every workgroup owns 33..64 columns and 33..64
-# panel rows in the first half of the factorization.  Bounding the grids
-# gives the same per-workgroup shapes at n = 2048.
+# registers (l <= 144) and more, or taller sketches, in LDS.  It takes 64
+# columns per workgroup where it can, so at every size the first block's
+# workgroups own 64 or, ragged, fewer (n = 2000: 63, the last one 47), and
+# later blocks run every width down to 33 as N shrinks.  A bounded grid gives
+# more than 64 columns (LDS slab); grid limits (32, 32) give the q = b panel
+# its full-size shape of 64 rows per workgroup at n = 2048.
 @pytest.mark.parametrize("n,b,p,limits,regs,cols", [
     (2048, 128, 16, (32, 32), 1, 64),    # register slab, 64 columns; panel rows 64
-    (2048, 128, 16, (48, 48), 1, 43),    # register slab, ragged 43 columns
-    (1300, 128, 24, (0, 0), 0, 32),      # l = 152 > 144: LDS slab
+    (2000, 128, 16, (0, 0), 1, 63),      # register slab, ragged 63 columns
+    (1300, 128, 24, (0, 0), 0, 62),      # l = 152 > 144: LDS slab
     (2048, 128, 16, (24, 0), 0, 86),     # more than 64 columns: LDS slab
 ])
 def test_factor_selection_shapes_match_oracle(rcp, n, b, p, limits, regs, cols):
