@@ -29,7 +29,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kColsPerPass = 64;   // a quad of lanes per column
 constexpr int kRecStride = RCP_REC_STRIDE;
-constexpr int kIdxFirstG = 256;   // grids at least this large poll index-first
+constexpr int kIdxFirstG = 128;   // grids at least this large poll index-first
 
 struct SelectParams {
   const double* B;
@@ -130,12 +130,12 @@ __global__ void __launch_bounds__(kThreads) select_kernel(SelectParams a) {
       unsigned long long w0 = 0, w1 = 0;
       unsigned int spins = 0;
       for (;;) {
-        // on the full grid, the index word alone until it is current (the
-        // writer stores it last), then the value word: one load per probe
-        // while waiting.  Halving the probes' traffic there made the
-        // selection 3 % faster beside the trailing update (and the update
-        // 10 % faster beside it); on smaller grids the extra round trip
-        // costs more than it saves.
+        // on grids of 128 workgroups or more, the index word alone until it
+        // is current (the writer stores it last), then the value word: one
+        // load per probe while waiting.  Halving the probes' traffic there
+        // made the selection 2-3 % faster beside the trailing update (and the
+        // update 7-10 % faster beside it); on smaller grids the extra round
+        // trip costs more than it saves.
         w1 = ld_agent(&rec[kRecStride * w + 1]);
         if (!IDX_FIRST) w0 = ld_agent(&rec[kRecStride * w]);
         if (rec_index_current(w1, j)) {
