@@ -933,10 +933,10 @@ size_t panel_lds(int R, int ldp, int bb, int ntr, int ldt) {
 }  // namespace
 
 int panel_grid(int N, int ldp, int lpad, int num_cu, size_t* lds_bytes, int* ntr_out) {
-  // 16 rows per workgroup where the grid allows: more rows (64) made the
-  // exchange cheaper but the speculating step's row work dearer (n = 16384:
-  // 98.8 ms instead of 98.1 ms; n = 4096: 23.3 ms instead of 22.2 ms)
-  int G = std::max(1, std::min(num_cu, (N + 15) / 16));
+  // 32 rows per workgroup where the grid allows: fewer workgroups make the
+  // exchange cheaper, more rows the speculating step's row work dearer
+  // (n = 16384: 97.6 ms with 32, 98.1 ms with 16, 98.8 ms with 64)
+  int G = std::max(1, std::min(num_cu, (N + 31) / 32));
   auto lds_of = [&](int gg) {
     const int ntr = (lpad + gg - 1) / gg;
     return panel_lds((N + gg - 1) / gg, ldp, ldp, ntr, ldp);

@@ -147,8 +147,8 @@ def test_launch_shape_dispatch_without_gpu():
     assert (sh["select_grid"], sh["select_cols"], sh["select_regs"]) == (141, 64, 1)
     sh = pkg.rcp_launch_shape(2000, 128, 16, 256)
     assert (sh["select_grid"], sh["select_cols"]) == (32, 63)
-    # the q = b panel keeps 16 rows per workgroup below the full grid
-    assert (sh["panel_grid"], sh["panel_rows"]) == (125, 16)
+    # the q = b panel takes 32 rows per workgroup below the full grid
+    assert (sh["panel_grid"], sh["panel_rows"]) == (63, 32)
     # one more column than the register slab holds, or a taller sketch: LDS
     assert pkg.rcp_launch_shape(16385, 128, 16, 256)["select_regs"] == 0
     assert pkg.rcp_launch_shape(1300, 128, 24, 256)["select_regs"] == 0
