@@ -313,7 +313,7 @@ __global__ void __launch_bounds__(kThreads) select_reg_kernel(SelectParams a) {
   if (tid < 16 * kRegCols) posl[tid] = (tid < nown) ? s0 + tid : -1;
 #pragma unroll
   for (int e = 0; e < kRegCols; ++e) {
-    const int c = 4 * cg + e;
+    const int c = kRegCols * cg + e;
     const double* col = a.B + (int64_t)min(s0 + c, a.N - 1) * a.lpad;   // clamped; unused if c >= nown
 #pragma unroll
     for (int u = 0; u < kRegRows; ++u) {
@@ -330,7 +330,7 @@ __global__ void __launch_bounds__(kThreads) select_reg_kernel(SelectParams a) {
 #pragma unroll
     for (int u = 0; u < kRegRows; ++u) sq = fma(d[u][e], d[u][e], sq);
     sq = sum16(sq);
-    if (rq == 0) nrm[4 * cg + e] = sq;
+    if (rq == 0) nrm[kRegCols * cg + e] = sq;
   }
   __syncthreads();
 
@@ -420,7 +420,7 @@ __global__ void __launch_bounds__(kThreads) select_reg_kernel(SelectParams a) {
     }
     bool live[kRegCols];
 #pragma unroll
-    for (int e = 0; e < kRegCols; ++e) live[e] = posl[4 * cg + e] > j;
+    for (int e = 0; e < kRegCols; ++e) live[e] = posl[kRegCols * cg + e] > j;
     // ---- Householder v = x + sign(x_j) ||x|| e_j, beta = 1 / (||x|| (||x|| +
     // |x_j|)), from the winner's published squared norm
     const double nx = sqrt(cand.val);
@@ -460,7 +460,7 @@ __global__ void __launch_bounds__(kThreads) select_reg_kernel(SelectParams a) {
     if (rq == 0) {
 #pragma unroll
       for (int e = 0; e < kRegCols; ++e)
-        if (live[e]) nrm[4 * cg + e] = sq[e];
+        if (live[e]) nrm[kRegCols * cg + e] = sq[e];
     }
     __syncthreads();
   }
