@@ -23,7 +23,11 @@ constexpr int kTC = 160;   // output columns (r) per workgroup (10 fragments)
 
 // TA = double: FP64 matrix cores; TA = float: FP32 matrix cores (Omega is
 // rounded to FP32 as it is staged).  Partial sums are written in FP64.
-template <typename TA>
+// NF: output fragments of 16 columns per workgroup, a compile-time count so
+// that the product loop has no branches (a runtime count put a branch and a
+// dependent LDS read before every product); columns of the last fragment
+// block beyond lpad are staged as zeros and not written.
+template <typename TA, int NF>
 __global__ void __launch_bounds__(256) sketch_partial_kernel(int64_t n, const TA* __restrict__ A,
                                                              int64_t ld,
                                                              const double* __restrict__ OmT,
@@ -39,12 +43,12 @@ __global__ void __launch_bounds__(256) sketch_partial_kernel(int64_t n, const TA
   const int64_t kbeg = (int64_t)blockIdx.y * kchunk;
   const int64_t kend = std::min<int64_t>(n, kbeg + kchunk);
   const int c0 = blockIdx.z * kTC;
-  const int ncols = std::min(kTC, lpad - c0);
-  const int nf = ncols / 16;
+  const int ncols = std::min(kTC, lpad - c0);   // a multiple of 16, <= 16 NF
+  constexpr int kW = 16 * NF;                     // staged columns
 
-  Acc acc[kTC / 16];
+  Acc acc[NF];
 #pragma unroll
-  for (int f = 0; f < kTC / 16; ++f) acc[f] = Acc{0, 0, 0, 0};
+  for (int f = 0; f < NF; ++f) acc[f] = Acc{0, 0, 0, 0};
 
   // A tile (rows j0.., columns i0..) of the symmetric matrix of one
   // contraction chunk: each thread's share is loaded into registers from
@@ -67,6 +71,11 @@ __global__ void __launch_bounds__(256) sketch_partial_kernel(int64_t n, const TA
   };
   auto store_chunk = [&](int64_t i0) {
     const bool all_upper = i0 > (j0 + kTJ - 1);
+    // an empty asm per value keeps the masking below (which needs the
+    // loaded value) after the barrier: hoisted into the product loop, it
+    // made the products wait for the next chunk's loads
+#pragma unroll
+    for (int q = 0; q < kQa; ++q) asm volatile("" : "+v"(ra[q]));
 #pragma unroll
     for (int q = 0; q < kQa; ++q) {
       const int e = tid + 256 * q;
@@ -77,21 +86,21 @@ __global__ void __launch_bounds__(256) sketch_partial_kernel(int64_t n, const TA
     // four entries per round of loads (clamped addresses, every load of a
     // group issued before its first store): a quarter of the round trips of
     // one load per entry, with few registers live beside the accumulators
-    const int nb = kTK * ncols;
+    constexpr int nb = kTK * kW;
     for (int e0 = tid; e0 < nb; e0 += 4 * 256) {
       double rb[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int e = min(e0 + 256 * u, nb - 1);
-        const int ii = e / ncols, cc = e - ii * ncols;
-        rb[u] = OmT[min(i0 + ii, kend - 1) * lpad + c0 + cc];
+        const int ii = e / kW, cc = e - ii * kW;
+        rb[u] = OmT[min(i0 + ii, kend - 1) * lpad + c0 + min(cc, ncols - 1)];
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int e = e0 + 256 * u;
         if (e < nb) {
-          const int ii = e / ncols, cc = e - ii * ncols;
-          Bs[ii][cc] = (i0 + ii < kend) ? (TA)rb[u] : (TA)0;
+          const int ii = e / kW, cc = e - ii * kW;
+          Bs[ii][cc] = (i0 + ii < kend && cc < ncols) ? (TA)rb[u] : (TA)0;
         }
       }
     }
@@ -103,27 +112,28 @@ __global__ void __launch_bounds__(256) sketch_partial_kernel(int64_t n, const TA
   }
   __syncthreads();
   for (int64_t i0 = kbeg; i0 < kend; i0 += kTK) {
-    const bool more = i0 + kTK < kend;
-    if (more) load_chunk(i0 + kTK);
+    // the next chunk's loads, issued before the products and waited for
+    // only when staged; unconditional (after the last chunk they read
+    // clamped addresses and stage zeros that nothing reads), since under a
+    // condition the compiler waited for them before the first product
+    load_chunk(i0 + kTK);
 #pragma unroll
     for (int kk = 0; kk < kTK / 4; ++kk) {
       const TA a = As[16 * w + frag_row(lane)][4 * kk + frag_k(lane)];
 #pragma unroll
-      for (int f = 0; f < kTC / 16; ++f) {
-        if (f < nf) {
-          const TA b = Bs[4 * kk + frag_k(lane)][16 * f + frag_col(lane)];
-          acc[f] = mfma16x16x4(a, b, acc[f]);
-        }
+      for (int f = 0; f < NF; ++f) {
+        const TA b = Bs[4 * kk + frag_k(lane)][16 * f + frag_col(lane)];
+        acc[f] = mfma16x16x4(a, b, acc[f]);
       }
     }
     __syncthreads();
-    if (more) store_chunk(i0 + kTK);
+    store_chunk(i0 + kTK);
     __syncthreads();
   }
   double* Pz = P + (int64_t)blockIdx.y * n * lpad;
 #pragma unroll
-  for (int f = 0; f < kTC / 16; ++f) {
-    if (f < nf) {
+  for (int f = 0; f < NF; ++f) {
+    if (16 * f < ncols) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t j = j0 + 16 * w + MfmaAcc<TA>::row(lane, v);
@@ -239,12 +249,27 @@ void launch_sketch(int64_t n, const void* Acur, int prec, int64_t ld, const doub
   kchunk = (kchunk + kTK - 1) / kTK * kTK;
   const int ks = (int)((n + kchunk - 1) / kchunk);
   dim3 grid((unsigned)((n + kTJ - 1) / kTJ), (unsigned)ks, (unsigned)((lpad + kTC - 1) / kTC));
-  if (prec_f64_storage(prec))
-    hipLaunchKernelGGL(sketch_partial_kernel<double>, grid, dim3(256), 0, s, n,
-                       (const double*)Acur, ld, OmT, lpad, ks == 1 ? B : partial, kchunk);
-  else
-    hipLaunchKernelGGL(sketch_partial_kernel<float>, grid, dim3(256), 0, s, n, (const float*)Acur,
-                       ld, OmT, lpad, ks == 1 ? B : partial, kchunk);
+  // fragments per workgroup: lpad / 16 when one workgroup column covers
+  // lpad, else kTC / 16 (the last block staging zeros beyond lpad)
+  const int nf = lpad <= kTC ? lpad / 16 : kTC / 16;
+  double* out = ks == 1 ? B : partial;
+  switch (nf) {
+#define RCP_SKETCH_CASE(NF)                                                                     \
+  case NF:                                                                                    \
+    if (prec_f64_storage(prec))                                                               \
+      hipLaunchKernelGGL((sketch_partial_kernel<double, NF>), grid, dim3(256), 0, s, n,        \
+                         (const double*)Acur, ld, OmT, lpad, out, kchunk);                    \
+    else                                                                                      \
+      hipLaunchKernelGGL((sketch_partial_kernel<float, NF>), grid, dim3(256), 0, s, n,         \
+                         (const float*)Acur, ld, OmT, lpad, out, kchunk);                     \
+    break;
+    RCP_SKETCH_CASE(1) RCP_SKETCH_CASE(2) RCP_SKETCH_CASE(3) RCP_SKETCH_CASE(4)
+    RCP_SKETCH_CASE(5) RCP_SKETCH_CASE(6) RCP_SKETCH_CASE(7) RCP_SKETCH_CASE(8)
+    RCP_SKETCH_CASE(9) RCP_SKETCH_CASE(10)
+#undef RCP_SKETCH_CASE
+    default:
+      break;
+  }
   if (ks > 1) {
     const int64_t total = n * lpad;
     hipLaunchKernelGGL(sketch_reduce_kernel, dim3(grid1d(total)), dim3(256), 0, s, total, ks,
