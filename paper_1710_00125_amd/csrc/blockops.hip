@@ -62,8 +62,10 @@ __global__ void __launch_bounds__(256) sketch_update_kernel(
   // The loads have clamped addresses and no condition (a branch around a
   // load would be waited for at its end, a round trip per element); the
   // masks are applied when the values are stored to LDS.  Fragments past
-  // nrf take no products and are not stored, and rows r >= l are stored as
-  // zeros whatever they hold (every output element is its own sum).
+  // nrf are multiplied like the others (from clamped rows) but not stored:
+  // a guard per product put a branch and a dependent LDS read before each
+  // one.  Rows r >= l are stored as zeros whatever they hold (every output
+  // element is its own sum).
   double lv[8], tv[kTP];
   auto fetch = [&](int k0) {
     const int kn = min(kSuK, m - k0);
@@ -109,10 +111,8 @@ __global__ void __launch_bounds__(256) sketch_update_kernel(
       const double av = Ls[(16 * w + frag_row(lane)) * (kSuK + 1) + t];
 #pragma unroll
       for (int f = 0; f < FR; ++f) {
-        if (f0 + f < nrf) {
-          const double bv = Ts[t * kLdt + 16 * f + frag_col(lane)];
-          acc[f] = mfma16x16x4(av, bv, acc[f]);
-        }
+        const double bv = Ts[t * kLdt + 16 * f + frag_col(lane)];
+        acc[f] = mfma16x16x4(av, bv, acc[f]);
       }
     }
   }
