@@ -103,6 +103,16 @@ def test_factor_householder_matches_oracle(rcp, n, b, p, seed):
     _factor_case(rcp, A, b, p, seed)
 
 
+@pytest.mark.parametrize("n,b,p,seed", [(700, 128, 40, 8), (450, 32, 140, 9)])
+def test_factor_wide_sketch_matches_oracle(rcp, n, b, p, seed):
+    """Sketches of more than 160 rows (l = 168 and 172): the sketch product
+    covers them in two column blocks of at most 160, the last one narrower
+    and staged with zero columns."""
+    _say(f"factor wide sketch n={n} b={b} p={p} seed={seed}")
+    A = gen.householder_spectrum(n, seed, cond=1e6, nrefl=64)
+    _factor_case(rcp, A, b, p, seed)
+
+
 @pytest.mark.parametrize("n,b,p,seed", [(128, 16, 4, 2), (400, 64, 10, 2), (1500, 64, 10, 3)])
 def test_factor_kkt_matches_oracle(rcp, n, b, p, seed):
     _say(f"factor kkt n={n} b={b} p={p} seed={seed}")
