@@ -157,18 +157,20 @@ template <typename TA>
 __global__ void copy_lower_kernel(int64_t n, const double* __restrict__ A, int64_t lda,
                                   TA* __restrict__ Acur, Ctrl* ctrl) {
   // one workgroup per column, rows j..n-1; the largest magnitude read goes
-  // to ctrl->max_abs_a (one atomic per wave)
-  // (four loads per thread in flight: rows past the end are clamped to row
+  // to ctrl->max_abs_a (one atomic per workgroup: one per wave, all on one
+  // word, queued behind each other)
+  // (eight loads per thread in flight: rows past the end are clamped to row
   // n - 1, a real entry of the lower triangle, so the maximum needs no
   // mask; only rows inside the column are stored)
+  __shared__ double wmx[4];
   double mx = 0.0;
   for (int64_t j = blockIdx.x; j < n; j += gridDim.x) {
-    for (int64_t i0 = j + threadIdx.x; i0 < n; i0 += 4 * blockDim.x) {
-      double v[4];
+    for (int64_t i0 = j + threadIdx.x; i0 < n; i0 += 8 * blockDim.x) {
+      double v[8];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) v[u] = A[std::min<int64_t>(i0 + u * blockDim.x, n - 1) + j * lda];
+      for (int u = 0; u < 8; ++u) v[u] = A[std::min<int64_t>(i0 + u * blockDim.x, n - 1) + j * lda];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < 8; ++u) {
         const int64_t i = i0 + u * blockDim.x;
         if (i < n) Acur[i + j * n] = (TA)v[u];
         mx = fmax(mx, fabs(v[u]));   // fmax drops a NaN; non-finite input is caught by the sketch check
@@ -181,8 +183,12 @@ __global__ void copy_lower_kernel(int64_t n, const double* __restrict__ A, int64
   mx = fmax(mx, xchg<8>(mx));
   mx = fmax(mx, xchg<16>(mx));
   mx = fmax(mx, xchg<32>(mx));
-  if ((threadIdx.x & 63) == 0 && mx > 0.0)
-    atomicMax(&ctrl->max_abs_a, (unsigned long long)__double_as_longlong(mx));
+  if ((threadIdx.x & 63) == 0) wmx[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    mx = fmax(fmax(wmx[0], wmx[1]), fmax(wmx[2], wmx[3]));
+    if (mx > 0.0) atomicMax(&ctrl->max_abs_a, (unsigned long long)__double_as_longlong(mx));
+  }
 }
 
 __global__ void check_finite_kernel(int64_t n, const double* __restrict__ B, int lpad, int l,
