@@ -83,20 +83,22 @@ __global__ void __launch_bounds__(256) sketch_partial_kernel(int64_t n, const TA
       const int ii = all_upper ? e % kTK : e / kTJ;
       As[jj][ii] = (j0 + jj < n && i0 + ii < kend) ? ra[q] : (TA)0;
     }
-    // four entries per round of loads (clamped addresses, every load of a
-    // group issued before its first store): a quarter of the round trips of
-    // one load per entry, with few registers live beside the accumulators
+    // twelve entries per round of loads (clamped addresses, every load of
+    // a group issued before its first store): two round trips per chunk at
+    // 9 or 10 fragments, within the registers of two workgroups per CU
+    // (groups of 18 or 20 are not)
     constexpr int nb = kTK * kW;
-    for (int e0 = tid; e0 < nb; e0 += 4 * 256) {
-      double rb[4];
+    constexpr int kG = 12;
+    for (int e0 = tid; e0 < nb; e0 += kG * 256) {
+      double rb[kG];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kG; ++u) {
         const int e = min(e0 + 256 * u, nb - 1);
         const int ii = e / kW, cc = e - ii * kW;
         rb[u] = OmT[min(i0 + ii, kend - 1) * lpad + c0 + min(cc, ncols - 1)];
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kG; ++u) {
         const int e = e0 + 256 * u;
         if (e < nb) {
           const int ii = e / kW, cc = e - ii * kW;
