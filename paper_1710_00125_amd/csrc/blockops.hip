@@ -166,15 +166,16 @@ __device__ __forceinline__ double w_of_row_all(const double* __restrict__ x,
 // packed arrays is ((g * Qk + qk) * 64 + lane), holding row 16 g + lane % 16
 // and k = 4 qk + lane / 16.  W21 is stored negated.
 template <typename TF>
-__global__ void commit_pack_kernel(const int* __restrict__ srcat, int m, int N, int K0, int64_t n,
-                                   const double* __restrict__ Lp, int ldp,
-                                   const double* __restrict__ Dg, const int8_t* __restrict__ ipiv,
-                                   TF* __restrict__ L21p, TF* __restrict__ W21p, int Qk,
-                                   int rows_pad, int* __restrict__ rowsrc) {
+__device__ __forceinline__ void commit_pack_body(int64_t bid, int64_t nblk,
+                                                 const int* __restrict__ srcat, int m, int N,
+                                                 int K0, int64_t n, const double* __restrict__ Lp,
+                                                 int ldp, const double* __restrict__ Dg,
+                                                 const int8_t* __restrict__ ipiv,
+                                                 TF* __restrict__ L21p, TF* __restrict__ W21p,
+                                                 int Qk, int rows_pad, int* __restrict__ rowsrc) {
   const int64_t total = (int64_t)rows_pad * Qk * 4;
   const int N2 = N - m;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t e = bid * blockDim.x + threadIdx.x; e < total; e += nblk * blockDim.x) {
     const int lane = (int)(e & 63);
     const int64_t gq = e >> 6;
     const int qk = (int)(gq % Qk);
@@ -190,8 +191,7 @@ __global__ void commit_pack_kernel(const int* __restrict__ srcat, int m, int N, 
     L21p[e] = (TF)lv;
     W21p[e] = (TF)(-wv);   // negated: the update accumulates onto the old entries
   }
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N2;
-       i += (int64_t)gridDim.x * blockDim.x)
+  for (int64_t i = bid * blockDim.x + threadIdx.x; i < N2; i += nblk * blockDim.x)
     rowsrc[i] = srcat[m + i];
 }
 
@@ -349,13 +349,15 @@ __global__ void commit_pack_bf16s_kernel(const int* __restrict__ srcat, int m, i
 }
 
 template <typename TL>
-__global__ void commit_rows_kernel(const int* __restrict__ srcat, int m, int N, int K0, int64_t n,
-                                   const double* __restrict__ Lp, int ldp,
-                                   const int64_t* __restrict__ Pcur, int64_t* __restrict__ Pnext,
-                                   TL* __restrict__ Lwork) {
+__device__ __forceinline__ void commit_rows_body(int64_t bid, int64_t nblk,
+                                                 const int* __restrict__ srcat, int m, int N,
+                                                 int K0, int64_t n, const double* __restrict__ Lp,
+                                                 int ldp, const int64_t* __restrict__ Pcur,
+                                                 int64_t* __restrict__ Pnext,
+                                                 TL* __restrict__ Lwork) {
   // one workgroup per block position i: the block's L entries of the source
   // that ends at i go to row P(original index) of Lwork
-  for (int i = blockIdx.x; i < N; i += gridDim.x) {
+  for (int64_t i = bid; i < N; i += nblk) {
     const int s = srcat[i];
     const int64_t orig = Pcur[K0 + s];
     const double* x = Lp + (size_t)s * ldp;
@@ -363,9 +365,35 @@ __global__ void commit_rows_kernel(const int* __restrict__ srcat, int m, int N, 
     for (int t = threadIdx.x; t < m; t += blockDim.x) dst[t] = (TL)x[t];
     if (threadIdx.x == 0) Pnext[K0 + i] = orig;
   }
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < K0;
-       j += (int64_t)gridDim.x * blockDim.x)
+  for (int64_t j = bid * blockDim.x + threadIdx.x; j < K0; j += nblk * blockDim.x)
     Pnext[j] = Pcur[j];
+}
+
+template <typename TL>
+__global__ void commit_rows_kernel(const int* __restrict__ srcat, int m, int N, int K0, int64_t n,
+                                   const double* __restrict__ Lp, int ldp,
+                                   const int64_t* __restrict__ Pcur, int64_t* __restrict__ Pnext,
+                                   TL* __restrict__ Lwork) {
+  commit_rows_body(blockIdx.x, gridDim.x, srcat, m, N, K0, n, Lp, ldp, Pcur, Pnext, Lwork);
+}
+
+// The FP64 / FP32 commit in one launch: blocks [0, npack) pack the update's
+// operands, the rest move the block's L rows and the permutation.  The two
+// parts read the same inputs and write disjoint arrays.
+template <typename T>
+__global__ void commit_fused_kernel(int64_t npack, const int* __restrict__ srcat, int m, int N,
+                                    int K0, int64_t n, const double* __restrict__ Lp, int ldp,
+                                    const double* __restrict__ Dg,
+                                    const int8_t* __restrict__ ipiv, T* __restrict__ L21p,
+                                    T* __restrict__ W21p, int Qk, int rows_pad,
+                                    int* __restrict__ rowsrc, const int64_t* __restrict__ Pcur,
+                                    int64_t* __restrict__ Pnext, T* __restrict__ Lwork) {
+  if ((int64_t)blockIdx.x < npack)
+    commit_pack_body(blockIdx.x, npack, srcat, m, N, K0, n, Lp, ldp, Dg, ipiv, L21p, W21p, Qk,
+                     rows_pad, rowsrc);
+  else
+    commit_rows_body((int64_t)blockIdx.x - npack, (int64_t)gridDim.x - npack, srcat, m, N, K0,
+                     n, Lp, ldp, Pcur, Pnext, Lwork);
 }
 
 }  // namespace
@@ -413,20 +441,26 @@ void launch_commit(const int* srcat, int m, int N, int K0, int64_t n, const doub
                    int ldp, const double* Dg, const int8_t* ipiv, const int64_t* Pcur,
                    int64_t* Pnext, void* Lwork, int prec, void* L21p, void* W21p, int Qk,
                    int rows_pad, int* rowsrc, hipStream_t s) {
-  if (N - m > 0) {
-    const int64_t total = (prec == kPrecBF16x3 || prec == kPrecBF16S)
-                              ? (int64_t)(rows_pad / 16) * Qk * 64
-                              : (int64_t)rows_pad * Qk * 4;
-    const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 8192);
+  const unsigned rblocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(N, 8192));
+  if (prec == kPrecF64 || prec == kPrecF32) {
+    // packing and rows in one launch (no packing after the last block)
+    const int64_t total = N - m > 0 ? (int64_t)rows_pad * Qk * 4 : 0;
+    const int64_t npack = std::min<int64_t>((total + 255) / 256, 8192);
+    const dim3 grid((unsigned)(npack + rblocks));
     if (prec == kPrecF64)
-      hipLaunchKernelGGL(commit_pack_kernel<double>, dim3(blocks), dim3(256), 0, s, srcat, m, N,
+      hipLaunchKernelGGL(commit_fused_kernel<double>, grid, dim3(256), 0, s, npack, srcat, m, N,
                          K0, n, Lpanel, ldp, Dg, ipiv, (double*)L21p, (double*)W21p, Qk,
-                         rows_pad, rowsrc);
-    else if (prec == kPrecF32)
-      hipLaunchKernelGGL(commit_pack_kernel<float>, dim3(blocks), dim3(256), 0, s, srcat, m, N,
+                         rows_pad, rowsrc, Pcur, Pnext, (double*)Lwork);
+    else
+      hipLaunchKernelGGL(commit_fused_kernel<float>, grid, dim3(256), 0, s, npack, srcat, m, N,
                          K0, n, Lpanel, ldp, Dg, ipiv, (float*)L21p, (float*)W21p, Qk, rows_pad,
-                         rowsrc);
-    else if (prec == kPrecBF16x3)
+                         rowsrc, Pcur, Pnext, (float*)Lwork);
+    return;
+  }
+  if (N - m > 0) {
+    const int64_t total = (int64_t)(rows_pad / 16) * Qk * 64;
+    const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 8192);
+    if (prec == kPrecBF16x3)
       hipLaunchKernelGGL(commit_pack_bf16x3_kernel, dim3(blocks), dim3(256), 0, s, srcat, m, N,
                          K0, n, Lpanel, ldp, Dg, ipiv, (rcp_bf8*)L21p, (rcp_bf8*)W21p, Qk,
                          rows_pad, rowsrc);
@@ -440,12 +474,11 @@ void launch_commit(const int* srcat, int m, int N, int K0, int64_t n, const doub
                          rows_pad, eL, eW, rowsrc);
     }
   }
-  const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(N, 8192));
   if (prec_f64_storage(prec))
-    hipLaunchKernelGGL(commit_rows_kernel<double>, dim3(blocks), dim3(128), 0, s, srcat, m, N, K0,
+    hipLaunchKernelGGL(commit_rows_kernel<double>, dim3(rblocks), dim3(128), 0, s, srcat, m, N, K0,
                        n, Lpanel, ldp, Pcur, Pnext, (double*)Lwork);
   else
-    hipLaunchKernelGGL(commit_rows_kernel<float>, dim3(blocks), dim3(128), 0, s, srcat, m, N, K0,
+    hipLaunchKernelGGL(commit_rows_kernel<float>, dim3(rblocks), dim3(128), 0, s, srcat, m, N, K0,
                        n, Lpanel, ldp, Pcur, Pnext, (float*)Lwork);
 }
 
